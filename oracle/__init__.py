@@ -1,0 +1,30 @@
+"""CPU oracle for the partial-trace typicality estimator of the equilibrium
+reduced density matrix (Chen & Cheng, arXiv:2204.08147).
+
+THIS PACKAGE IS TEST INFRASTRUCTURE.  It is a plain, slow, FP64 NumPy
+implementation written from the paper, used only by ``tests/``, by
+``__graft_entry__.smoke()`` and by the ``cpu_baseline`` leg of ``bench.py``.
+The product path (the HIP library under ``paper_2204_08147_amd``) never imports,
+calls or links anything here, and nothing here imports the product path: the
+two share no code.  Both take their inputs from ``workloads`` (seeded draws
+only) and generate bath vectors from the same published counter-based rule,
+implemented separately on each side.
+
+Modules
+-------
+rng          SplitMix64 and the Rademacher bath-vector rule.
+spin         Pauli/Kronecker Hamiltonian (dense) and an independent
+             matrix-free apply (sparse scatter form).
+exact        O1: dense exact rho*, H*, ln Z*, S by diagonalisation;
+             O2: exact typicality with the same bath vectors (no Krylov error).
+lanczos      O3: the hot path's algorithm, step by step, in FP64: per-column
+             Lanczos, Lanczos function approximation of exp(-beta H/2),
+             Gram, n_v average, bath Lanczos, finalize.
+block        O4: the paper's block Lanczos (Algorithm 1) with block Gauss
+             quadrature.
+closed_form  O5: the solvable XX chain (paper appendix "Solution to the spin
+             chain", with its two garbled formulas read as described there)
+             and a two-spin closed form derived directly.
+variance     O6: exact per-entry variance of the Rademacher partial-trace
+             estimator.
+"""

@@ -1,0 +1,120 @@
+"""O3: the hot path's algorithm, step by step, in FP64 on the CPU.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+For each start column x_c = |m> (x) |v_j> (c = j*d_s + m) this runs the
+Lanczos recurrence of Algorithm 1 with block size one (the scalar case the
+paper mentions for an empty system, Section "Algorithm"), without
+reorthogonalisation (Section "Finite precision arithmetic"):
+
+    q_1 = x / |x|,  q_0 = 0,  b_0 = 0
+    for j = 1..k:  w = H q_j - b_{j-1} q_{j-1};  a_j = q_j . w;  w -= a_j q_j
+                   if j < k:  b_j = |w|;  q_{j+1} = w / b_j
+
+and stops early (k_c = j) when b_j <= tau * max(|a_1..a_j|, b_1..b_{j-1}).
+T = tridiag(b, a, b) of order k_c.  A Lanczos function approximation of
+exp(-beta (H - E0)/2) x is  psi = |x| Q exp(-beta (T - E0)/2) e_1, where E0 is
+the smallest Ritz value over all columns of the solve (the overflow shift of
+Section "An algorithm for the mean force Hamiltonian").  Then
+
+    M(beta) = (1/n_v) sum_j Psi_j^T Psi_j,   Psi_j = [psi_{j*d_s+m}]_m,
+
+which equals V_j^T exp(-beta (H-E0)) V_j up to the Krylov error: the per-column
+form of the block quadrature (eqn:fT, eqn:trB_est), exact when f = g^2 with
+deg g <= k-1.  The bath scalar m_b(beta) is the Gauss quadrature
+e_1^T exp(-beta (T_b - E0b)) e_1 of a Lanczos run on H_b from the same v_j
+(eqn:H_est), averaged over j.  ``exact.finalize`` produces rho*, H*, ln Z*, S.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .exact import finalize, start_columns
+from .rng import bath_vectors
+from .spin import sparse_bath_hamiltonian, sparse_hamiltonian
+
+TAU_FP64 = 1e-12
+
+
+def lanczos(apply, x: np.ndarray, k: int, tau: float = TAU_FP64, keep_q: bool = True):
+    """Plain Lanczos on one vector.  Returns (alpha[k_c], beta[k_c-1], Q or
+    None, |x|)."""
+    nx = float(np.sqrt(np.dot(x, x)))
+    q = x / nx
+    q_prev = np.zeros_like(q)
+    b_prev = 0.0
+    alphas, betas, qs = [], [], [q] if keep_q else None
+    scale = 0.0
+    for j in range(1, k + 1):
+        w = apply(q) - b_prev * q_prev
+        a = float(np.dot(q, w))
+        w = w - a * q
+        alphas.append(a)
+        scale = max(scale, abs(a))
+        if j == k:
+            break
+        b = float(np.sqrt(np.dot(w, w)))
+        if b <= tau * scale:
+            break
+        scale = max(scale, b)
+        betas.append(b)
+        q_prev, q, b_prev = q, w / b, b
+        if keep_q:
+            qs.append(q)
+    qmat = np.stack(qs, axis=1) if keep_q else None
+    return np.array(alphas), np.array(betas), qmat, nx
+
+
+def tridiag(alpha: np.ndarray, beta: np.ndarray) -> np.ndarray:
+    return np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+
+
+def fa_weights(alpha, beta, beta_t: float, e0: float) -> np.ndarray:
+    """y = exp(-beta_t (T - e0)/2) e_1 through the eigendecomposition of T."""
+    th, s = np.linalg.eigh(tridiag(alpha, beta))
+    return s @ (np.exp(-0.5 * beta_t * (th - e0)) * s[0, :])
+
+
+def quad_weight(alpha, beta, beta_t: float, e0: float) -> float:
+    """Gauss quadrature e_1^T exp(-beta_t (T - e0)) e_1."""
+    th, s = np.linalg.eigh(tridiag(alpha, beta))
+    return float((s[0, :] ** 2 * np.exp(-beta_t * (th - e0))).sum())
+
+
+def min_ritz(alpha, beta) -> float:
+    return float(np.linalg.eigvalsh(tridiag(alpha, beta))[0])
+
+
+def solve(inst, betas=None, tau: float = TAU_FP64, keep=False) -> dict:
+    """Run the whole path for one instance.  Returns per-beta outputs plus the
+    intermediate Lanczos coefficients (for coefficient-level comparisons)."""
+    betas = np.asarray(inst.betas if betas is None else betas, float)
+    op = sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    opb = sparse_bath_hamiltonian(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+    d_s, d_b, n_v = inst.d_s, inst.d_b, inst.n_v
+    x0 = start_columns(inst)
+    cols = []
+    for c in range(x0.shape[1]):
+        a, b, q, nx = lanczos(op.apply, x0[:, c], inst.k, tau)
+        cols.append((a, b, q, nx))
+    e0 = min(min_ritz(a, b) for a, b, _, _ in cols)
+    v = bath_vectors(inst.seed, n_v, inst.n_b)
+    bath = [lanczos(opb.apply, v[:, j], inst.k, tau, keep_q=False) for j in range(n_v)]
+    e0b = min(min_ritz(a, b) for a, b, _, _ in bath)
+    results = []
+    for bt in betas:
+        m = np.zeros((d_s, d_s))
+        for j in range(n_v):
+            psi = np.stack([cols[j * d_s + mm][2] @ (cols[j * d_s + mm][3] *
+                            fa_weights(cols[j * d_s + mm][0], cols[j * d_s + mm][1], bt, e0))
+                            for mm in range(d_s)], axis=1)
+            m += psi.T @ psi
+        m /= n_v
+        m_b = sum(nx * nx * quad_weight(a, b, bt, e0b) for a, b, _, nx in bath) / n_v
+        results.append(finalize(m, m_b, e0, e0b, bt, d_b) | {"m": m, "m_b": m_b})
+    out = {"results": results, "e0": e0, "e0b": e0b,
+           "alpha": [c[0] for c in cols], "beta": [c[1] for c in cols],
+           "bath_alpha": [b[0] for b in bath], "bath_beta": [b[1] for b in bath]}
+    if keep:
+        out["q"] = [c[2] for c in cols]
+    return out

@@ -1,0 +1,121 @@
+"""Pins of O3 (per-column Lanczos, function approximation, Gram, bath
+quadrature, finalize) and O4 (block Lanczos, Algorithm 1)."""
+import numpy as np
+import pytest
+
+from oracle import block, exact, lanczos, spin
+from oracle.rng import bath_vectors
+from workloads import Instance, cfg_small_chain, long_range_xx_zz, random_dense_terms
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _scaled_op(inst):
+    H = spin.dense_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    s = np.abs(np.linalg.eigvalsh(H)).max()
+    return H / s
+
+
+def test_quadrature_moments_exact():
+    # e_1^T T^p e_1 = x^T H^p x / |x|^2 for p <= 2k-1 (Gauss quadrature)
+    inst = random_dense_terms(1, 6, 31)
+    H = _scaled_op(inst)
+    x = np.random.default_rng(1).normal(size=inst.dim)
+    k = 8
+    a, b, q, nx = lanczos.lanczos(lambda v: H @ v, x, k)
+    T = lanczos.tridiag(a, b)
+    xn = x / nx
+    hp = xn.copy()
+    tp = np.eye(k)[:, 0]
+    for p in range(0, 2 * k):
+        assert abs(xn @ hp - np.eye(k)[:, 0] @ tp) < 1e-12, p
+        hp = H @ hp
+        tp = T @ tp
+    # degree 2k is no longer exact
+    assert abs(xn @ hp - np.eye(k)[:, 0] @ tp) > 1e-10
+
+
+def test_function_approximation_exact_for_low_degree():
+    # |x| Q T^p e_1 = H^p x for p <= k-1
+    inst = random_dense_terms(2, 4, 32)
+    H = _scaled_op(inst)
+    x = np.random.default_rng(2).normal(size=inst.dim)
+    k = 7
+    a, b, q, nx = lanczos.lanczos(lambda v: H @ v, x, k)
+    T = lanczos.tridiag(a, b)
+    hp, tp = x.copy(), np.eye(k)[:, 0]
+    for p in range(k):
+        assert np.abs(nx * q @ tp - hp).max() < 1e-12 * max(1, np.abs(hp).max()), p
+        hp, tp = H @ hp, T @ tp
+    assert np.abs(nx * q @ tp - hp).max() > 1e-10
+
+
+@pytest.mark.parametrize("make", [cfg_small_chain,
+                                  lambda: random_dense_terms(2, 5, 33, betas=(0.3, 1.0, 2.5), k=40),
+                                  lambda: long_range_xx_zz(2, 6, 1.0, 34, n_v=3, k=40)])
+def test_lanczos_path_equals_exact_typicality(make):
+    inst = make()
+    o2 = exact.exact_typicality(inst)
+    o3 = lanczos.solve(inst)
+    o4 = block.solve(inst)
+    for r2, r3, r4 in zip(o2, o3["results"], o4["results"]):
+        assert _rel(r3["rho"], r2["rho"]) < 1e-12
+        assert _rel(r3["h_star"], r2["h_star"]) < 1e-11
+        assert abs(r3["log_z"] - r2["log_z"]) < 1e-11
+        assert abs(r3["entropy"] - r2["entropy"]) < 1e-12
+        assert _rel(r4["rho"], r2["rho"]) < 1e-12
+        assert _rel(r4["h_star"], r2["h_star"]) < 1e-11
+
+
+def test_block_converges_faster_than_per_column():
+    # the block quadrature is exact to degree 2k-1, the per-column Gram only for
+    # f = g^2 with deg g <= k-1 (Section "Block Gauss quadrature")
+    inst = cfg_small_chain()
+    o2 = exact.exact_typicality(inst)[0]
+    inst.k = 12
+    e3 = _rel(lanczos.solve(inst)["results"][0]["rho"], o2["rho"])
+    e4 = _rel(block.solve(inst)["results"][0]["rho"], o2["rho"])
+    assert e4 < e3
+
+
+def test_breakdown_small_space():
+    # dim 8 < k: the recurrence stops on an invariant subspace and is exact
+    inst = random_dense_terms(1, 2, 35, k=20, n_v=2)
+    o3 = lanczos.solve(inst)
+    assert all(len(a) <= 8 for a in o3["alpha"])
+    o2 = exact.exact_typicality(inst)[0]
+    assert _rel(o3["results"][0]["rho"], o2["rho"]) < 1e-10
+
+
+def test_no_coupling_exact_with_one_sample():
+    # H_sb = 0: (I (x) <v|) exp(-bH) (I (x) |v>) = exp(-b H_s) <v|exp(-b H_b)|v>,
+    # so rho* = rho_s and H* = H_s for any single v
+    base = random_dense_terms(2, 5, 36, k=60, n_v=1)
+    cps = [c for c in base.couplings if (c[0] < 2) == (c[1] < 2)]
+    inst = Instance(2, 5, cps, base.hx, base.hz, np.array([0.8]), 1, 60, 5)
+    hs, _, _ = spin.split_dense(2, 5, cps, base.hx, base.hz)
+    e, u = np.linalg.eigh(hs)
+    rho_s = (u * np.exp(-0.8 * e)) @ u.T
+    rho_s /= np.trace(rho_s)
+    r = lanczos.solve(inst)["results"][0]
+    assert np.abs(r["rho"] - rho_s).max() < 1e-13
+    assert np.abs(r["h_star"] - hs).max() < 1e-12
+
+
+def test_high_temperature_note():
+    # beta -> 0: H*_est = H_s + avg_j (I (x) <v_j|) H_sb (I (x) |v_j>) + O(beta)
+    inst = random_dense_terms(2, 4, 37, k=20, n_v=2)
+    hs, _, hsb = spin.split_dense(2, 4, inst.couplings, inst.hx, inst.hz)
+    v = bath_vectors(inst.seed, inst.n_v, inst.n_b)
+    corr = np.zeros((4, 4))
+    for j in range(inst.n_v):
+        vj = np.kron(np.eye(4), v[:, j:j + 1])
+        corr += vj.T @ hsb @ vj
+    corr /= inst.n_v
+    beta = 1e-5
+    r = lanczos.solve(inst, betas=[beta])["results"][0]
+    assert np.abs(r["h_star"] - (hs + corr)).max() < 1e-3
+    assert np.abs(r["h_star"] - hs).max() > 10 * np.abs(r["h_star"] - (hs + corr)).max()
+    assert np.abs(r["rho"] - np.eye(4) / 4).max() < 1e-3
