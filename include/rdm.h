@@ -1,0 +1,245 @@
+/*
+ * rdm.h -- C ABI of the MI355X (gfx950) library for the equilibrium reduced
+ * density matrix of a spin system strongly coupled to a spin bath, by the
+ * partial-trace typicality estimator of Chen & Cheng, "Numerical computation
+ * of the equilibrium-reduced density matrix for strongly coupled open quantum
+ * systems" (arXiv:2204.08147).
+ *
+ * All functions have C linkage; no C++ exception crosses this boundary.  Every
+ * function returning rdm_status leaves a human-readable message retrievable
+ * with rdm_last_error() when it fails.  Unless stated otherwise, pointers
+ * named host_* or documented as "host" point to host memory owned by the
+ * caller, and pointers documented as "device" point to device memory on the
+ * current HIP device, also owned by the caller.
+ *
+ * Physics conventions (the paper's eqn:Ht and the site operators of Section
+ * "Spin systems"):
+ *   - N = n_s + n_b spin-1/2 sites, 0-based; site 0 is the leftmost Kronecker
+ *     factor, the system is sites 0..n_s-1.  Site i is bit (N-1-i) of a basis
+ *     index, so the system index of basis state idx is idx >> n_b, and bit
+ *     value 0 means sigma^z = +1.
+ *   - H_t = sum_pairs (jx sx_i sx_j + jy sy_i sy_j + jz sz_i sz_j)
+ *           + sum_i (hx_i sx_i + hz_i sz_i)              (Pauli matrices)
+ *     Each pair is given once (unordered); a pair listed several times has its
+ *     coefficients summed.  The paper's field "(h/2) sigma^z" is hz_i = h/2.
+ *   - H_s / H_b / H_sb follow the paper's split: terms with all sites in the
+ *     system / all in the bath / mixed.
+ *
+ * Estimator (Section "Algorithm"): n_v real Rademacher bath vectors v_j of
+ * unit norm are drawn from the seed by the SplitMix64 rule
+ *     key_j = sm64(seed ^ sm64(j)),  word = sm64(key_j ^ (b >> 6)),
+ *     v_j[b] = (1 - 2*((word >> (b & 63)) & 1)) * sqrt(2^-n_b),
+ * where sm64(x) is one SplitMix64 output from state x (golden-gamma add, then
+ * the 30/27/31 xor-shift-multiply finaliser).  Every start column
+ * |m> (x) |v_j> (column c = j*d_s + m) runs k steps of the scalar Lanczos
+ * recurrence (Algorithm 1 with block size one, no reorthogonalisation);
+ * psi = Lanczos approximation of exp(-beta (H_t - E0)/2) |m>(x)|v_j>; the
+ * averaged Gram M(beta) = (1/n_v) sum_j Psi_j^T Psi_j estimates
+ * exp(beta E0) tr_b exp(-beta H_t) / d_b (eqn:trace_est, eqn:fT, eqn:trB_est).
+ * A second Lanczos run on H_b from the same v_j gives Z_b (eqn:H_est).  E0 /
+ * E0b are the smallest Ritz values over all columns (the overflow shift of the
+ * section on the mean force Hamiltonian).
+ */
+#ifndef RDM_H
+#define RDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RDM_OK = 0,
+  RDM_E_INVALID = -1,   /* argument out of range; nothing was written       */
+  RDM_E_NOMEM = -2,     /* not enough device memory even for the two-pass plan */
+  RDM_E_DEVICE = -3,    /* a HIP runtime call failed                         */
+  RDM_E_NONFINITE = -4, /* a non-finite value appeared during the solve      */
+  RDM_E_BUSY = -5       /* serving queue full                                */
+} rdm_status;
+
+enum { RDM_FP64 = 0, RDM_MIXED = 1 };                 /* rdm_options.precision */
+enum { RDM_AUTO = 0, RDM_STORED_Q = 1, RDM_TWO_PASS = 2 }; /* rdm_options.mode  */
+
+/* One two-site term: jx sx_i sx_j + jy sy_i sy_j + jz sz_i sz_j (Pauli),
+ * eqn:Ht.  0 <= i, j < N, i != j; (i, j) and (j, i) denote the same pair. */
+typedef struct {
+  int32_t i, j;
+  double jx, jy, jz;
+} rdm_coupling;
+
+typedef struct rdm_hamiltonian rdm_hamiltonian; /* opaque, immutable */
+
+/* Solver options; a NULL pointer means all defaults (zeros). */
+typedef struct {
+  int32_t precision;   /* RDM_FP64: vectors and arithmetic in FP64.
+                          RDM_MIXED: vectors, the Hamiltonian apply and the
+                          three-term recurrence in FP32; every dot product and
+                          norm accumulated in FP64; tridiagonal eigenproblems,
+                          exponentials, cross-tile Gram sums, the n_v average
+                          and the finalisation in FP64.                      */
+  int32_t mode;        /* RDM_AUTO: stored Lanczos basis if it fits in
+                          hbm_budget, else two-pass.  RDM_STORED_Q: keep all
+                          k Lanczos vectors.  RDM_TWO_PASS: keep two; a second
+                          pass regenerates them bit-identically from the stored
+                          recurrence coefficients.                           */
+  uint64_t hbm_budget; /* bytes of device memory the solve may use; 0 = free
+                          device memory minus a 2 GiB reserve                */
+  int32_t slab;        /* apply kernel: 16-byte panels per lane (0 = tuned)   */
+  int32_t rows_per_lane;/* apply kernel: rows per lane (0 = tuned)            */
+  double tau;          /* breakdown threshold (0 = 1e-12 FP64, 1e-5 mixed)    */
+  int32_t reserved[4]; /* reserved[0] = 1: time the step kernels with HIP
+                          events on hip_stream (results in rdm_result.diag);
+                          others must be 0                                   */
+} rdm_options;
+
+/* Outputs of a solve, per inverse temperature (caller-owned host arrays). */
+typedef struct {
+  double* rho;      /* n_beta x d_s x d_s, row-major: rho*(beta) = M / tr M   */
+  double* h_star;   /* n_beta x d_s x d_s: mean force Hamiltonian (eqn:HMF)  */
+  double* log_z;    /* n_beta: ln Z* = ln Z_t - ln Z_b                       */
+  double* entropy;  /* n_beta: -tr rho* ln rho*                              */
+  double* diag;     /* optional (NULL ok), 16 + 2*n_beta doubles:
+                       [0] E0, [1] E0b, [2] columns of H_t that hit breakdown,
+                       [3] columns of H_b that hit breakdown, [4] 1 if the
+                       two-pass plan was used, [5] device bytes of the plan,
+                       [6] mu_min/mu_max of the last beta, [7] mean apply
+                       kernel time (ms), [8] mean norm kernel time (ms),
+                       [9] mean Gram kernel time (ms) -- [7..9] only when
+                       rdm_options.reserved[0] = 1 (event timing), else 0 --
+                       [10..15] zero; then per beta {ln Z_t, ln Z_b}.        */
+} rdm_result;
+
+/* Build a Hamiltonian (eqn:Ht) and its bath part.  hx, hz: host arrays of
+ * length n_s + n_b, coefficients of sx_i and sz_i; NULL means all zero.
+ * Validation: 1 <= n_s <= 3, 1 <= n_b, n_s + n_b <= 28, every coefficient
+ * finite, 0 <= i,j < N, i != j.  The library copies all inputs; device tables
+ * are built lazily on first use on the current device. */
+rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm_coupling* couplings,
+                                  int64_t n_couplings, const double* hx, const double* hz,
+                                  rdm_hamiltonian** out);
+void rdm_hamiltonian_destroy(rdm_hamiltonian* h);
+
+/* Table sizes of a built Hamiltonian: out[0]=N, [1]=n_s, [2]=n_b,
+ * [3]=uniform-coefficient hops, [4]=parity-dependent hops, [5]=diagonal terms,
+ * [6..8] the same three counts for H_b.  out: host array of 9 int64. */
+rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* out);
+
+/* Full solve (blocking; results on the host).  beta: host array of n_beta
+ * inverse temperatures, each > 0 and finite.  n_v >= 1 bath vectors, k >= 1
+ * Lanczos steps (capped at 2^N).  hip_stream: a hipStream_t or NULL for the
+ * null stream.  Device workspace is allocated and freed by the library. */
+rdm_status rdm_solve(const rdm_hamiltonian* h, const double* beta, int32_t n_beta, int32_t n_v,
+                     int32_t k, uint64_t seed, const rdm_options* opt, void* hip_stream,
+                     rdm_result* out);
+
+/* Device bytes rdm_solve_ws needs for these arguments (host output). */
+rdm_status rdm_workspace_size(const rdm_hamiltonian* h, int32_t n_beta, int32_t n_v, int32_t k,
+                              const rdm_options* opt, uint64_t* bytes);
+
+/* As rdm_solve, but all device memory comes from the caller's workspace
+ * (device pointer, 256-byte aligned, at least rdm_workspace_size bytes,
+ * borrowed for the duration of the call).  Device tables of the Hamiltonian
+ * are still cached inside the handle. */
+rdm_status rdm_solve_ws(const rdm_hamiltonian* h, const double* beta, int32_t n_beta, int32_t n_v,
+                        int32_t k, uint64_t seed, const rdm_options* opt, void* hip_stream,
+                        rdm_result* out, void* dev_workspace, uint64_t ws_bytes);
+
+/* One instance of a batched solve. */
+typedef struct {
+  const rdm_hamiltonian* h;
+  const double* beta;   /* host, n_beta entries */
+  int32_t n_beta, n_v, k;
+  uint64_t seed;
+  rdm_result out;
+  rdm_status status;    /* written by rdm_solve_batch */
+} rdm_batch_item;
+
+/* Solve independent instances of different sizes together: all instances
+ * advance their Lanczos recurrences in the same kernel launches (one launch per
+ * kernel per step for the whole batch), grouped into waves that fit in
+ * hbm_budget.  Each instance's result is bitwise identical to its own
+ * rdm_solve with the same options (fixed per-instance reduction order).
+ * Returns the first failing item's status, RDM_OK if all succeeded. */
+rdm_status rdm_solve_batch(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
+                           void* hip_stream);
+
+/* ---- Kernel-level entry points (device pointers; used by tests/bench) ---- */
+
+/* Block layout used by the library ("panels"): a block of C columns of length
+ * dim = 2^n is stored as ceil(C / w) panels of w = 16 / sizeof(scalar)
+ * columns (w = 2 FP64, 4 FP32); panel p holds rows 0..dim-1 of columns
+ * p*w .. p*w+w-1, row-major with the w values of one row contiguous (16 bytes),
+ * and the panels follow each other: element (row, c) is at offset
+ * ((c / w) * dim + row) * w + c % w.  Columns past C in the last panel are
+ * padding. */
+
+/* Y = H X (which = 0: H_t on 2^N rows; which = 1: H_b on 2^n_b rows), the
+ * matrix-free spin-Hamiltonian apply of the hot path (H is accessed only
+ * through such products, Section "Past algorithms").  x, y: device, panel
+ * layout above with n_cols columns, FP64 (precision RDM_FP64) or FP32
+ * (RDM_MIXED); x and y must not overlap.  Asynchronous on hip_stream. */
+rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t precision, int32_t n_cols,
+                     const void* x, void* y, const rdm_options* opt, void* hip_stream);
+
+/* The start block of a solve: column c = j*d_s + m is |m> (x) |v_j> (which = 0,
+ * 2^N rows, d_s*n_v columns) or v_j itself (which = 1, 2^n_b rows, n_v
+ * columns), in the panel layout.  out: device.  Asynchronous. */
+rdm_status rdm_start_block(const rdm_hamiltonian* h, int32_t which, int32_t precision, int32_t n_v,
+                           uint64_t seed, void* out, void* hip_stream);
+
+/* Run only the Lanczos recurrences of a solve (k steps on every start column
+ * of H_t, or of H_b if which = 1) and return their coefficients (blocking):
+ * host_alpha, host_beta: k x n_cols doubles (row j holds alpha_{j+1} /
+ * beta_{j+1} of every column), host_kc: n_cols int32 Krylov sizes after
+ * breakdown truncation.  n_cols = d_s*n_v (which = 0) or n_v (which = 1). */
+rdm_status rdm_lanczos(const rdm_hamiltonian* h, int32_t which, int32_t n_v, int32_t k,
+                       uint64_t seed, const rdm_options* opt, void* hip_stream,
+                       double* host_alpha, double* host_beta, int32_t* host_kc);
+
+/* Host routine of the hot path's step "eigendecomposition of T_k and function
+ * approximation weights" (eqn:fT): for one symmetric tridiagonal matrix with
+ * diagonal alpha[0..kk-1] and off-diagonal beta[0..kk-2] (host arrays) compute
+ * its eigenvalues theta (host out, kk) and, for each of n_beta inverse
+ * temperatures b, y_b = exp(-b (T - e0)/2) e_1 (host out, n_beta x kk) and the
+ * Gauss quadrature e_1^T exp(-b (T - e0)) e_1 (host out, n_beta).  Any output
+ * pointer may be NULL.  Implicit symmetric QR with Wilkinson shifts; the
+ * rotations are replayed on e_1 instead of forming the eigenvectors. */
+rdm_status rdm_tridiag_fa(int32_t kk, const double* alpha, const double* beta, int32_t n_beta,
+                          const double* betas, double e0, double* theta, double* y, double* quad);
+
+/* ---- Serving: continuous batching over one device stream ---- */
+
+typedef struct rdm_server rdm_server;
+
+/* Start a serving engine on the current device.  hbm_budget: device bytes the
+ * engine may hold for admitted requests (0 = free memory minus a reserve);
+ * max_active: most requests resident at once (0 = 64).  precision: as
+ * rdm_options.  A worker thread owns the device work. */
+rdm_status rdm_server_create(uint64_t hbm_budget, int32_t max_active, int32_t precision,
+                             rdm_server** out);
+/* Queue a solve (non-blocking).  The Hamiltonian must outlive the request;
+ * beta is copied.  ticket: host out.  Outputs are written into the caller's
+ * result buffers when the request completes. */
+rdm_status rdm_server_submit(rdm_server* s, const rdm_hamiltonian* h, const double* beta,
+                             int32_t n_beta, int32_t n_v, int32_t k, uint64_t seed,
+                             rdm_result out, uint64_t* ticket);
+/* done = 1 once the ticket's results are in its buffers; status = the solve's
+ * status.  Non-blocking. */
+rdm_status rdm_server_poll(rdm_server* s, uint64_t ticket, int32_t* done, rdm_status* status);
+/* Block until the ticket completes. */
+rdm_status rdm_server_wait(rdm_server* s, uint64_t ticket, rdm_status* status);
+/* Counters: out[0] submitted, [1] completed, [2] active, [3] queued, [4] engine
+ * steps, [5] peak active, [6] peak device bytes.  host out, 7 int64. */
+rdm_status rdm_server_stats(rdm_server* s, int64_t* out);
+/* Drain outstanding work and stop the engine. */
+void rdm_server_destroy(rdm_server* s);
+
+/* Message of the calling thread's last failure (valid until its next call). */
+const char* rdm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RDM_H */

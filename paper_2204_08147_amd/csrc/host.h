@@ -1,0 +1,83 @@
+// Host-side structures of the library (not part of the ABI).
+#pragma once
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace rdm {
+
+// Thread-local error message behind rdm_last_error().
+void set_error(const std::string& msg);
+const char* last_error();
+
+#define RDM_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::rdm::set_error(std::string(#call) + ": " + hipGetErrorString(e_));             \
+      return RDM_E_DEVICE;                                                             \
+    }                                                                                  \
+  } while (0)
+
+// Compiled term tables of one operator (H_t or H_b) on nbits sites.
+struct OpTables {
+  int nbits = 0;
+  std::vector<DiagTerm> diag;
+  std::vector<uint32_t> uf;   // uniform-coefficient hops
+  std::vector<double> uc;
+  std::vector<uint32_t> pf, pm;  // parity-dependent hops
+  std::vector<double> pcs, pcd;
+};
+
+// Device copy of an operator's tables in one precision.
+struct OpDevice {
+  bool ready = false;
+  int device = -1;
+  void* hopU = nullptr;
+  void* hopP = nullptr;
+  void* diag = nullptr;
+  void* dterms = nullptr;
+  int nU = 0, nP = 0;
+};
+
+}  // namespace rdm
+
+struct rdm_hamiltonian {
+  int n_s = 0, n_b = 0, n = 0;
+  std::vector<rdm_coupling> couplings;
+  std::vector<double> hx, hz;
+  rdm::OpTables op[2];           // [0] H_t, [1] H_b
+  mutable std::mutex mu;
+  mutable rdm::OpDevice dev[2][2];  // [which][precision]
+};
+
+namespace rdm {
+
+// Device tables of h for (which, precision), built on first use on the
+// current device (synchronous).
+rdm_status get_device_op(const rdm_hamiltonian* h, int which, int precision, hipStream_t st,
+                         const OpDevice** out);
+
+// Symmetric tridiagonal eigenproblem by implicit QR with Wilkinson shifts.
+// Fills theta (n) and zrow = first row of the eigenvector matrix (n), and
+// keeps the rotation sequence so that S w (S = eigenvectors) can be formed
+// later by replaying it.
+struct TridiagEig {
+  int n = 0;
+  std::vector<double> theta, zrow;
+  std::vector<int32_t> rot_i;
+  std::vector<double> rot_c, rot_s;
+  bool ok = true;
+  void solve(const double* alpha, const double* beta, int n);
+  // y = S diag(g) S^T e_1 for g_i given.
+  void apply_fn(const double* g, double* y) const;
+};
+
+// Eigendecomposition of a small symmetric matrix (cyclic Jacobi, n <= 16):
+// a (row-major n x n) -> eigenvalues w (ascending) and eigenvectors v (columns).
+void sym_eig_small(int n, const double* a, double* w, double* v);
+
+}  // namespace rdm

@@ -1,0 +1,132 @@
+// Internal declarations shared by the host driver and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rdm.h"
+
+namespace rdm {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxSlab = 4;        // most 16-byte panels one lane handles
+
+// Per-column device state, index [ST_x * cpad + c] (FP64).
+enum {
+  ST_SCUR = 0,   // s_j: scale of the current stored vector, q_j = s_j u_j
+  ST_SPREV,      // s_{j-1}
+  ST_BPS,        // beta_{j-1} * s_{j-1}: weight of u_{j-1} in the recurrence
+  ST_ACUR,       // alpha_j * s_j: weight of u_j when forming u_{j+1}
+  ST_RUNMAX,     // running max of |alpha_i|, beta_i (breakdown scale)
+  ST_FROZEN,     // 1 once the column hit breakdown (or is padding)
+  ST_COUNT
+};
+
+enum { MODE_LANCZOS = 0, MODE_REGEN = 1, MODE_PLAIN = 2 };
+enum { START_SYSBATH = 0, START_BATH = 1 };
+
+// Hop with a coefficient that does not depend on the basis state.
+template <typename T>
+struct alignas(16) HopU {
+  uint32_t f;      // flip mask
+  uint32_t pad;
+  T c;
+};
+// Hop whose coefficient depends on whether the two tested bits agree:
+// c = (parity(idx & m) == 0) ? cs : cd  (XX+YY pair: cs = jx - jy, cd = jx + jy).
+template <typename T>
+struct alignas(16) HopP {
+  uint32_t f, m;
+  T cs, cd;
+};
+// Diagonal term: c * (1 - 2 * parity(idx & mask)).
+struct DiagTerm {
+  uint32_t mask;
+  uint32_t pad;
+  double c;
+};
+
+// One Lanczos problem inside a (possibly batched) launch.  Lives in device
+// memory; all kernels read it with uniform loads.
+struct Seg {
+  const void* hopU;
+  const void* hopP;
+  const void* diag;
+  int32_t nU, nP;
+  int32_t nbits;       // log2(dim)
+  int32_t P;           // panels
+  int32_t S;           // panels per lane in apply/norm
+  int32_t rpl;         // rows per lane in apply/norm
+  int32_t C;           // real columns
+  int32_t cpad;        // P * panel width
+  int32_t k;
+  int32_t mode;        // MODE_*
+  int32_t ring;        // 0: slot j is Q + (j-1)*blk; 1: slot j is Q + ((j-1)&1)*blk
+  int32_t start_kind;  // START_*
+  int32_t ns_log;      // log2 d_s for START_SYSBATH
+  int32_t nb;          // bath bits (RNG index range)
+  int32_t n_beta;      // psi blocks (MODE_REGEN)
+  int32_t n_row_tiles; // partial-sum rows
+  uint64_t seed;
+  uint64_t blk;        // elements per vector block = dim * cpad
+  void* Q;
+  void* R;
+  void* psi;           // n_beta blocks (MODE_REGEN)
+  const void* ytab;    // [n_beta][k][cpad] in T (MODE_REGEN)
+  double* st;          // [ST_COUNT][cpad]
+  double* h_alpha;     // [k][cpad]
+  double* h_beta;      // [k][cpad]  entry j-1 holds beta_j (0 after breakdown)
+  double* h_s;         // [k][cpad]  entry j-1 holds s_j
+  double* part;        // [n_row_tiles][cpad]
+  int32_t* stepc;      // [cpad] current step (1-based) per column
+  int32_t* kc;         // [cpad] Krylov size after breakdown truncation
+  double tau;
+  int32_t pad0, pad1;
+};
+
+// Work item of the apply / norm kernels.
+struct Tile {
+  int32_t seg;
+  uint32_t row0;
+  int32_t panel0;
+  int32_t rtile;
+};
+
+// Segment of the Gram kernel.
+struct GSeg {
+  const void* Q;        // k slots (stored) or n_beta psi blocks
+  const void* ytab;     // [n_beta][k][cpad]
+  double* gpart;        // [n_row_tiles][n_beta][n_v][ds][ds]
+  uint64_t blk;
+  int32_t nbits, cpad, k, n_beta, n_v, ds_log, rpl, from_psi;
+  int32_t n_row_tiles, pad;
+};
+struct GTile {
+  int32_t seg;
+  uint32_t row0;
+  int32_t cblock;       // column block of width CB
+  int32_t rtile;
+};
+
+// ---- kernel launchers (kernels.hip) ----
+template <typename T>
+hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st);
+template <typename T>
+hipError_t launch_norm(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st);
+template <typename T>
+hipError_t launch_apply(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st);
+hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);
+hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st);
+hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st);
+template <typename T>
+hipError_t launch_gram(const GSeg* gs, const GTile* tiles, int ntiles, int ds, int nb_chunk,
+                       int beta0, int k, hipStream_t st);
+hipError_t launch_colsum(const double* part, int nrows, int width, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_start_block(int ns_log, int nb, int C, uint64_t seed, int kind, T* out,
+                              int nbits, int cpad, hipStream_t st);
+
+}  // namespace rdm

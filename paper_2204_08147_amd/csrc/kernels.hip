@@ -1,0 +1,667 @@
+// gfx950 kernels of the typicality RDM solver.
+//
+// Data layout ("panels"): a block of C columns over dim rows is stored as
+// P = cpad / W panels of W = 16 / sizeof(T) columns; panel p is a dim x W
+// row-major array, so one row of a panel is 16 bytes and a wave64 reading 64
+// consecutive rows of one panel reads 1 KiB contiguous.  A gathered partner
+// row idx ^ f of 64 consecutive rows is again an aligned 64-row block, so
+// every gather of the spin-Hamiltonian apply is a fully coalesced 1 KiB read.
+//
+// Every kernel takes a table of segments (independent Lanczos problems) and
+// a table of tiles, so a single launch advances any mix of instances of
+// different sizes and at different steps (batched solves, serving).
+#include "internal.h"
+
+namespace rdm {
+
+template <typename T> struct PanelT;
+template <> struct PanelT<float> {
+  typedef float V __attribute__((ext_vector_type(4)));
+  static constexpr int W = 4;
+};
+template <> struct PanelT<double> {
+  typedef double V __attribute__((ext_vector_type(2)));
+  static constexpr int W = 2;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// SplitMix64 output from state x (Steele, Lea & Flood 2014).
+__device__ __forceinline__ uint64_t sm64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Rademacher sign bit of bath vector j at bath index b.
+__device__ __forceinline__ uint32_t bath_bit(uint64_t seed, uint32_t j, uint64_t b) {
+  const uint64_t key = sm64(seed ^ sm64((uint64_t)j));
+  const uint64_t word = sm64(key ^ (b >> 6));
+  return (uint32_t)((word >> (b & 63)) & 1ull);
+}
+
+template <typename T> __device__ __forceinline__ T amp_of(int nb);
+template <> __device__ __forceinline__ double amp_of<double>(int nb) { return sqrt(ldexp(1.0, -nb)); }
+template <> __device__ __forceinline__ float amp_of<float>(int nb) { return sqrtf(ldexpf(1.0f, -nb)); }
+
+// Start-block entry (row, column c): |m> (x) |v_j> with c = j*d_s + m, or v_c.
+template <typename T>
+__device__ __forceinline__ T start_value(int kind, int ns_log, int nb, uint64_t seed, uint32_t row,
+                                         int c, int C, T amp) {
+  if (c >= C) return T(0);
+  uint32_t j, b;
+  if (kind == START_SYSBATH) {
+    const int m = c & ((1 << ns_log) - 1);
+    j = (uint32_t)(c >> ns_log);
+    if ((int)(row >> nb) != m) return T(0);
+    b = row & ((1u << nb) - 1u);
+  } else {
+    j = (uint32_t)c;
+    b = row;
+  }
+  return bath_bit(seed, j, b) ? -amp : amp;
+}
+
+// 16-byte panel access with a uniform base and a 32-bit row offset, so the
+// compiler can use global loads with an SGPR base and a VGPR offset.
+template <typename V>
+__device__ __forceinline__ V ldp(const V* base, uint32_t row) {
+  return *(const V*)((const char*)base + (uint32_t)(row << 4));
+}
+template <typename V>
+__device__ __forceinline__ void stp(V* base, uint32_t row, V v) {
+  *(V*)((char*)base + (uint32_t)(row << 4)) = v;
+}
+
+__device__ __forceinline__ float fma_s(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_s(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum NV per-lane values over the workgroup in a fixed tree; threads 0..NV-1
+// receive the totals.  lds: 4*NV doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* tot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int t = threadIdx.x;
+    *tot = ((lds[t] + lds[NV + t]) + lds[2 * NV + t]) + lds[3 * NV + t];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T* slot_ptr(const Seg& sg, int j) {
+  const int idx = sg.ring ? ((j - 1) & 1) : (j - 1);
+  return (T*)sg.Q + (uint64_t)idx * sg.blk;
+}
+
+// ---------------------------------------------------------------------------
+// diagonal of H: sum_t c_t (1 - 2 parity(idx & mask_t)), accumulated in FP64
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(const DiagTerm* __restrict__ terms, int nt,
+                                                 T* __restrict__ diag, uint32_t dim) {
+  const uint32_t row = blockIdx.x * kBlock + threadIdx.x;
+  if (row >= dim) return;
+  double d = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const uint32_t par = __builtin_popcount(row & terms[t].mask) & 1u;
+    d += par ? -terms[t].c : terms[t].c;
+  }
+  diag[row] = (T)d;
+}
+
+// ---------------------------------------------------------------------------
+// state initialisation: phase 0 = fresh Lanczos run, 1 = regeneration pass
+// ---------------------------------------------------------------------------
+__global__ void k_init_state(const Seg* __restrict__ segs, int phase) {
+  const Seg& sg = segs[blockIdx.x];
+  const int c = blockIdx.y * 64 + threadIdx.x;
+  if (c >= sg.cpad) return;
+  const int cp = sg.cpad;
+  for (int i = 0; i < ST_COUNT; ++i) sg.st[i * cp + c] = 0.0;
+  sg.st[ST_FROZEN * cp + c] = (c >= sg.C) ? 1.0 : 0.0;
+  sg.stepc[c] = 1;
+  if (phase == 0) sg.kc[c] = (c >= sg.C) ? 0 : sg.k;
+}
+
+// ---------------------------------------------------------------------------
+// norm kernel: u_j = r - (alpha_{j-1} s_{j-1}) u_{j-1}  (j >= 2) or the start
+// block (j = 1); partial sums of |u_j|^2; in the regeneration pass also
+// psi_b = fma(y_{b,j}, u_j, psi_b).
+// ---------------------------------------------------------------------------
+template <typename T, int SM>
+__global__ __launch_bounds__(kBlock) void k_norm(const Seg* __restrict__ segs,
+                                                 const Tile* __restrict__ tiles) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  __shared__ double lds[4 * SM * W];
+  const Tile t = tiles[blockIdx.x];
+  const Seg& sg = segs[t.seg];
+  const int j = sg.stepc[0];
+  if (j > sg.k) return;
+  const int S = sg.S, cp = sg.cpad;
+  const uint32_t dim = 1u << sg.nbits;
+  const uint64_t pstride = (uint64_t)dim;   // panel stride in V units
+
+  V* ucur = (V*)slot_ptr<T>(sg, j);
+  const V* uprev = (j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) : nullptr;
+  const V* rv = (const V*)sg.R;
+  const bool regen = sg.mode == MODE_REGEN;
+  const T amp = amp_of<T>(sg.nb);
+
+  V acur[SM];
+#pragma unroll
+  for (int s = 0; s < SM; ++s)
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const int c = (t.panel0 + s) * W + e;
+      acur[s][e] = (s < S) ? (T)sg.st[ST_ACUR * cp + c] : T(0);
+    }
+
+  double dsum[SM * W];
+#pragma unroll
+  for (int i = 0; i < SM * W; ++i) dsum[i] = 0.0;
+
+  for (int rr = 0; rr < sg.rpl; ++rr) {
+    const uint32_t row = t.row0 + rr * kBlock + threadIdx.x;
+    if (row >= dim) break;
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      if (s >= S) break;
+      const int panel = t.panel0 + s;
+      V u;
+      if (j == 1) {
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+          u[e] = start_value<T>(sg.start_kind, sg.ns_log, sg.nb, sg.seed, row, panel * W + e, sg.C, amp);
+      } else {
+        const V r = ldp(rv + panel * pstride, row);
+        const V up = ldp(uprev + panel * pstride, row);
+#pragma unroll
+        for (int e = 0; e < W; ++e) u[e] = fma_s(-acur[s][e], up[e], r[e]);
+      }
+      stp(ucur + panel * pstride, row, u);
+#pragma unroll
+      for (int e = 0; e < W; ++e) dsum[s * W + e] += (double)u[e] * (double)u[e];
+      if (regen) {
+        const T* yt = (const T*)sg.ytab;
+        for (int b = 0; b < sg.n_beta; ++b) {
+          V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + panel * pstride;
+          V old;
+          if (j == 1) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) old[e] = T(0);
+          } else {
+            old = ldp(pb, row);
+          }
+          V nw;
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            const T y = yt[((uint64_t)b * sg.k + (j - 1)) * cp + panel * W + e];
+            nw[e] = fma_s(y, u[e], old[e]);
+          }
+          stp(pb, row, nw);
+        }
+      }
+    }
+  }
+  double tot;
+  block_sum<SM * W>(dsum, lds, &tot);
+  if (threadIdx.x < S * W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// apply kernel: r = s_j (H u_j) - (beta_{j-1} s_{j-1}) u_{j-1}, partial sums of
+// <u_j, r>.  MODE_PLAIN: Y = H X with X = Q, Y = R.
+// ---------------------------------------------------------------------------
+template <typename T, int SM>
+__global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs,
+                                                  const Tile* __restrict__ tiles) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  __shared__ double lds[4 * SM * W];
+  const Tile t = tiles[blockIdx.x];
+  const Seg& sg = segs[t.seg];
+  const bool plain = sg.mode == MODE_PLAIN;
+  int j = 1;
+  if (!plain) {
+    j = sg.stepc[0];
+    if (j > sg.k) return;
+  }
+  const int S = sg.S, cp = sg.cpad;
+  const uint32_t dim = 1u << sg.nbits;
+  const uint64_t pstride = (uint64_t)dim;
+  const V* ucur = plain ? (const V*)sg.Q : (const V*)slot_ptr<T>(sg, j);
+  const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) : nullptr;
+  V* out = (V*)sg.R;
+  const HopU<T>* __restrict__ hu = (const HopU<T>*)sg.hopU;
+  const HopP<T>* __restrict__ hp = (const HopP<T>*)sg.hopP;
+  const T* __restrict__ dg = (const T*)sg.diag;
+  const int nU = sg.nU, nP = sg.nP;
+  const bool dots = sg.mode == MODE_LANCZOS;
+
+  V scur[SM], bps[SM];
+#pragma unroll
+  for (int s = 0; s < SM; ++s)
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const int c = (t.panel0 + s) * W + e;
+      scur[s][e] = plain ? T(1) : ((s < S) ? (T)sg.st[ST_SCUR * cp + c] : T(0));
+      bps[s][e] = plain ? T(0) : ((s < S) ? (T)sg.st[ST_BPS * cp + c] : T(0));
+    }
+
+  const V* ub[SM];
+#pragma unroll
+  for (int s = 0; s < SM; ++s) ub[s] = ucur + (uint64_t)(t.panel0 + (s < S ? s : 0)) * pstride;
+
+  double dq[SM * W];
+#pragma unroll
+  for (int i = 0; i < SM * W; ++i) dq[i] = 0.0;
+
+  for (int rr = 0; rr < sg.rpl; ++rr) {
+    const uint32_t row = t.row0 + rr * kBlock + threadIdx.x;
+    const uint32_t wbase = __builtin_amdgcn_readfirstlane(row & ~63u);
+    if (wbase >= dim) break;
+    if (row < dim) {
+      const T d = dg[row];
+      V acc[SM], xc[SM];
+#pragma unroll
+      for (int s = 0; s < SM; ++s) {
+        if (s < S) {
+          xc[s] = ldp(ub[s], row);
+          acc[s] = d * xc[s];
+        }
+      }
+      for (int h = 0; h < nU; ++h) {
+        const uint32_t p = row ^ hu[h].f;
+        const T c = hu[h].c;
+#pragma unroll
+        for (int s = 0; s < SM; ++s)
+          if (s < S) acc[s] += c * ldp(ub[s], p);
+      }
+      for (int h = 0; h < nP; ++h) {
+        const uint32_t f = hp[h].f, m = hp[h].m;
+        const T cs = hp[h].cs, cd = hp[h].cd;
+        const uint32_t p = row ^ f;
+        T c;
+        if ((m & 63u) == 0u) {
+          // both tested bits are above the 64 rows of this wave: uniform
+          c = (__builtin_popcount(wbase & m) & 1u) ? cd : cs;
+          if (c == T(0)) continue;
+        } else {
+          c = (__builtin_popcount(row & m) & 1u) ? cd : cs;
+        }
+#pragma unroll
+        for (int s = 0; s < SM; ++s)
+          if (s < S) acc[s] += c * ldp(ub[s], p);
+      }
+#pragma unroll
+      for (int s = 0; s < SM; ++s) {
+        if (s < S) {
+          const uint64_t po = (uint64_t)(t.panel0 + s) * pstride;
+          V r = scur[s] * acc[s];
+          if (uprev) {
+            const V up = ldp(uprev + po, row);
+#pragma unroll
+            for (int e = 0; e < W; ++e) r[e] = fma_s(-bps[s][e], up[e], r[e]);
+          }
+          stp(out + po, row, r);
+          if (dots) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) dq[s * W + e] += (double)xc[s][e] * (double)r[e];
+          }
+        }
+      }
+    }
+  }
+  if (!dots) return;
+  double tot;
+  block_sum<SM * W>(dq, lds, &tot);
+  if (threadIdx.x < S * W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// reductions of the per-tile partial sums, one thread per column; fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double column_total(const Seg& sg, int c, double (*lds)[64]) {
+  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  double s = 0.0;
+  if (c < sg.cpad)
+    for (int t = grp; t < sg.n_row_tiles; t += 4) s += sg.part[(uint64_t)t * sg.cpad + c];
+  lds[grp][cl] = s;
+  __syncthreads();
+  return ((lds[0][cl] + lds[1][cl]) + lds[2][cl]) + lds[3][cl];
+}
+
+// beta_{j-1} = |u_j| (or |u_1| -> s_1 at j = 1), breakdown test, scales.
+__global__ __launch_bounds__(kBlock) void k_red_beta(const Seg* __restrict__ segs) {
+  const Seg& sg = segs[blockIdx.x];
+  if ((int)blockIdx.y * 64 >= sg.cpad) return;
+  __shared__ double lds[4][64];
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  const double tot = column_total(sg, c, lds);
+  if ((threadIdx.x >> 6) != 0 || c >= sg.cpad) return;
+  const int j = sg.stepc[c];
+  if (j > sg.k) return;
+  const int cp = sg.cpad;
+  double* st = sg.st;
+  const bool frozen = st[ST_FROZEN * cp + c] != 0.0;
+  double s, beff;
+  if (sg.mode == MODE_REGEN) {
+    s = sg.h_s[(uint64_t)(j - 1) * cp + c];
+    beff = (j == 1) ? 0.0 : sg.h_beta[(uint64_t)(j - 2) * cp + c];
+  } else if (j == 1) {
+    beff = 0.0;
+    s = frozen ? 0.0 : 1.0 / sqrt(tot);
+    st[ST_RUNMAX * cp + c] = 0.0;
+  } else {
+    const double b = sqrt(tot);
+    const double runmax = st[ST_RUNMAX * cp + c];
+    if (frozen) {
+      beff = 0.0;
+      s = 0.0;
+    } else if (!(b > sg.tau * runmax)) {
+      st[ST_FROZEN * cp + c] = 1.0;
+      sg.kc[c] = j - 1;
+      beff = 0.0;
+      s = 0.0;
+    } else {
+      st[ST_RUNMAX * cp + c] = fmax(runmax, b);
+      beff = b;
+      s = 1.0 / b;
+    }
+    sg.h_beta[(uint64_t)(j - 2) * cp + c] = beff;
+  }
+  if (sg.mode != MODE_REGEN) sg.h_s[(uint64_t)(j - 1) * cp + c] = s;
+  const double sprev = (j == 1) ? 0.0 : st[ST_SCUR * cp + c];
+  st[ST_BPS * cp + c] = beff * sprev;
+  st[ST_SPREV * cp + c] = sprev;
+  st[ST_SCUR * cp + c] = s;
+}
+
+// alpha_j = s_j <u_j, r>; weight alpha_j s_j for the next step; advance.
+__global__ __launch_bounds__(kBlock) void k_red_alpha(const Seg* __restrict__ segs) {
+  const Seg& sg = segs[blockIdx.x];
+  if ((int)blockIdx.y * 64 >= sg.cpad) return;
+  __shared__ double lds[4][64];
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  const double tot = column_total(sg, c, lds);
+  if ((threadIdx.x >> 6) != 0 || c >= sg.cpad) return;
+  const int j = sg.stepc[c];
+  if (j > sg.k) return;
+  const int cp = sg.cpad;
+  double* st = sg.st;
+  double a;
+  if (sg.mode == MODE_REGEN) {
+    a = sg.h_alpha[(uint64_t)(j - 1) * cp + c];
+  } else {
+    const bool frozen = st[ST_FROZEN * cp + c] != 0.0;
+    a = frozen ? 0.0 : st[ST_SCUR * cp + c] * tot;
+    st[ST_RUNMAX * cp + c] = fmax(st[ST_RUNMAX * cp + c], fabs(a));
+    sg.h_alpha[(uint64_t)(j - 1) * cp + c] = a;
+  }
+  st[ST_ACUR * cp + c] = a * st[ST_SCUR * cp + c];
+  sg.stepc[c] = j + 1;
+}
+
+// ---------------------------------------------------------------------------
+// recombination psi_b = sum_j y'_{b,j} u_j (fused) and the per-bath-vector
+// d_s x d_s Gram blocks, accumulated per lane over its rows in T and summed
+// across lanes / tiles in FP64.
+// ---------------------------------------------------------------------------
+template <typename T, int DS, int NB>
+__global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
+                                                 const GTile* __restrict__ tiles, int beta0) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  constexpr int CB = DS > W ? DS : W;
+  constexpr int NPAN = CB / W;
+  constexpr int NG = CB / DS;
+  constexpr int NE = DS * (DS + 1) / 2;
+  constexpr int NV = NB * NG * NE;
+  extern __shared__ double smem[];
+  double* lds = smem;                       // 4 * NV doubles
+  T* ys = (T*)(smem + 4 * NV);              // [k][NB][CB]
+  const GTile t = tiles[blockIdx.x];
+  const GSeg& g = gsegs[t.seg];
+  const uint32_t dim = 1u << g.nbits;
+  const uint64_t pstride = dim;
+  const int nb = (g.n_beta - beta0) < NB ? (g.n_beta - beta0) : NB;
+  const int k = g.k, cp = g.cpad;
+  const int col0 = t.cblock * CB;
+  if (!g.from_psi) {
+    const T* yt = (const T*)g.ytab;
+    for (int i = threadIdx.x; i < k * NB * CB; i += kBlock) {
+      const int jj = i / (NB * CB), rem = i % (NB * CB), b = rem / CB, cc = rem % CB;
+      ys[i] = (b < nb) ? yt[((uint64_t)(beta0 + b) * k + jj) * cp + col0 + cc] : T(0);
+    }
+    __syncthreads();
+  }
+  T gacc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) gacc[i] = T(0);
+
+  for (int rr = 0; rr < g.rpl; ++rr) {
+    const uint32_t row = t.row0 + rr * kBlock + threadIdx.x;
+    if (row >= dim) break;
+    V psi[NB][NPAN];
+    if (g.from_psi) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < NPAN; ++q) {
+          if (b < nb) {
+            const V* pb = (const V*)g.Q + (uint64_t)(beta0 + b) * (g.blk / W) +
+                          (uint64_t)(t.cblock * NPAN + q) * pstride;
+            psi[b][q] = ldp(pb, row);
+          } else {
+#pragma unroll
+            for (int e = 0; e < W; ++e) psi[b][q][e] = T(0);
+          }
+        }
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < NPAN; ++q)
+#pragma unroll
+          for (int e = 0; e < W; ++e) psi[b][q][e] = T(0);
+      for (int jj = 0; jj < k; ++jj) {
+        const V* sb = (const V*)g.Q + (uint64_t)jj * (g.blk / W);
+        V qv[NPAN];
+#pragma unroll
+        for (int q = 0; q < NPAN; ++q) qv[q] = ldp(sb + (uint64_t)(t.cblock * NPAN + q) * pstride, row);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int q = 0; q < NPAN; ++q)
+#pragma unroll
+            for (int e = 0; e < W; ++e)
+              psi[b][q][e] = fma_s(ys[(jj * NB + b) * CB + q * W + e], qv[q][e], psi[b][q][e]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int gg = 0; gg < NG; ++gg) {
+        int e = 0;
+#pragma unroll
+        for (int m = 0; m < DS; ++m)
+#pragma unroll
+          for (int n = m; n < DS; ++n) {
+            const int cm = gg * DS + m, cn = gg * DS + n;
+            const T pm = psi[b][cm / W][cm % W], pn = psi[b][cn / W][cn % W];
+            gacc[(b * NG + gg) * NE + e] = fma_s(pm, pn, gacc[(b * NG + gg) * NE + e]);
+            ++e;
+          }
+      }
+  }
+  double gv[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) gv[i] = (double)gacc[i];
+  double tot;
+  block_sum<NV>(gv, lds, &tot);
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    const int b = i / (NG * NE), gg = (i / NE) % NG, e = i % NE;
+    const int jv = t.cblock * NG + gg;
+    if (b < nb && jv < g.n_v) {
+      int m = 0, rem = e;
+      while (rem >= DS - m) { rem -= DS - m; ++m; }
+      const int n = m + rem;
+      double* o = g.gpart + ((((uint64_t)t.rtile * g.n_beta + beta0 + b) * g.n_v + jv) * DS) * DS;
+      o[m * DS + n] = tot;
+      o[n * DS + m] = tot;
+    }
+  }
+}
+
+// out[w] = sum over rows of part[row][w], rows summed in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_colsum(const double* __restrict__ part, int nrows,
+                                                   int width, double* __restrict__ out) {
+  __shared__ double lds[4][64];
+  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int w = blockIdx.x * 64 + cl;
+  double s = 0.0;
+  if (w < width)
+    for (int r = grp; r < nrows; r += 4) s += part[(uint64_t)r * width + w];
+  lds[grp][cl] = s;
+  __syncthreads();
+  if (grp == 0 && w < width) out[w] = ((lds[0][cl] + lds[1][cl]) + lds[2][cl]) + lds[3][cl];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_start_block(int ns_log, int nb, int C, uint64_t seed,
+                                                        int kind, T* __restrict__ out,
+                                                        uint32_t dim, int cpad) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  const uint32_t row = blockIdx.x * kBlock + threadIdx.x;
+  const int panel = blockIdx.y;
+  if (row >= dim) return;
+  const T amp = amp_of<T>(nb);
+  V u;
+#pragma unroll
+  for (int e = 0; e < W; ++e) u[e] = start_value<T>(kind, ns_log, nb, seed, row, panel * W + e, C, amp);
+  stp((V*)out + (uint64_t)panel * dim, row, u);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st) {
+  const uint32_t dim = 1u << nbits;
+  hipLaunchKernelGGL(k_diag<T>, dim3((dim + kBlock - 1) / kBlock), dim3(kBlock), 0, st, terms, nt,
+                     diag, dim);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_norm(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (slab) {
+    case 1: hipLaunchKernelGGL((k_norm<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+    case 2: hipLaunchKernelGGL((k_norm<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+    default: hipLaunchKernelGGL((k_norm<T, 4>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apply(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (slab) {
+    case 1: hipLaunchKernelGGL((k_apply<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+    case 2: hipLaunchKernelGGL((k_apply<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+    default: hipLaunchKernelGGL((k_apply<T, 4>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_red_beta, dim3(nseg, (cmax + 63) / 64), dim3(kBlock), 0, st, segs);
+  return hipGetLastError();
+}
+
+hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_red_alpha, dim3(nseg, (cmax + 63) / 64), dim3(kBlock), 0, st, segs);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_state, dim3(nseg, (cmax + 63) / 64), dim3(64), 0, st, segs, phase);
+  return hipGetLastError();
+}
+
+template <typename T, int DS, int NB>
+static hipError_t launch_gram_t(const GSeg* gs, const GTile* tiles, int ntiles, int beta0, int k,
+                                hipStream_t st) {
+  constexpr int W = PanelT<T>::W;
+  constexpr int CB = DS > W ? DS : W;
+  constexpr int NG = CB / DS;
+  constexpr int NE = DS * (DS + 1) / 2;
+  constexpr int NV = NB * NG * NE;
+  const size_t shm = 4 * NV * sizeof(double) + (size_t)k * NB * CB * sizeof(T);
+  hipLaunchKernelGGL((k_gram<T, DS, NB>), dim3(ntiles), dim3(kBlock), shm, st, gs, tiles, beta0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gram(const GSeg* gs, const GTile* tiles, int ntiles, int ds, int nb_chunk,
+                       int beta0, int k, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+#define RDM_G(DSV, NBV) \
+  if (ds == DSV && nb_chunk == NBV) return launch_gram_t<T, DSV, NBV>(gs, tiles, ntiles, beta0, k, st);
+  RDM_G(2, 1) RDM_G(2, 2) RDM_G(2, 4) RDM_G(4, 1) RDM_G(4, 2) RDM_G(4, 4)
+  RDM_G(8, 1) RDM_G(8, 2)
+#undef RDM_G
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_colsum(const double* part, int nrows, int width, double* out, hipStream_t st) {
+  if (width <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colsum, dim3((width + 63) / 64), dim3(kBlock), 0, st, part, nrows, width, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_start_block(int ns_log, int nb, int C, uint64_t seed, int kind, T* out, int nbits,
+                              int cpad, hipStream_t st) {
+  constexpr int W = PanelT<T>::W;
+  const uint32_t dim = 1u << nbits;
+  hipLaunchKernelGGL(k_start_block<T>, dim3((dim + kBlock - 1) / kBlock, cpad / W), dim3(kBlock), 0,
+                     st, ns_log, nb, C, seed, kind, out, dim, cpad);
+  return hipGetLastError();
+}
+
+template hipError_t launch_diag<float>(const DiagTerm*, int, float*, int, hipStream_t);
+template hipError_t launch_diag<double>(const DiagTerm*, int, double*, int, hipStream_t);
+template hipError_t launch_norm<float>(const Seg*, const Tile*, int, int, hipStream_t);
+template hipError_t launch_norm<double>(const Seg*, const Tile*, int, int, hipStream_t);
+template hipError_t launch_apply<float>(const Seg*, const Tile*, int, int, hipStream_t);
+template hipError_t launch_apply<double>(const Seg*, const Tile*, int, int, hipStream_t);
+template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
+template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
+template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);
+template hipError_t launch_start_block<double>(int, int, int, uint64_t, int, double*, int, int, hipStream_t);
+
+}  // namespace rdm

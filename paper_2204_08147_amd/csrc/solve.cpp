@@ -1,0 +1,600 @@
+// Solve driver: planning, workspace layout, the Lanczos step loop over a
+// batch of segments, host eigen-work, recombination + Gram, finalisation.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <thread>
+
+#include "host.h"
+#include "solve.h"
+
+namespace rdm {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int panel_width(int prec) { return prec == RDM_FP64 ? 2 : 4; }
+size_t scalar_bytes(int prec) { return prec == RDM_FP64 ? 8 : 4; }
+
+int ilog2(uint64_t x) {
+  int r = 0;
+  while ((1ull << r) < x) ++r;
+  return r;
+}
+
+void parallel_for(int n, const std::function<void(int)>& fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min({n, hw, 16});
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&] {
+      for (int i = next++; i < n; i = next++) fn(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// planning
+// ---------------------------------------------------------------------------
+void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
+              size_t& off) {
+  const int W = panel_width(prec);
+  const size_t sb = scalar_bytes(prec);
+  g.nbits = nbits;
+  g.dim = 1ull << nbits;
+  g.C = C;
+  g.P = (C + W - 1) / W;
+  g.cpad = g.P * W;
+  g.k = k;
+  int S = slab_opt > 0 ? slab_opt : kMaxSlab;
+  S = std::min(S, kMaxSlab);
+  while (S > 1 && (g.P % S) != 0) S >>= 1;
+  g.S = std::max(S, 1);
+  int rpl = rpl_opt;
+  if (rpl <= 0) {
+    // enough row tiles to fill 256 CUs several times over
+    const uint64_t slabs = g.P / g.S;
+    const uint64_t want_tiles = 4096;
+    uint64_t r = (g.dim * slabs) / (kBlock * want_tiles);
+    rpl = (int)std::max<uint64_t>(1, std::min<uint64_t>(r, 16));
+  }
+  g.rpl = rpl;
+  g.n_row_tiles = (int)((g.dim + (uint64_t)kBlock * rpl - 1) / ((uint64_t)kBlock * rpl));
+  g.blk = g.dim * g.cpad;
+  g.nslots = nslots;
+  g.o_Q = off; off = al(off + (size_t)nslots * g.blk * sb);
+  g.o_R = off; off = al(off + g.blk * sb);
+  g.o_st = off; off = al(off + (size_t)ST_COUNT * g.cpad * 8);
+  g.o_ha = off; off = al(off + (size_t)k * g.cpad * 8);
+  g.o_hb = off; off = al(off + (size_t)k * g.cpad * 8);
+  g.o_hs = off; off = al(off + (size_t)k * g.cpad * 8);
+  g.o_part = off; off = al(off + (size_t)g.n_row_tiles * g.cpad * 8);
+  g.o_step = off; off = al(off + (size_t)g.cpad * 4);
+  g.o_kc = off; off = al(off + (size_t)g.cpad * 4);
+}
+
+int max_nb_chunk(int prec, int ds) {
+  if (ds >= 8) return prec == RDM_FP64 ? 1 : 2;
+  return 4;
+}
+
+rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
+                         int mode_req, uint64_t budget, int slab_opt, int rpl_opt) {
+  p.h = h;
+  p.prec = prec;
+  p.n_beta = n_beta;
+  p.n_v = n_v;
+  const uint64_t dim = 1ull << h->n;
+  p.k = (int)std::min<uint64_t>((uint64_t)k, dim);
+  p.kb = (int)std::min<uint64_t>((uint64_t)k, 1ull << h->n_b);
+  p.ds_log = h->n_s;
+  p.ds = 1 << h->n_s;
+  const int W = panel_width(prec);
+  const size_t sb = scalar_bytes(prec);
+  p.cb = std::max(p.ds, W);
+  p.groups_per_block = p.cb / p.ds;
+  p.n_cblocks = (n_v + p.groups_per_block - 1) / p.groups_per_block;
+  p.nb_chunk = std::min(max_nb_chunk(prec, p.ds), n_beta <= 1 ? 1 : (n_beta <= 2 ? 2 : 4));
+  // LDS for the y slice of the Gram kernel
+  while (p.nb_chunk > 1 &&
+         (size_t)p.k * p.nb_chunk * p.cb * sb + 4 * 144 * 8 > 60 * 1024)
+    p.nb_chunk >>= 1;
+  if ((size_t)p.k * p.nb_chunk * p.cb * sb + 4 * 144 * 8 > 60 * 1024) {
+    set_error("k too large for the Gram kernel's LDS tile");
+    return RDM_E_INVALID;
+  }
+  auto layout = [&](bool two_pass) {
+    size_t off = 0;
+    plan_seg(p.tot, h->n, p.ds * n_v, p.k, prec, slab_opt, rpl_opt, two_pass ? 2 : p.k, off);
+    plan_seg(p.bath, h->n_b, n_v, p.kb, prec, slab_opt, rpl_opt, 2, off);
+    p.o_psi = off;
+    if (two_pass) off = al(off + (size_t)n_beta * p.tot.blk * sb);
+    p.o_y = off; off = al(off + (size_t)n_beta * p.k * p.tot.cpad * sb);
+    // Gram tiling
+    uint64_t r = (p.tot.dim * p.n_cblocks) / (kBlock * 4096ull);
+    p.g_rpl = (int)std::max<uint64_t>(1, std::min<uint64_t>(r, 16));
+    p.g_rtiles = (int)((p.tot.dim + (uint64_t)kBlock * p.g_rpl - 1) / ((uint64_t)kBlock * p.g_rpl));
+    p.o_gpart = off; off = al(off + (size_t)p.g_rtiles * n_beta * n_v * p.ds * p.ds * 8);
+    p.o_gsum = off; off = al(off + (size_t)n_beta * n_v * p.ds * p.ds * 8);
+    p.o_gseg = off; off = al(off + sizeof(GSeg));
+    p.o_gtiles = off; off = al(off + sizeof(GTile) * (size_t)p.g_rtiles * p.n_cblocks);
+    return off;
+  };
+  const size_t stored = layout(false);
+  const size_t twop = layout(true);
+  if (mode_req == RDM_STORED_Q) {
+    p.two_pass = false;
+  } else if (mode_req == RDM_TWO_PASS) {
+    p.two_pass = true;
+  } else {
+    p.two_pass = budget != 0 && stored > budget;
+  }
+  p.bytes = layout(p.two_pass);
+  (void)twop;
+  if (budget != 0 && p.bytes > budget) {
+    set_error("instance needs " + std::to_string(p.bytes) + " device bytes, budget " +
+              std::to_string(budget));
+    return RDM_E_NOMEM;
+  }
+  return RDM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// execution
+// ---------------------------------------------------------------------------
+namespace {
+
+Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int start_kind, int ns_log,
+             int nb, uint64_t seed, double tau) {
+  Seg s{};
+  s.hopU = op->hopU;
+  s.hopP = op->hopP;
+  s.diag = op->diag;
+  s.nU = op->nU;
+  s.nP = op->nP;
+  s.nbits = g.nbits;
+  s.P = g.P;
+  s.S = g.S;
+  s.rpl = g.rpl;
+  s.C = g.C;
+  s.cpad = g.cpad;
+  s.k = g.k;
+  s.mode = mode;
+  s.ring = g.nslots < g.k ? 1 : 0;
+  s.start_kind = start_kind;
+  s.ns_log = ns_log;
+  s.nb = nb;
+  s.n_beta = 0;
+  s.n_row_tiles = g.n_row_tiles;
+  s.seed = seed;
+  s.blk = g.blk;
+  s.Q = base + g.o_Q;
+  s.R = base + g.o_R;
+  s.psi = nullptr;
+  s.ytab = nullptr;
+  s.st = (double*)(base + g.o_st);
+  s.h_alpha = (double*)(base + g.o_ha);
+  s.h_beta = (double*)(base + g.o_hb);
+  s.h_s = (double*)(base + g.o_hs);
+  s.part = (double*)(base + g.o_part);
+  s.stepc = (int32_t*)(base + g.o_step);
+  s.kc = (int32_t*)(base + g.o_kc);
+  s.tau = tau;
+  return s;
+}
+
+struct HostHist {
+  std::vector<double> a, b, s;
+  std::vector<int32_t> kc;
+};
+
+rdm_status fetch_hist(const SegPlan& g, char* base, HostHist& hh, hipStream_t st) {
+  const size_t n = (size_t)g.k * g.cpad;
+  hh.a.resize(n);
+  hh.b.resize(n);
+  hh.s.resize(n);
+  hh.kc.resize(g.cpad);
+  RDM_HIP(hipMemcpyAsync(hh.a.data(), base + g.o_ha, n * 8, hipMemcpyDeviceToHost, st));
+  RDM_HIP(hipMemcpyAsync(hh.b.data(), base + g.o_hb, n * 8, hipMemcpyDeviceToHost, st));
+  RDM_HIP(hipMemcpyAsync(hh.s.data(), base + g.o_hs, n * 8, hipMemcpyDeviceToHost, st));
+  RDM_HIP(hipMemcpyAsync(hh.kc.data(), base + g.o_kc, g.cpad * 4, hipMemcpyDeviceToHost, st));
+  return RDM_OK;
+}
+
+// Column c of a history as contiguous alpha[0..kc-1], beta[0..kc-2].
+void column(const HostHist& hh, int cpad, int c, std::vector<double>& a, std::vector<double>& b) {
+  const int kc = hh.kc[c];
+  a.resize(kc);
+  b.resize(kc > 0 ? kc - 1 : 0);
+  for (int j = 0; j < kc; ++j) a[j] = hh.a[(size_t)j * cpad + c];
+  for (int j = 0; j + 1 < kc; ++j) b[j] = hh.b[(size_t)j * cpad + c];
+}
+
+bool all_finite(const std::vector<double>& v) {
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// phases shared by single solves, batches and the serving engine
+// ---------------------------------------------------------------------------
+rdm_status bind_ops(InstRun& r, hipStream_t st) {
+  const InstPlan& p = *r.plan;
+  rdm_status s = get_device_op(p.h, 0, p.prec, st, &r.op_t);
+  if (s != RDM_OK) return s;
+  return get_device_op(p.h, 1, p.prec, st, &r.op_b);
+}
+
+Seg seg_of(const InstRun& r, int which, int mode, double tau) {
+  const InstPlan& p = *r.plan;
+  if (which == 1)
+    return make_seg(p.bath, r.op_b, r.base, MODE_LANCZOS, START_BATH, 0, p.h->n_b, r.seed, tau);
+  Seg sg = make_seg(p.tot, r.op_t, r.base, mode, START_SYSBATH, p.ds_log, p.h->n_b, r.seed, tau);
+  if (mode == MODE_REGEN) {
+    sg.n_beta = p.n_beta;
+    sg.psi = r.base + p.o_psi;
+    sg.ytab = r.base + p.o_y;
+  }
+  return sg;
+}
+
+void seg_tiles(const Seg& sg, int seg_index, std::vector<Tile>& tiles) {
+  const int rows = kBlock * sg.rpl;
+  const int nrt = sg.n_row_tiles;
+  for (int rt = 0; rt < nrt; ++rt)
+    for (int p0 = 0; p0 < sg.P; p0 += sg.S)
+      tiles.push_back(Tile{seg_index, (uint32_t)((uint64_t)rt * rows), p0, rt});
+}
+
+rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Tile* dtiles, int ntiles, int slab,
+                       int cmax, hipStream_t st, StepTimers* tm) {
+  if (tm) RDM_HIP(tm->norm.mark(st));
+  RDM_HIP(prec == RDM_FP64 ? launch_norm<double>(dsegs, dtiles, ntiles, slab, st)
+                           : launch_norm<float>(dsegs, dtiles, ntiles, slab, st));
+  if (tm) RDM_HIP(tm->norm.mark(st));
+  RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
+  if (tm) RDM_HIP(tm->apply.mark(st));
+  RDM_HIP(prec == RDM_FP64 ? launch_apply<double>(dsegs, dtiles, ntiles, slab, st)
+                           : launch_apply<float>(dsegs, dtiles, ntiles, slab, st));
+  if (tm) RDM_HIP(tm->apply.mark(st));
+  RDM_HIP(launch_red_alpha(dsegs, nseg, cmax, st));
+  return RDM_OK;
+}
+
+namespace {
+
+template <typename T>
+rdm_status host_phase_t(InstRun& r, hipStream_t st) {
+  const InstPlan& p = *r.plan;
+  HostHist ht, hb;
+  rdm_status s;
+  if ((s = fetch_hist(p.tot, r.base, ht, st)) != RDM_OK) return s;
+  if ((s = fetch_hist(p.bath, r.base, hb, st)) != RDM_OK) return s;
+  RDM_HIP(hipStreamSynchronize(st));
+  if (!all_finite(ht.a) || !all_finite(ht.b) || !all_finite(hb.a) || !all_finite(hb.b)) {
+    set_error("non-finite Lanczos coefficients");
+    return RDM_E_NONFINITE;
+  }
+  std::vector<TridiagEig> et(p.tot.C), eb(p.bath.C);
+  parallel_for(p.tot.C + p.bath.C, [&](int t) {
+    std::vector<double> a, b;
+    if (t < p.tot.C) {
+      column(ht, p.tot.cpad, t, a, b);
+      et[t].solve(a.data(), b.data(), (int)a.size());
+    } else {
+      const int c = t - p.tot.C;
+      column(hb, p.bath.cpad, c, a, b);
+      eb[c].solve(a.data(), b.data(), (int)a.size());
+    }
+  });
+  double e0 = INFINITY, e0b = INFINITY;
+  bool ok = true;
+  for (auto& e : et) {
+    ok &= e.ok && e.n > 0;
+    for (double x : e.theta) e0 = std::min(e0, x);
+  }
+  for (auto& e : eb) {
+    ok &= e.ok && e.n > 0;
+    for (double x : e.theta) e0b = std::min(e0b, x);
+  }
+  if (!ok || !std::isfinite(e0) || !std::isfinite(e0b)) {
+    set_error("tridiagonal eigenproblem failed");
+    return RDM_E_NONFINITE;
+  }
+  r.e0 = e0;
+  r.e0b = e0b;
+  r.n_break_t = r.n_break_b = 0;
+  for (int c = 0; c < p.tot.C; ++c) r.n_break_t += ht.kc[c] < p.tot.k;
+  for (int c = 0; c < p.bath.C; ++c) r.n_break_b += hb.kc[c] < p.bath.k;
+  // weights y'_{b,j,c} = y_b[j] s_j / s_1: psi = |x| Q y and q_j = s_j u_j, |x| = 1/s_1
+  std::vector<T> yt((size_t)p.n_beta * p.k * p.tot.cpad, T(0));
+  parallel_for(p.tot.C, [&](int c) {
+    const TridiagEig& e = et[c];
+    std::vector<double> g(e.n), y(e.n);
+    const double s1 = ht.s[c];
+    for (int b = 0; b < p.n_beta; ++b) {
+      for (int q = 0; q < e.n; ++q) g[q] = std::exp(-0.5 * r.betas[b] * (e.theta[q] - e0));
+      e.apply_fn(g.data(), y.data());
+      for (int j = 0; j < e.n; ++j)
+        yt[((size_t)b * p.k + j) * p.tot.cpad + c] = (T)(y[j] * ht.s[(size_t)j * p.tot.cpad + c] / s1);
+    }
+  });
+  // bath: Gauss quadrature e_1^T exp(-b (T_b - E0b)) e_1 scaled by |v|^2 = 1/s_1^2
+  r.mb.assign(p.n_beta, 0.0);
+  for (int b = 0; b < p.n_beta; ++b) {
+    double acc = 0.0;
+    for (int c = 0; c < p.bath.C; ++c) {
+      const TridiagEig& e = eb[c];
+      const double s1 = hb.s[c];
+      double q = 0.0;
+      for (int t = 0; t < e.n; ++t) q += e.zrow[t] * e.zrow[t] * std::exp(-r.betas[b] * (e.theta[t] - e0b));
+      acc += q / (s1 * s1);
+    }
+    r.mb[b] = acc / p.n_v;
+  }
+  RDM_HIP(hipMemcpyAsync(r.base + p.o_y, yt.data(), yt.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  RDM_HIP(hipStreamSynchronize(st));
+  return RDM_OK;
+}
+
+}  // namespace
+
+rdm_status host_phase(InstRun& r, hipStream_t st) {
+  return r.plan->prec == RDM_FP64 ? host_phase_t<double>(r, st) : host_phase_t<float>(r, st);
+}
+
+rdm_status gram_phase(InstRun& r, hipStream_t st, Timers* tg) {
+  const InstPlan& p = *r.plan;
+  GSeg g{};
+  g.Q = r.base + (p.two_pass ? p.o_psi : p.tot.o_Q);
+  g.ytab = r.base + p.o_y;
+  g.gpart = (double*)(r.base + p.o_gpart);
+  g.blk = p.tot.blk;
+  g.nbits = p.tot.nbits;
+  g.cpad = p.tot.cpad;
+  g.k = p.k;
+  g.n_beta = p.n_beta;
+  g.n_v = p.n_v;
+  g.ds_log = p.ds_log;
+  g.rpl = p.g_rpl;
+  g.from_psi = p.two_pass ? 1 : 0;
+  g.n_row_tiles = p.g_rtiles;
+  std::vector<GTile> gt;
+  for (int rt = 0; rt < p.g_rtiles; ++rt)
+    for (int cb = 0; cb < p.n_cblocks; ++cb)
+      gt.push_back(GTile{0, (uint32_t)((uint64_t)rt * kBlock * p.g_rpl), cb, rt});
+  GSeg* dg = (GSeg*)(r.base + p.o_gseg);
+  GTile* dgt = (GTile*)(r.base + p.o_gtiles);
+  RDM_HIP(hipMemcpyAsync(dg, &g, sizeof(GSeg), hipMemcpyHostToDevice, st));
+  RDM_HIP(hipMemcpyAsync(dgt, gt.data(), gt.size() * sizeof(GTile), hipMemcpyHostToDevice, st));
+  for (int b0 = 0; b0 < p.n_beta; b0 += p.nb_chunk) {
+    if (tg) RDM_HIP(tg->mark(st));
+    RDM_HIP(p.prec == RDM_FP64 ? launch_gram<double>(dg, dgt, (int)gt.size(), p.ds, p.nb_chunk, b0, p.k, st)
+                               : launch_gram<float>(dg, dgt, (int)gt.size(), p.ds, p.nb_chunk, b0, p.k, st));
+    if (tg) RDM_HIP(tg->mark(st));
+  }
+  const int width = p.n_beta * p.n_v * p.ds * p.ds;
+  RDM_HIP(launch_colsum((double*)(r.base + p.o_gpart), p.g_rtiles, width, (double*)(r.base + p.o_gsum), st));
+  r.gsum.assign(width, 0.0);
+  RDM_HIP(hipMemcpyAsync(r.gsum.data(), r.base + p.o_gsum, width * 8, hipMemcpyDeviceToHost, st));
+  RDM_HIP(hipStreamSynchronize(st));
+  return RDM_OK;
+}
+
+size_t batch_header_bytes(const std::vector<InstPlan>& plans) {
+  const size_t ni = plans.size();
+  size_t nt = 0;
+  for (auto& p : plans)
+    nt += (size_t)p.tot.n_row_tiles * (p.tot.P / p.tot.S) + (size_t)p.bath.n_row_tiles * (p.bath.P / p.bath.S);
+  return al(sizeof(Seg) * 2 * ni) + al(sizeof(Tile) * std::max<size_t>(nt, 1));
+}
+
+rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, int prec, int phase,
+                     hipStream_t st, StepTimers* tm) {
+  if (hsegs.empty()) return RDM_OK;
+  std::vector<Tile> tiles;
+  int kmax = 0, cmax = 0, slab = 1;
+  for (size_t i = 0; i < hsegs.size(); ++i) {
+    seg_tiles(hsegs[i], (int)i, tiles);
+    kmax = std::max(kmax, hsegs[i].k);
+    cmax = std::max(cmax, hsegs[i].cpad);
+    slab = std::max(slab, hsegs[i].S);
+  }
+  const int nseg = (int)hsegs.size();
+  RDM_HIP(hipMemcpyAsync(dsegs, hsegs.data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
+  RDM_HIP(hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+  RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
+  for (int j = 1; j <= kmax; ++j) {
+    rdm_status s = launch_step(prec, dsegs, nseg, dtiles, (int)tiles.size(), slab, cmax, st, tm);
+    if (s != RDM_OK) return s;
+  }
+  // the host vectors above must outlive the asynchronous copies
+  RDM_HIP(hipStreamSynchronize(st));
+  return RDM_OK;
+}
+
+rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile) {
+  const int ni = (int)runs.size();
+  if (ni == 0) return RDM_OK;
+  const int prec = runs[0].plan->prec;
+  std::vector<InstPlan> plans;
+  for (auto& r : runs) plans.push_back(*r.plan);
+  const size_t header = batch_header_bytes(plans);
+  Seg* dsegs = (Seg*)ws;
+  Tile* dtiles = (Tile*)(ws + al(sizeof(Seg) * 2 * ni));
+  size_t inst_off = header;
+  for (auto& r : runs) {
+    r.base = ws + inst_off;
+    inst_off += r.plan->bytes;
+    rdm_status s = bind_ops(r, st);
+    if (s != RDM_OK) return s;
+  }
+  StepTimers tm;
+  tm.apply.on = tm.norm.on = profile;
+  // pass 1: every total and bath segment in the same launches
+  std::vector<Seg> segs;
+  for (auto& r : runs) {
+    segs.push_back(seg_of(r, 0, MODE_LANCZOS, tau));
+    segs.push_back(seg_of(r, 1, MODE_LANCZOS, tau));
+  }
+  rdm_status s = run_phase(segs, dsegs, dtiles, prec, 0, st, profile ? &tm : nullptr);
+  if (s != RDM_OK) return s;
+  for (auto& r : runs) r.status = host_phase(r, st);
+  // pass 2 (two-pass plans): regenerate u_j from the stored coefficients
+  segs.clear();
+  for (auto& r : runs)
+    if (r.plan->two_pass && r.status == RDM_OK) segs.push_back(seg_of(r, 0, MODE_REGEN, tau));
+  if ((s = run_phase(segs, dsegs, dtiles, prec, 1, st, nullptr)) != RDM_OK) return s;
+  Timers tg;
+  tg.on = profile;
+  for (auto& r : runs) {
+    if (r.status != RDM_OK) continue;
+    if ((s = gram_phase(r, st, profile ? &tg : nullptr)) != RDM_OK) return s;
+  }
+  if (profile)
+    for (auto& r : runs) {
+      r.t_apply_ms = tm.apply.avg_ms();
+      r.t_norm_ms = tm.norm.avg_ms();
+      r.t_gram_ms = tg.avg_ms();
+    }
+  return RDM_OK;
+}
+
+// A9: rho*, H*, ln Z*, S from the averaged Gram and the bath scalar.
+rdm_status finalize(const InstRun& r, rdm_result* out) {
+  const InstPlan& p = *r.plan;
+  const int ds = p.ds;
+  const double ln_db = p.h->n_b * std::log(2.0);
+  double ratio_last = 0.0;
+  std::vector<double> m(ds * ds), w(ds), v(ds * ds);
+  for (int b = 0; b < p.n_beta; ++b) {
+    std::fill(m.begin(), m.end(), 0.0);
+    for (int jv = 0; jv < p.n_v; ++jv)
+      for (int t = 0; t < ds * ds; ++t) m[t] += r.gsum[((size_t)b * p.n_v + jv) * ds * ds + t];
+    for (int t = 0; t < ds * ds; ++t) m[t] /= p.n_v;
+    for (int x = 0; x < ds; ++x)
+      for (int y = x + 1; y < ds; ++y) {
+        const double a = 0.5 * (m[x * ds + y] + m[y * ds + x]);
+        m[x * ds + y] = m[y * ds + x] = a;
+      }
+    double tr = 0.0;
+    for (int x = 0; x < ds; ++x) tr += m[x * ds + x];
+    const double beta = r.betas[b];
+    const double mb = r.mb[b];
+    if (!(tr > 0.0) || !(mb > 0.0) || !std::isfinite(tr) || !std::isfinite(mb)) {
+      set_error("non-positive or non-finite trace in finalisation");
+      return RDM_E_NONFINITE;
+    }
+    sym_eig_small(ds, m.data(), w.data(), v.data());
+    const double mu_max = w[ds - 1];
+    double mu_sum = 0.0;
+    for (int x = 0; x < ds; ++x) mu_sum += w[x];
+    const double ln_zt = std::log(tr) - beta * r.e0 + ln_db;
+    const double ln_zb = std::log(mb) - beta * r.e0b + ln_db;
+    if (out->rho)
+      for (int t = 0; t < ds * ds; ++t) out->rho[(size_t)b * ds * ds + t] = m[t] / tr;
+    if (out->h_star) {
+      std::vector<double> he(ds);
+      for (int x = 0; x < ds; ++x) {
+        const double mu = std::max(w[x], mu_max * std::ldexp(1.0, -52));
+        he[x] = -std::log(mu / mb) / beta + r.e0 - r.e0b;
+      }
+      for (int x = 0; x < ds; ++x)
+        for (int y = 0; y < ds; ++y) {
+          double acc = 0.0;
+          for (int q = 0; q < ds; ++q) acc += v[x * ds + q] * he[q] * v[y * ds + q];
+          out->h_star[(size_t)b * ds * ds + x * ds + y] = acc;
+        }
+    }
+    if (out->log_z) out->log_z[b] = ln_zt - ln_zb;
+    if (out->entropy) {
+      double sum = 0.0;
+      for (int x = 0; x < ds; ++x) {
+        const double pp = w[x] / mu_sum;
+        if (pp > 0.0) sum -= pp * std::log(pp);
+      }
+      out->entropy[b] = sum;
+    }
+    if (out->diag) {
+      out->diag[kDiagFixed + 2 * b] = ln_zt;
+      out->diag[kDiagFixed + 2 * b + 1] = ln_zb;
+    }
+    ratio_last = w[0] / mu_max;
+  }
+  if (out->diag) {
+    double* d = out->diag;
+    d[0] = r.e0;
+    d[1] = r.e0b;
+    d[2] = r.n_break_t;
+    d[3] = r.n_break_b;
+    d[4] = p.two_pass ? 1.0 : 0.0;
+    d[5] = (double)p.bytes;
+    d[6] = ratio_last;
+    d[7] = r.t_apply_ms;
+    d[8] = r.t_norm_ms;
+    d[9] = r.t_gram_ms;
+    for (int t = 10; t < kDiagFixed; ++t) d[t] = 0.0;
+  }
+  return RDM_OK;
+}
+
+rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uint64_t seed, int prec,
+                        int slab, int rpl, double tau, hipStream_t st, double* alpha, double* beta,
+                        int32_t* kc) {
+  SegPlan g;
+  size_t off = al(sizeof(Seg));
+  const size_t o_tiles = off;
+  const int nbits = which == 0 ? h->n : h->n_b;
+  const int C = which == 0 ? (1 << h->n_s) * n_v : n_v;
+  const int kk = (int)std::min<uint64_t>((uint64_t)k, 1ull << nbits);
+  // tiles first need the geometry; plan into a scratch offset, then shift
+  size_t tmp = 0;
+  plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, tmp);
+  const size_t ntiles = (size_t)g.n_row_tiles * (g.P / g.S);
+  off = al(o_tiles + ntiles * sizeof(Tile));
+  const size_t base_off = off;
+  off += tmp;
+  char* ws = nullptr;
+  RDM_HIP(hipMalloc(&ws, off));
+  const OpDevice* op = nullptr;
+  rdm_status s = get_device_op(h, which, prec, st, &op);
+  if (s != RDM_OK) {
+    (void)hipFree(ws);
+    return s;
+  }
+  std::vector<Seg> segs;
+  segs.push_back(make_seg(g, op, ws + base_off, MODE_LANCZOS, which == 0 ? START_SYSBATH : START_BATH,
+                          h->n_s, h->n_b, seed, tau));
+  s = run_phase(segs, (Seg*)ws, (Tile*)(ws + o_tiles), prec, 0, st, nullptr);
+  HostHist hh;
+  if (s == RDM_OK) s = fetch_hist(g, ws + base_off, hh, st);
+  if (s == RDM_OK && hipStreamSynchronize(st) != hipSuccess) {
+    set_error("hipStreamSynchronize failed");
+    s = RDM_E_DEVICE;
+  }
+  (void)hipFree(ws);
+  if (s != RDM_OK) return s;
+  for (int j = 0; j < k; ++j)
+    for (int c = 0; c < C; ++c) {
+      alpha[(size_t)j * C + c] = j < kk ? hh.a[(size_t)j * g.cpad + c] : 0.0;
+      beta[(size_t)j * C + c] = j < kk ? hh.b[(size_t)j * g.cpad + c] : 0.0;
+    }
+  for (int c = 0; c < C; ++c) kc[c] = hh.kc[c];
+  return RDM_OK;
+}
+
+}  // namespace rdm

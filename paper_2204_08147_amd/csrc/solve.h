@@ -1,0 +1,105 @@
+// Planning and execution of (batched) solves.
+#pragma once
+
+#include <vector>
+
+#include "host.h"
+
+namespace rdm {
+
+constexpr int kDiagFixed = 16;  // fixed entries of rdm_result.diag before the per-beta pairs
+
+// Geometry and workspace offsets of one Lanczos segment.
+struct SegPlan {
+  int nbits = 0, C = 0, cpad = 0, P = 0, S = 1, rpl = 1, n_row_tiles = 0, k = 0, nslots = 0;
+  uint64_t dim = 0, blk = 0;
+  size_t o_Q = 0, o_R = 0, o_st = 0, o_ha = 0, o_hb = 0, o_hs = 0, o_part = 0, o_step = 0, o_kc = 0;
+};
+
+struct InstPlan {
+  const rdm_hamiltonian* h = nullptr;
+  int prec = RDM_FP64, n_beta = 0, n_v = 0, k = 0, kb = 0;
+  int ds = 2, ds_log = 1, cb = 2, groups_per_block = 1, n_cblocks = 0, nb_chunk = 1;
+  int g_rpl = 1, g_rtiles = 0;
+  bool two_pass = false;
+  SegPlan tot, bath;
+  size_t o_psi = 0, o_y = 0, o_gpart = 0, o_gsum = 0, o_gseg = 0, o_gtiles = 0;
+  size_t bytes = 0;
+};
+
+// Event pairs recorded around kernel launches on the solve's stream.
+struct Timers {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  Timers() = default;
+  Timers(const Timers&) = delete;
+  Timers& operator=(const Timers&) = delete;
+  ~Timers() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  hipError_t mark(hipStream_t st) {
+    if (!on) return hipSuccess;
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ev.push_back(e);
+    return hipEventRecord(e, st);
+  }
+  // mean duration of the (start, stop) pairs in ms (after the stream synced)
+  double avg_ms() const {
+    if (!on || ev.size() < 2) return 0.0;
+    double tot = 0.0;
+    int n = 0;
+    for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
+        tot += ms;
+        ++n;
+      }
+    }
+    return n ? tot / n : 0.0;
+  }
+};
+struct StepTimers {
+  Timers apply, norm;
+};
+
+struct InstRun {
+  const InstPlan* plan = nullptr;
+  const OpDevice* op_t = nullptr;
+  const OpDevice* op_b = nullptr;
+  std::vector<double> betas;
+  uint64_t seed = 0;
+  char* base = nullptr;
+  rdm_status status = RDM_OK;
+  double e0 = 0, e0b = 0;
+  int n_break_t = 0, n_break_b = 0;
+  std::vector<double> mb, gsum;
+  double t_apply_ms = 0, t_norm_ms = 0, t_gram_ms = 0;
+};
+
+void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
+              size_t& off);
+rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
+                         int mode_req, uint64_t budget, int slab_opt, int rpl_opt);
+size_t batch_header_bytes(const std::vector<InstPlan>& plans);
+rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile);
+
+// Phases (used by execute and by the serving engine).
+rdm_status bind_ops(InstRun& r, hipStream_t st);
+Seg seg_of(const InstRun& r, int which, int mode, double tau);
+void seg_tiles(const Seg& sg, int seg_index, std::vector<Tile>& tiles);
+rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Tile* dtiles, int ntiles, int slab,
+                       int cmax, hipStream_t st, StepTimers* tm);
+rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, int prec, int phase,
+                     hipStream_t st, StepTimers* tm);
+rdm_status host_phase(InstRun& r, hipStream_t st);   // synchronous
+rdm_status gram_phase(InstRun& r, hipStream_t st, Timers* tg);  // synchronous
+rdm_status finalize(const InstRun& r, rdm_result* out);
+
+// Lanczos coefficients only (rdm_lanczos).
+rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uint64_t seed, int prec,
+                        int slab, int rpl, double tau, hipStream_t st, double* alpha, double* beta,
+                        int32_t* kc);
+
+}  // namespace rdm
