@@ -1,0 +1,230 @@
+"""Benchmark: reduced-density-matrix solves per second on one MI355X.
+
+Workload (the metric's configuration): 2 system + 18 bath spins (dim 2^20),
+long-range XX+ZZ couplings J_ij = |i-j|^-1.5, transverse x-field
+h in {0.5, 1.0, 1.5}, beta in {0.5, 1, 2, 4} from one Lanczos run per h,
+n_v = 16 Rademacher bath vectors (64 start columns), k = 60 Lanczos steps.
+One step = the whole hot path for the three fields (three solves, four
+temperatures each), mixed precision (FP32 vectors, FP64 reductions); the FP64
+plain path is timed the same way and reported beside it.
+
+Prints one JSON line.  ``value`` = mixed-precision solves per second with the
+Hamiltonian tables and workspaces resident on the device.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 and FP64 vector FMA issue at the same rate on gfx950:
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.  (The 157.3
+# TFLOP/s FP32 figure needs packed FP32 FMA, which this build does not emit.)
+VALU_PEAK_TFLOPS = 78.6
+
+METRIC = ("ρ_s solves/s & spin-H apply GB/s, mixed vs FP64 plain; p50/p99 solve latency")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-b", type=int, default=18, help="bath spins (18 = the metric's workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
+    return ap.parse_args()
+
+
+def nnz_per_row(info_tot):
+    """Average non-zeros per row of H: the diagonal, every uniform hop, and the
+    parity hops weighted by how often their coefficient is non-zero (1/2 for
+    XXZ pairs with J^x = J^y)."""
+    return 1 + info_tot["hops_uniform"] + info_tot["hops_parity_nonzero"]
+
+
+def kernel_source_hash():
+    src = open(os.path.join(ROOT, "paper_2204_08147_amd", "csrc", "kernels.hip"), "rb").read()
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def read_traffic(name):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary, or
+    None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(inst, budget_s=20.0):
+    """The oracle's FP64 Lanczos path (as it stands) on a bounded sample: a few
+    Lanczos steps of one start column, scaled to a full solve (every column,
+    k steps, plus the bath run)."""
+    from oracle import exact, lanczos as olz, spin
+    op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    x0 = exact.start_columns(inst)[:, 0]
+    t0 = time.perf_counter()
+    olz.lanczos(op.apply, x0, 1, keep_q=False)
+    t = time.perf_counter() - t0
+    steps = 1
+    if t < budget_s / 4:
+        steps = max(2, min(inst.k, int(budget_s / max(t, 1e-3))))
+        t0 = time.perf_counter()
+        olz.lanczos(op.apply, x0, steps, keep_q=False)
+        t = time.perf_counter() - t0
+    per_step_col = t / steps
+    cols = inst.n_cols + inst.n_v * (inst.d_b / inst.dim)  # bath columns are 1/d_s the size
+    t_solve = per_step_col * inst.k * cols
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 Lanczos steps of 1 of {inst.n_cols} start columns "
+                      f"(dim 2^{inst.n}), {t:.1f} s, scaled x{inst.k / steps:.0f} steps "
+                      f"x{cols:.2f} columns (NumPy, single-threaded element-wise kernels)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the path would shard bath-vector groups across GPUs, see the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2204_08147_amd as rdm
+    from workloads import LR_FIELDS, cfg_long_range
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: reads 1 GiB, writes 1 GiB
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    insts = [cfg_long_range(i, n_b=args.n_b) for i in range(len(LR_FIELDS))]
+    hs = [rdm.Hamiltonian.from_instance(i) for i in insts]
+    inst0 = insts[0]
+    stream = torch.cuda.current_stream()
+
+    def make_ws(prec):
+        return [torch.empty(rdm.workspace_size(h, len(i.betas), i.n_v, i.k, precision=prec, mode="stored"),
+                            dtype=torch.uint8, device="cuda") for h, i in zip(hs, insts)]
+
+    def run(prec, steps, warmup, ws, profile):
+        lat, apply_ms, norm_ms, gram_ms, res = [], [], [], [], None
+        for s in range(warmup + steps):
+            if s == warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            for h, i, w in zip(hs, insts, ws):
+                t1 = time.perf_counter()
+                res = rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision=prec, mode="stored",
+                                workspace=w, stream=stream, profile=profile and s >= warmup)
+                if s >= warmup:
+                    lat.append(time.perf_counter() - t1)
+                    if profile:
+                        apply_ms.append(res["t_apply_ms"])
+                        norm_ms.append(res["t_norm_ms"])
+                        gram_ms.append(res["t_gram_ms"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, lat, apply_ms, norm_ms, gram_ms, res
+
+    ws_m = make_ws("mixed")
+    wall_m, lat_m, ap_m, no_m, gr_m, res_m = run("mixed", args.steps, args.warmup, ws_m, True)
+    del ws_m
+    torch.cuda.empty_cache()
+    fp64 = None
+    if not args.no_fp64:
+        ws_d = make_ws("fp64")
+        wall_d, lat_d, ap_d, no_d, gr_d, res_d = run("fp64", max(1, args.steps // 2), args.warmup, ws_d, True)
+        del ws_d
+        torch.cuda.empty_cache()
+        n_d = len(lat_d)
+        fp64 = {"solves_per_s": n_d / wall_d, "p50_ms": 1e3 * float(np.percentile(lat_d, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat_d, 99)),
+                "apply_kernel_ms": float(np.mean(ap_d))}
+
+    n_solves = len(lat_m)
+    value = n_solves / wall_m
+    ms_per_step = 1e3 * wall_m / args.steps
+
+    # roofline of the dominant kernel: the apply launch (H_t and H_b segments)
+    info = hs[0].info()
+    info["hops_parity_nonzero"] = info["hops_parity"] * 0.5
+    nnz = nnz_per_row(info)
+    infob = {"hops_uniform": info["bath_hops_uniform"],
+             "hops_parity_nonzero": info["bath_hops_parity"] * 0.5}
+    nnz_b = nnz_per_row(infob)
+    dim, db, C, nv, k = inst0.dim, inst0.d_b, inst0.n_cols, inst0.n_v, inst0.k
+    s32 = 4
+    # per launch (average over the k steps): read u_j, read u_{j-1} (absent at
+    # j = 1), write r, read the diagonal
+    prev_frac = (k - 1) / k
+    bytes_tot = dim * C * s32 * (2 + prev_frac) + dim * s32
+    bytes_bath = db * nv * s32 * (2 + prev_frac) + db * s32
+    flops = 2.0 * nnz * dim * C + 2.0 * nnz_b * db * nv
+    t_apply = float(np.mean(ap_m)) * 1e-3
+    achieved_tflops = flops / t_apply / 1e12
+    achieved_gbs = (bytes_tot + bytes_bath) / t_apply / 1e9
+    t_hbm = (bytes_tot + bytes_bath) / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (VALU_PEAK_TFLOPS * 1e12)
+    traffic = read_traffic("apply_lr_xxzz_2+18_mixed_counters.txt")
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / VALU_PEAK_TFLOPS, 4),
+                "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inst0)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 vectors + f64 reductions", "data": "synthetic",
+        "config": {"workload": f"long-range XX+ZZ, N_s=2 + N_b={args.n_b} (dim 2^{2 + args.n_b}), "
+                               "J_ij=|i-j|^-1.5, x-field h in {0.5,1.0,1.5}, beta in {0.5,1,2,4}, "
+                               "n_v=16 Rademacher, k=60; one step = the three fields",
+                   "solves_per_step": len(insts), "n_columns": C, "nnz_per_row": nnz},
+        "p50_ms": round(1e3 * float(np.percentile(lat_m, 50)), 3),
+        "p99_ms": round(1e3 * float(np.percentile(lat_m, 99)), 3),
+        "apply_gbs_algorithmic": round(achieved_gbs, 1),
+        "apply_kernel_ms": round(1e3 * t_apply, 4),
+        "norm_kernel_ms": round(float(np.mean(no_m)), 4),
+        "gram_kernel_ms": round(float(np.mean(gr_m)), 4),
+        "fp64": None if fp64 is None else {k2: round(v, 4) for k2, v in fp64.items()},
+        "mixed_over_fp64": None if fp64 is None else round(value / fp64["solves_per_s"], 3),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -123,6 +123,7 @@ class SparseSpinOperator:
                 self.terms.append(("x", s, "", -1, float(hx[s])))
             if hz[s] != 0.0:
                 self.terms.append(("z", s, "", -1, float(hz[s])))
+        self._cache = None
 
     @property
     def dim(self) -> int:
@@ -152,8 +153,11 @@ class SparseSpinOperator:
         p = np.arange(self.dim, dtype=np.int64)
         y = np.zeros_like(x)
         shape = (-1,) + (1,) * (x.ndim - 1)
-        for t in self.terms:
-            out, ph = self._action(t, p)
+        if self._cache is None and self.dim <= (1 << 16):
+            # small spaces: keep each term's (image, phase) table between calls
+            self._cache = [self._action(t, p) for t in self.terms]
+        for i, t in enumerate(self.terms):
+            out, ph = self._cache[i] if self._cache is not None else self._action(t, p)
             # every term is an involution on basis states, so ``out`` is a
             # permutation and an indexed add has no repeated targets
             y[out] += ph.reshape(shape) * x

@@ -84,6 +84,11 @@ SIGNATURES = [
 
 
 def load(path: str = LIB_PATH):
+    # torch bundles its own HIP runtime (same SONAME as /opt/rocm's).  Loading
+    # torch first makes librdm.so bind to that one copy, so device memory and
+    # streams handed over from torch belong to the runtime that launches the
+    # kernels; loading librdm.so first would put two HIP runtimes in the process.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2204_08147_amd.build` "
                           "(there is no fallback implementation)")

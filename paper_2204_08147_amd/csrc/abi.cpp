@@ -241,6 +241,7 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   sg.diag = op->diag;
   sg.nU = op->nU;
   sg.nP = op->nP;
+  sg.nPh = op->nPh;
   sg.nbits = nbits;
   sg.P = g.P;
   sg.S = g.S;

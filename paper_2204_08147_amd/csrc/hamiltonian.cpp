@@ -1,5 +1,6 @@
 // Hamiltonian construction: validation and compilation of eqn:Ht into the
 // apply kernel's term tables.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <utility>
@@ -62,6 +63,22 @@ void compile(const rdm_hamiltonian& h, int first_site, OpTables& t) {
       t.uc.push_back(h.hx[s]);
     }
   }
+  // parity hops whose tested bits are all >= 6 first: within a wave of 64
+  // consecutive rows their coefficient is uniform
+  std::vector<size_t> order(t.pf.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return ((t.pm[a] & 63u) == 0u) > ((t.pm[b] & 63u) == 0u);
+  });
+  OpTables s2 = t;
+  for (size_t i = 0; i < order.size(); ++i) {
+    t.pf[i] = s2.pf[order[i]];
+    t.pm[i] = s2.pm[order[i]];
+    t.pcs[i] = s2.pcs[order[i]];
+    t.pcd[i] = s2.pcd[order[i]];
+  }
+  t.nPh = 0;
+  for (size_t i = 0; i < t.pm.size(); ++i) t.nPh += (t.pm[i] & 63u) == 0u;
 }
 
 template <typename T>
@@ -86,6 +103,7 @@ rdm_status upload(const OpTables& t, OpDevice& d, hipStream_t st) {
   RDM_HIP(hipStreamSynchronize(st));
   d.nU = (int)hu.size();
   d.nP = (int)hp.size();
+  d.nPh = t.nPh;
   d.ready = true;
   return RDM_OK;
 }

@@ -30,6 +30,7 @@ struct OpTables {
   std::vector<double> uc;
   std::vector<uint32_t> pf, pm;  // parity-dependent hops
   std::vector<double> pcs, pcd;
+  int nPh = 0;  // leading parity hops with both tested bits >= 6
 };
 
 // Device copy of an operator's tables in one precision.
@@ -40,7 +41,7 @@ struct OpDevice {
   void* hopP = nullptr;
   void* diag = nullptr;
   void* dterms = nullptr;
-  int nU = 0, nP = 0;
+  int nU = 0, nP = 0, nPh = 0;
 };
 
 }  // namespace rdm

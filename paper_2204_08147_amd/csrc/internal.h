@@ -56,6 +56,7 @@ struct Seg {
   const void* hopP;
   const void* diag;
   int32_t nU, nP;
+  int32_t nPh;         // leading parity hops whose tested bits are all >= 6
   int32_t nbits;       // log2(dim)
   int32_t P;           // panels
   int32_t S;           // panels per lane in apply/norm
@@ -84,7 +85,7 @@ struct Seg {
   int32_t* stepc;      // [cpad] current step (1-based) per column
   int32_t* kc;         // [cpad] Krylov size after breakdown truncation
   double tau;
-  int32_t pad0, pad1;
+  int32_t pad0;
 };
 
 // Work item of the apply / norm kernels.

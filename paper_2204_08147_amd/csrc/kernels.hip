@@ -65,15 +65,30 @@ __device__ __forceinline__ T start_value(int kind, int ns_log, int nb, uint64_t 
   return bath_bit(seed, j, b) ? -amp : amp;
 }
 
-// 16-byte panel access with a uniform base and a 32-bit row offset, so the
-// compiler can use global loads with an SGPR base and a VGPR offset.
+#define GLOBAL_AS __attribute__((address_space(1)))
+#define CONST_AS __attribute__((address_space(4)))
+
+// 16-byte panel access in the global address space with a uniform base and a
+// 32-bit row offset, so the compiler emits global loads/stores with an SGPR
+// base and a VGPR offset.
 template <typename V>
-__device__ __forceinline__ V ldp(const V* base, uint32_t row) {
-  return *(const V*)((const char*)base + (uint32_t)(row << 4));
+__device__ __forceinline__ V ldg(const V* base, uint32_t row) {
+  return *(const GLOBAL_AS V*)((const GLOBAL_AS char*)base + (uint32_t)(row << 4));
 }
 template <typename V>
-__device__ __forceinline__ void stp(V* base, uint32_t row, V v) {
-  *(V*)((char*)base + (uint32_t)(row << 4)) = v;
+__device__ __forceinline__ void stg(V* base, uint32_t row, V v) {
+  *(GLOBAL_AS V*)((GLOBAL_AS char*)base + (uint32_t)(row << 4)) = v;
+}
+template <typename T>
+__device__ __forceinline__ T ldg_s(const T* base, uint32_t row) {
+  return ((const GLOBAL_AS T*)base)[row];
+}
+
+// Segment descriptors are read-only during a kernel: read them through the
+// constant address space so uniform fields come in with scalar loads.
+typedef Seg CSeg;
+__device__ __forceinline__ const CONST_AS CSeg& cseg(const Seg* segs, int i) {
+  return ((const CONST_AS CSeg*)segs)[i];
 }
 
 __device__ __forceinline__ float fma_s(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -104,7 +119,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* 
 }
 
 template <typename T>
-__device__ __forceinline__ T* slot_ptr(const Seg& sg, int j) {
+__device__ __forceinline__ T* slot_ptr(const CONST_AS Seg& sg, int j) {
   const int idx = sg.ring ? ((j - 1) & 1) : (j - 1);
   return (T*)sg.Q + (uint64_t)idx * sg.blk;
 }
@@ -142,196 +157,253 @@ __global__ void k_init_state(const Seg* __restrict__ segs, int phase) {
 // ---------------------------------------------------------------------------
 // norm kernel: u_j = r - (alpha_{j-1} s_{j-1}) u_{j-1}  (j >= 2) or the start
 // block (j = 1); partial sums of |u_j|^2; in the regeneration pass also
-// psi_b = fma(y_{b,j}, u_j, psi_b).
+// psi_b = fma(y_{b,j}, u_j, psi_b).  S = panels per lane (exact).
 // ---------------------------------------------------------------------------
-template <typename T, int SM>
+template <typename T, int S>
 __global__ __launch_bounds__(kBlock) void k_norm(const Seg* __restrict__ segs,
                                                  const Tile* __restrict__ tiles) {
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
-  __shared__ double lds[4 * SM * W];
+  __shared__ double lds[4 * S * W];
   const Tile t = tiles[blockIdx.x];
-  const Seg& sg = segs[t.seg];
+  const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const int j = sg.stepc[0];
   if (j > sg.k) return;
-  const int S = sg.S, cp = sg.cpad;
+  const int cp = sg.cpad;
   const uint32_t dim = 1u << sg.nbits;
-  const uint64_t pstride = (uint64_t)dim;   // panel stride in V units
+  const uint64_t pstride = (uint64_t)dim;
 
-  V* ucur = (V*)slot_ptr<T>(sg, j);
-  const V* uprev = (j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) : nullptr;
-  const V* rv = (const V*)sg.R;
+  V* ucur = (V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
+  const V* uprev = (j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride : nullptr;
+  const V* rv = (const V*)sg.R + (uint64_t)t.panel0 * pstride;
   const bool regen = sg.mode == MODE_REGEN;
   const T amp = amp_of<T>(sg.nb);
+  const CONST_AS double* st = (const CONST_AS double*)sg.st;
 
-  V acur[SM];
+  V acur[S];
 #pragma unroll
-  for (int s = 0; s < SM; ++s)
+  for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int e = 0; e < W; ++e) {
-      const int c = (t.panel0 + s) * W + e;
-      acur[s][e] = (s < S) ? (T)sg.st[ST_ACUR * cp + c] : T(0);
-    }
+    for (int e = 0; e < W; ++e) acur[s][e] = (T)st[ST_ACUR * cp + (t.panel0 + s) * W + e];
 
-  double dsum[SM * W];
+  double dsum[S * W];
 #pragma unroll
-  for (int i = 0; i < SM * W; ++i) dsum[i] = 0.0;
+  for (int i = 0; i < S * W; ++i) dsum[i] = 0.0;
 
   for (int rr = 0; rr < sg.rpl; ++rr) {
     const uint32_t row = t.row0 + rr * kBlock + threadIdx.x;
     if (row >= dim) break;
+    V u[S];
+    if (j == 1) {
 #pragma unroll
-    for (int s = 0; s < SM; ++s) {
-      if (s >= S) break;
-      const int panel = t.panel0 + s;
-      V u;
-      if (j == 1) {
+      for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int e = 0; e < W; ++e)
-          u[e] = start_value<T>(sg.start_kind, sg.ns_log, sg.nb, sg.seed, row, panel * W + e, sg.C, amp);
-      } else {
-        const V r = ldp(rv + panel * pstride, row);
-        const V up = ldp(uprev + panel * pstride, row);
+          u[s][e] = start_value<T>(sg.start_kind, sg.ns_log, sg.nb, sg.seed, row, (t.panel0 + s) * W + e,
+                                   sg.C, amp);
+    } else {
+      V r[S], up[S];
 #pragma unroll
-        for (int e = 0; e < W; ++e) u[e] = fma_s(-acur[s][e], up[e], r[e]);
+      for (int s = 0; s < S; ++s) {
+        r[s] = ldg(rv + s * pstride, row);
+        up[s] = ldg(uprev + s * pstride, row);
       }
-      stp(ucur + panel * pstride, row, u);
 #pragma unroll
-      for (int e = 0; e < W; ++e) dsum[s * W + e] += (double)u[e] * (double)u[e];
-      if (regen) {
-        const T* yt = (const T*)sg.ytab;
-        for (int b = 0; b < sg.n_beta; ++b) {
-          V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + panel * pstride;
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int e = 0; e < W; ++e) u[s][e] = fma_s(-acur[s][e], up[s][e], r[s][e]);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      stg(ucur + s * pstride, row, u[s]);
+#pragma unroll
+      for (int e = 0; e < W; ++e) dsum[s * W + e] += (double)u[s][e] * (double)u[s][e];
+    }
+    if (regen) {
+      const CONST_AS T* yt = (const CONST_AS T*)sg.ytab;
+      for (int b = 0; b < sg.n_beta; ++b) {
+        V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + (uint64_t)t.panel0 * pstride;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
           V old;
           if (j == 1) {
 #pragma unroll
             for (int e = 0; e < W; ++e) old[e] = T(0);
           } else {
-            old = ldp(pb, row);
+            old = ldg(pb + s * pstride, row);
           }
           V nw;
 #pragma unroll
           for (int e = 0; e < W; ++e) {
-            const T y = yt[((uint64_t)b * sg.k + (j - 1)) * cp + panel * W + e];
-            nw[e] = fma_s(y, u[e], old[e]);
+            const T y = yt[((uint64_t)b * sg.k + (j - 1)) * cp + (t.panel0 + s) * W + e];
+            nw[e] = fma_s(y, u[s][e], old[e]);
           }
-          stp(pb, row, nw);
+          stg(pb + s * pstride, row, nw);
         }
       }
     }
   }
   double tot;
-  block_sum<SM * W>(dsum, lds, &tot);
+  block_sum<S * W>(dsum, lds, &tot);
   if (threadIdx.x < S * W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
 }
 
 // ---------------------------------------------------------------------------
 // apply kernel: r = s_j (H u_j) - (beta_{j-1} s_{j-1}) u_{j-1}, partial sums of
 // <u_j, r>.  MODE_PLAIN: Y = H X with X = Q, Y = R.
+//
+// One lane per basis row, S 16-byte panels (S*W columns) per lane.  The hop
+// tables are read with scalar loads (every lane of a wave walks the same
+// list); each hop gathers the partner row idx ^ f of every panel with one
+// coalesced 16-byte load per lane.  Hops are processed U at a time so U*S
+// gathers are in flight before the FMAs that consume them.
 // ---------------------------------------------------------------------------
-template <typename T, int SM>
+template <typename T, int S, int U>
+__device__ __forceinline__ void hops_uniform(const CONST_AS HopU<T>* hu, int n, uint32_t row,
+                                             const typename PanelT<T>::V* __restrict__ ub,
+                                             uint64_t pstride, typename PanelT<T>::V (&acc)[S]) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  int h = 0;
+  for (; h + U <= n; h += U) {
+    V x[U][S];
+    T c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t p = row ^ hu[h + u].f;
+      c[u] = hu[h + u].c;
+#pragma unroll
+      for (int s = 0; s < S; ++s) x[u][s] = ldg(ub + s * pstride, p);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] += c[u] * x[u][s];
+    // issue every gather of the group before the FMAs that consume them
+    __builtin_amdgcn_sched_group_barrier(0x0020, U * S, 0);
+    __builtin_amdgcn_sched_group_barrier(0x0002, U * S * W, 0);
+  }
+  for (; h < n; ++h) {
+    const uint32_t p = row ^ hu[h].f;
+    const T c = hu[h].c;
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
+  }
+}
+
+template <typename T, int S>
 __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs,
                                                   const Tile* __restrict__ tiles) {
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
-  __shared__ double lds[4 * SM * W];
+  constexpr int U = S >= 4 ? 4 : (S == 2 ? 8 : 8);
+  __shared__ double lds[4 * S * W];
   const Tile t = tiles[blockIdx.x];
-  const Seg& sg = segs[t.seg];
+  const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const bool plain = sg.mode == MODE_PLAIN;
   int j = 1;
   if (!plain) {
     j = sg.stepc[0];
     if (j > sg.k) return;
   }
-  const int S = sg.S, cp = sg.cpad;
+  const int cp = sg.cpad;
   const uint32_t dim = 1u << sg.nbits;
   const uint64_t pstride = (uint64_t)dim;
-  const V* ucur = plain ? (const V*)sg.Q : (const V*)slot_ptr<T>(sg, j);
-  const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) : nullptr;
-  V* out = (V*)sg.R;
-  const HopU<T>* __restrict__ hu = (const HopU<T>*)sg.hopU;
-  const HopP<T>* __restrict__ hp = (const HopP<T>*)sg.hopP;
-  const T* __restrict__ dg = (const T*)sg.diag;
-  const int nU = sg.nU, nP = sg.nP;
+  const V* ub = (plain ? (const V*)sg.Q : (const V*)slot_ptr<T>(sg, j)) + (uint64_t)t.panel0 * pstride;
+  const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride
+                                     : nullptr;
+  V* out = (V*)sg.R + (uint64_t)t.panel0 * pstride;
+  const CONST_AS HopU<T>* hu = (const CONST_AS HopU<T>*)sg.hopU;
+  const CONST_AS HopP<T>* hp = (const CONST_AS HopP<T>*)sg.hopP;
+  const T* dg = (const T*)sg.diag;
+  const int nU = sg.nU, nP = sg.nP, nPh = sg.nPh;
   const bool dots = sg.mode == MODE_LANCZOS;
+  const CONST_AS double* st = (const CONST_AS double*)sg.st;
 
-  V scur[SM], bps[SM];
+  V scur[S], bps[S];
 #pragma unroll
-  for (int s = 0; s < SM; ++s)
+  for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int e = 0; e < W; ++e) {
       const int c = (t.panel0 + s) * W + e;
-      scur[s][e] = plain ? T(1) : ((s < S) ? (T)sg.st[ST_SCUR * cp + c] : T(0));
-      bps[s][e] = plain ? T(0) : ((s < S) ? (T)sg.st[ST_BPS * cp + c] : T(0));
+      scur[s][e] = plain ? T(1) : (T)st[ST_SCUR * cp + c];
+      bps[s][e] = plain ? T(0) : (T)st[ST_BPS * cp + c];
     }
 
-  const V* ub[SM];
+  double dq[S * W];
 #pragma unroll
-  for (int s = 0; s < SM; ++s) ub[s] = ucur + (uint64_t)(t.panel0 + (s < S ? s : 0)) * pstride;
-
-  double dq[SM * W];
-#pragma unroll
-  for (int i = 0; i < SM * W; ++i) dq[i] = 0.0;
+  for (int i = 0; i < S * W; ++i) dq[i] = 0.0;
 
   for (int rr = 0; rr < sg.rpl; ++rr) {
     const uint32_t row = t.row0 + rr * kBlock + threadIdx.x;
     const uint32_t wbase = __builtin_amdgcn_readfirstlane(row & ~63u);
     if (wbase >= dim) break;
     if (row < dim) {
-      const T d = dg[row];
-      V acc[SM], xc[SM];
+      const T d = ldg_s(dg, row);
+      V acc[S], xc[S];
 #pragma unroll
-      for (int s = 0; s < SM; ++s) {
-        if (s < S) {
-          xc[s] = ldp(ub[s], row);
-          acc[s] = d * xc[s];
+      for (int s = 0; s < S; ++s) {
+        xc[s] = ldg(ub + s * pstride, row);
+        acc[s] = d * xc[s];
+      }
+      hops_uniform<T, S, U>(hu, nU, row, ub, pstride, acc);
+      // parity hops whose two tested bits lie above the wave's 64 rows: the
+      // coefficient is the same for the whole wave, and zero ones are skipped
+      for (int h = 0; h < nPh; ++h) {
+        const uint32_t m = hp[h].m;
+        const T c = (__builtin_popcount(wbase & m) & 1u) ? hp[h].cd : hp[h].cs;
+        if (c == T(0)) continue;
+        const uint32_t p = row ^ hp[h].f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
+      }
+      // remaining parity hops: per-row coefficient
+      int h = nPh;
+      for (; h + 2 <= nP; h += 2) {
+        V x0[S], x1[S];
+        const uint32_t p0 = row ^ hp[h].f, p1 = row ^ hp[h + 1].f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          x0[s] = ldg(ub + s * pstride, p0);
+          x1[s] = ldg(ub + s * pstride, p1);
+        }
+        const T c0 = (__builtin_popcount(row & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
+        const T c1 = (__builtin_popcount(row & hp[h + 1].m) & 1u) ? hp[h + 1].cd : hp[h + 1].cs;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          acc[s] += c0 * x0[s];
+          acc[s] += c1 * x1[s];
         }
       }
-      for (int h = 0; h < nU; ++h) {
-        const uint32_t p = row ^ hu[h].f;
-        const T c = hu[h].c;
+      for (; h < nP; ++h) {
+        const uint32_t p = row ^ hp[h].f;
+        const T c = (__builtin_popcount(row & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
 #pragma unroll
-        for (int s = 0; s < SM; ++s)
-          if (s < S) acc[s] += c * ldp(ub[s], p);
+        for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
       }
-      for (int h = 0; h < nP; ++h) {
-        const uint32_t f = hp[h].f, m = hp[h].m;
-        const T cs = hp[h].cs, cd = hp[h].cd;
-        const uint32_t p = row ^ f;
-        T c;
-        if ((m & 63u) == 0u) {
-          // both tested bits are above the 64 rows of this wave: uniform
-          c = (__builtin_popcount(wbase & m) & 1u) ? cd : cs;
-          if (c == T(0)) continue;
-        } else {
-          c = (__builtin_popcount(row & m) & 1u) ? cd : cs;
+      V up[S];
+      if (uprev) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) up[s] = ldg(uprev + s * pstride, row);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        V r = scur[s] * acc[s];
+        if (uprev) {
+#pragma unroll
+          for (int e = 0; e < W; ++e) r[e] = fma_s(-bps[s][e], up[s][e], r[e]);
         }
+        stg(out + s * pstride, row, r);
+        if (dots) {
 #pragma unroll
-        for (int s = 0; s < SM; ++s)
-          if (s < S) acc[s] += c * ldp(ub[s], p);
-      }
-#pragma unroll
-      for (int s = 0; s < SM; ++s) {
-        if (s < S) {
-          const uint64_t po = (uint64_t)(t.panel0 + s) * pstride;
-          V r = scur[s] * acc[s];
-          if (uprev) {
-            const V up = ldp(uprev + po, row);
-#pragma unroll
-            for (int e = 0; e < W; ++e) r[e] = fma_s(-bps[s][e], up[e], r[e]);
-          }
-          stp(out + po, row, r);
-          if (dots) {
-#pragma unroll
-            for (int e = 0; e < W; ++e) dq[s * W + e] += (double)xc[s][e] * (double)r[e];
-          }
+          for (int e = 0; e < W; ++e) dq[s * W + e] += (double)xc[s][e] * (double)r[e];
         }
       }
     }
   }
   if (!dots) return;
   double tot;
-  block_sum<SM * W>(dq, lds, &tot);
+  block_sum<S * W>(dq, lds, &tot);
   if (threadIdx.x < S * W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
 }
 
@@ -468,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
           if (b < nb) {
             const V* pb = (const V*)g.Q + (uint64_t)(beta0 + b) * (g.blk / W) +
                           (uint64_t)(t.cblock * NPAN + q) * pstride;
-            psi[b][q] = ldp(pb, row);
+            psi[b][q] = ldg(pb, row);
           } else {
 #pragma unroll
             for (int e = 0; e < W; ++e) psi[b][q][e] = T(0);
@@ -485,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
         const V* sb = (const V*)g.Q + (uint64_t)jj * (g.blk / W);
         V qv[NPAN];
 #pragma unroll
-        for (int q = 0; q < NPAN; ++q) qv[q] = ldp(sb + (uint64_t)(t.cblock * NPAN + q) * pstride, row);
+        for (int q = 0; q < NPAN; ++q) qv[q] = ldg(sb + (uint64_t)(t.cblock * NPAN + q) * pstride, row);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -558,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_start_block(int ns_log, int nb, int 
   V u;
 #pragma unroll
   for (int e = 0; e < W; ++e) u[e] = start_value<T>(kind, ns_log, nb, seed, row, panel * W + e, C, amp);
-  stp((V*)out + (uint64_t)panel * dim, row, u);
+  stg((V*)out + (uint64_t)panel * dim, row, u);
 }
 
 // ---------------------------------------------------------------------------

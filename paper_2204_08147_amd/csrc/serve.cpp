@@ -192,7 +192,7 @@ void rdm_server::run() {
     segs.clear();
     tiles.clear();
     std::vector<std::pair<int, int>> init_ranges;  // (first seg, phase) of segments to initialise
-    int cmax = 0, slab = 1;
+    int cmax = 0;
     for (Req* r : active) {
       const int first = (int)segs.size();
       if (r->phase == 0) {
@@ -206,10 +206,10 @@ void rdm_server::run() {
         r->need_init = false;
       }
     }
+    const int slab = common_slab(segs);
     for (size_t i = 0; i < segs.size(); ++i) {
       seg_tiles(segs[i], (int)i, tiles);
       cmax = std::max(cmax, segs[i].cpad);
-      slab = std::max(slab, segs[i].S);
     }
     rdm_status s = ensure_tables(segs.size(), tiles.size());
     if (s == RDM_OK && hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg),

@@ -163,6 +163,7 @@ Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int sta
   s.diag = op->diag;
   s.nU = op->nU;
   s.nP = op->nP;
+  s.nPh = op->nPh;
   s.nbits = g.nbits;
   s.P = g.P;
   s.S = g.S;
@@ -252,11 +253,23 @@ Seg seg_of(const InstRun& r, int which, int mode, double tau) {
   return sg;
 }
 
+int common_slab(std::vector<Seg>& segs) {
+  // one launch uses one panel count per lane; every segment's own choice is a
+  // power of two dividing its panel count, so the smallest one divides all.
+  // Results do not depend on it (it only splits columns across lanes).
+  int slab = kMaxSlab;
+  for (auto& sg : segs) slab = std::min(slab, sg.S);
+  for (auto& sg : segs) sg.S = slab;
+  return slab;
+}
+
 void seg_tiles(const Seg& sg, int seg_index, std::vector<Tile>& tiles) {
+  // slab-major: the blocks in flight share one group of panels, so the
+  // gathered vector's working set is one slab (dim * S * 16 bytes)
   const int rows = kBlock * sg.rpl;
   const int nrt = sg.n_row_tiles;
-  for (int rt = 0; rt < nrt; ++rt)
-    for (int p0 = 0; p0 < sg.P; p0 += sg.S)
+  for (int p0 = 0; p0 < sg.P; p0 += sg.S)
+    for (int rt = 0; rt < nrt; ++rt)
       tiles.push_back(Tile{seg_index, (uint32_t)((uint64_t)rt * rows), p0, rt});
 }
 
@@ -395,24 +408,35 @@ rdm_status gram_phase(InstRun& r, hipStream_t st, Timers* tg) {
   return RDM_OK;
 }
 
-size_t batch_header_bytes(const std::vector<InstPlan>& plans) {
-  const size_t ni = plans.size();
+// Tiles of a segment when a launch lowers its slab to one panel per lane (the
+// most a shared launch can ever create for it).
+size_t max_tiles(const SegPlan& g) { return (size_t)g.n_row_tiles * g.P; }
+
+size_t batch_tile_capacity(const std::vector<InstPlan>& plans) {
   size_t nt = 0;
-  for (auto& p : plans)
-    nt += (size_t)p.tot.n_row_tiles * (p.tot.P / p.tot.S) + (size_t)p.bath.n_row_tiles * (p.bath.P / p.bath.S);
-  return al(sizeof(Seg) * 2 * ni) + al(sizeof(Tile) * std::max<size_t>(nt, 1));
+  for (auto& p : plans) nt += max_tiles(p.tot) + max_tiles(p.bath);
+  return std::max<size_t>(nt, 1);
 }
 
-rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, int prec, int phase,
-                     hipStream_t st, StepTimers* tm) {
+size_t batch_header_bytes(const std::vector<InstPlan>& plans) {
+  return al(sizeof(Seg) * 2 * plans.size()) + al(sizeof(Tile) * batch_tile_capacity(plans));
+}
+
+rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, size_t tile_cap, int prec,
+                     int phase, hipStream_t st, StepTimers* tm) {
   if (hsegs.empty()) return RDM_OK;
   std::vector<Tile> tiles;
-  int kmax = 0, cmax = 0, slab = 1;
+  int kmax = 0, cmax = 0;
+  const int slab = common_slab(hsegs);
   for (size_t i = 0; i < hsegs.size(); ++i) {
     seg_tiles(hsegs[i], (int)i, tiles);
     kmax = std::max(kmax, hsegs[i].k);
     cmax = std::max(cmax, hsegs[i].cpad);
-    slab = std::max(slab, hsegs[i].S);
+  }
+  if (tiles.size() > tile_cap) {
+    set_error("internal: tile table of " + std::to_string(tiles.size()) + " entries exceeds its buffer (" +
+              std::to_string(tile_cap) + ")");
+    return RDM_E_INVALID;
   }
   const int nseg = (int)hsegs.size();
   RDM_HIP(hipMemcpyAsync(dsegs, hsegs.data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
@@ -434,6 +458,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
   std::vector<InstPlan> plans;
   for (auto& r : runs) plans.push_back(*r.plan);
   const size_t header = batch_header_bytes(plans);
+  const size_t tile_cap = batch_tile_capacity(plans);
   Seg* dsegs = (Seg*)ws;
   Tile* dtiles = (Tile*)(ws + al(sizeof(Seg) * 2 * ni));
   size_t inst_off = header;
@@ -451,14 +476,14 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     segs.push_back(seg_of(r, 0, MODE_LANCZOS, tau));
     segs.push_back(seg_of(r, 1, MODE_LANCZOS, tau));
   }
-  rdm_status s = run_phase(segs, dsegs, dtiles, prec, 0, st, profile ? &tm : nullptr);
+  rdm_status s = run_phase(segs, dsegs, dtiles, tile_cap, prec, 0, st, profile ? &tm : nullptr);
   if (s != RDM_OK) return s;
   for (auto& r : runs) r.status = host_phase(r, st);
   // pass 2 (two-pass plans): regenerate u_j from the stored coefficients
   segs.clear();
   for (auto& r : runs)
     if (r.plan->two_pass && r.status == RDM_OK) segs.push_back(seg_of(r, 0, MODE_REGEN, tau));
-  if ((s = run_phase(segs, dsegs, dtiles, prec, 1, st, nullptr)) != RDM_OK) return s;
+  if ((s = run_phase(segs, dsegs, dtiles, tile_cap, prec, 1, st, nullptr)) != RDM_OK) return s;
   Timers tg;
   tg.on = profile;
   for (auto& r : runs) {
@@ -564,7 +589,7 @@ rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uin
   // tiles first need the geometry; plan into a scratch offset, then shift
   size_t tmp = 0;
   plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, tmp);
-  const size_t ntiles = (size_t)g.n_row_tiles * (g.P / g.S);
+  const size_t ntiles = max_tiles(g);
   off = al(o_tiles + ntiles * sizeof(Tile));
   const size_t base_off = off;
   off += tmp;
@@ -579,7 +604,7 @@ rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uin
   std::vector<Seg> segs;
   segs.push_back(make_seg(g, op, ws + base_off, MODE_LANCZOS, which == 0 ? START_SYSBATH : START_BATH,
                           h->n_s, h->n_b, seed, tau));
-  s = run_phase(segs, (Seg*)ws, (Tile*)(ws + o_tiles), prec, 0, st, nullptr);
+  s = run_phase(segs, (Seg*)ws, (Tile*)(ws + o_tiles), ntiles, prec, 0, st, nullptr);
   HostHist hh;
   if (s == RDM_OK) s = fetch_hist(g, ws + base_off, hh, st);
   if (s == RDM_OK && hipStreamSynchronize(st) != hipSuccess) {

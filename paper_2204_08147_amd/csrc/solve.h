@@ -82,17 +82,20 @@ void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int r
               size_t& off);
 rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
                          int mode_req, uint64_t budget, int slab_opt, int rpl_opt);
+size_t max_tiles(const SegPlan& g);
+size_t batch_tile_capacity(const std::vector<InstPlan>& plans);
 size_t batch_header_bytes(const std::vector<InstPlan>& plans);
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile);
 
 // Phases (used by execute and by the serving engine).
 rdm_status bind_ops(InstRun& r, hipStream_t st);
 Seg seg_of(const InstRun& r, int which, int mode, double tau);
+int common_slab(std::vector<Seg>& segs);
 void seg_tiles(const Seg& sg, int seg_index, std::vector<Tile>& tiles);
 rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Tile* dtiles, int ntiles, int slab,
                        int cmax, hipStream_t st, StepTimers* tm);
-rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, int prec, int phase,
-                     hipStream_t st, StepTimers* tm);
+rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, size_t tile_cap, int prec,
+                     int phase, hipStream_t st, StepTimers* tm);
 rdm_status host_phase(InstRun& r, hipStream_t st);   // synchronous
 rdm_status gram_phase(InstRun& r, hipStream_t st, Timers* tg);  // synchronous
 rdm_status finalize(const InstRun& r, rdm_result* out);

@@ -77,7 +77,7 @@ APPLY_CASES = [
     lambda: random_dense_terms(3, 8, 53, density=0.3),  # 2048 rows, d_s = 8
     lambda: long_range_xx_zz(2, 11, 1.0, 54),     # uniform hops only
     lambda: long_range_xxz(3, 10, 55),            # parity hops with c_same = 0
-    lambda: random_sparse_xxz(3007),
+    lambda: random_sparse_xxz(3007, n_range=(12, 14)),
 ]
 
 
@@ -197,7 +197,7 @@ SOLVE_CASES = {
     "random_3+5": lambda: random_dense_terms(3, 5, 72, betas=(0.5, 2.0), n_v=2, k=40),
     "lr_2+9": lambda: long_range_xx_zz(2, 9, 1.5, 73, betas=(0.5, 1.0, 2.0, 4.0), n_v=5, k=60),
     "xxz_chain_2+10": lambda: nn_xxz_chain(2, 10, 74, betas=(0.7, 5.0), n_v=4, k=50),
-    "sparse": lambda: random_sparse_xxz(3011),
+    "sparse": lambda: random_sparse_xxz(3011, n_range=(12, 13)),
 }
 
 
@@ -251,14 +251,37 @@ def test_auto_mode_falls_back_to_two_pass_under_budget():
     assert e.value.status == -2
 
 
-def test_breakdown_small_space():
-    inst = random_dense_terms(1, 2, 81, k=20, n_v=2, betas=(0.5, 2.0))
-    want = olz.solve(inst)["results"]
+def _few_levels():
+    # only ZZ couplings and z-fields: H is diagonal with a handful of distinct
+    # levels, so every Krylov space closes after a few steps (k = 12 > k_c)
+    return Instance(1, 5, [(0, 1, 0.0, 0.0, 0.7), (2, 4, 0.0, 0.0, -0.4)],
+                    np.zeros(6), np.array([0.3, 0.0, 0.0, 0.5, 0.0, 0.0]), np.array([0.5, 2.0]), 3, 12, 9)
+
+
+def test_breakdown_freezes_columns():
+    inst = _few_levels()
+    o3 = olz.solve(inst)
+    assert max(len(a) for a in o3["alpha"]) < inst.k  # the oracle stops early too
+    want = o3["results"]
     got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
-    assert got["breakdown_total"] > 0 and got["breakdown_bath"] > 0
+    assert got["breakdown_total"] == inst.n_cols and got["breakdown_bath"] == inst.n_v
     check_result(got, want, 1e-10, "breakdown")
     ex = exact.exact_typicality(inst)
     check_result(got, ex, 1e-10, "breakdown vs exact typicality")
+    a, b, kc = rdm.lanczos(H(inst), which=0, n_v=inst.n_v, k=inst.k, seed=inst.seed, precision="fp64")
+    assert list(kc) == [len(x) for x in o3["alpha"]]
+    # frozen columns keep exact zeros past their Krylov size
+    for c in range(inst.n_cols):
+        assert np.all(a[kc[c]:, c] == 0.0)
+    mixed = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed")
+    check_result(mixed, want, 1e-5, "breakdown mixed")
+
+
+def test_k_capped_at_dimension():
+    inst = random_dense_terms(1, 2, 81, k=20, n_v=2, betas=(0.5, 2.0))
+    want = exact.exact_typicality(inst)
+    got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    check_result(got, want, 1e-10, "k > dim")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
