@@ -42,6 +42,12 @@ def parse():
     ap.add_argument("--n-b", type=int, default=18, help="bath spins (18 = the metric's workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="lr", choices=["lr", "batch", "large", "serve"],
+                    help="lr: the metric's workload (default); batch: 64 heterogeneous sparse XXZ "
+                         "instances in one batched solve; large: 3+23 spins (dim 2^26) two-pass; "
+                         "serve: Poisson arrivals of transverse-field requests")
+    ap.add_argument("--requests", type=int, default=400, help="serve: timed requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -103,6 +109,174 @@ def cpu_baseline(inst, budget_s=20.0):
                       f"x{cols:.2f} columns (NumPy, single-threaded element-wise kernels)"}
 
 
+def apply_work(insts, prec_bytes):
+    """Algorithmic bytes and flops of one apply launch over the H_t and H_b
+    segments of the given instances (averaged over the k steps: the previous
+    vector is absent at the first step)."""
+    import paper_2204_08147_amd as rdm
+    by = fl = 0.0
+    for inst in insts:
+        info = rdm.Hamiltonian.from_instance(inst).info()
+        nnz = 1 + info["hops_uniform"] + 0.5 * info["hops_parity"]
+        nnz_b = 1 + info["bath_hops_uniform"] + 0.5 * info["bath_hops_parity"]
+        prev = (inst.k - 1) / inst.k
+        for dim, cols, z in ((inst.dim, inst.n_cols, nnz), (inst.d_b, inst.n_v, nnz_b)):
+            by += dim * cols * prec_bytes * (2 + prev) + dim * prec_bytes
+            fl += 2.0 * z * dim * cols
+    return by, fl
+
+
+def roofline(bytes_, flops, t_s, traffic=None):
+    gbs = bytes_ / t_s / 1e9
+    tf = flops / t_s / 1e12
+    if flops / (VALU_PEAK_TFLOPS * 1e12) >= bytes_ / (HBM_PEAK_GBS * 1e9):
+        return {"bound": "alu", "achieved": round(tf, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / VALU_PEAK_TFLOPS, 4), "traffic": traffic}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def bench_batch(args):
+    """64 independent random-sparse XXZ instances (N in [12, 22], N_s in
+    {1,2,3}, average degree 4, beta log-uniform in [0.1, 10], n_v = 8, k = 50)
+    solved together by one batched call, mixed precision."""
+    import torch
+    import paper_2204_08147_amd as rdm
+    from workloads import cfg_batch
+    insts = cfg_batch()
+    hs = [rdm.Hamiltonian.from_instance(i) for i in insts]
+    items = [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
+    for _ in range(args.warmup):
+        rdm.solve_batch(items, precision="mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = rdm.solve_batch(items, precision="mixed", profile=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert all(o["status"] == 0 for o in out), [o["status"] for o in out]
+    by, fl = apply_work(insts, 4)
+    # one apply launch covers every instance resident in a wave; with several
+    # waves the event average is per launch of the wave, so report the sum
+    t_apply = float(np.mean([o["t_apply_ms"] for o in out])) * 1e-3
+    n = len(insts) * args.steps
+    return {"metric": "batched solves/s (64 heterogeneous instances)", "value": round(n / wall, 3),
+            "unit": "solves/s", "ms_per_step": round(1e3 * wall / args.steps, 2), "steps": args.steps,
+            "warmup": args.warmup, "dtype": "f32 vectors + f64 reductions",
+            "config": {"workload": "64 random sparse XXZ instances, N in [12,22], N_s in {1,2,3}, "
+                                   "degree 4, beta log-U[0.1,10], n_v=8, k=50",
+                       "dims": sorted(int(i.n) for i in insts)},
+            "apply_kernel_ms_mean": round(1e3 * t_apply, 4),
+            "two_pass_instances": int(sum(o["two_pass"] for o in out))}
+
+
+def bench_large(args):
+    """3 system + 23 bath spins (dim 2^26), long-range XXZ alpha = 1.2,
+    Delta = 0.8, x-field 1.0, beta = 2, n_v = 4 (32 columns), k = 80,
+    two-pass, mixed precision."""
+    import torch
+    import paper_2204_08147_amd as rdm
+    from workloads import cfg_large
+    inst = cfg_large()
+    h = rdm.Hamiltonian.from_instance(inst)
+    res = None
+    t0 = time.perf_counter()
+    res = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="two_pass",
+                    profile=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    by, fl = apply_work([inst], 4)
+    t_apply = res["t_apply_ms"] * 1e-3
+    return {"metric": "large-instance solve time", "value": round(wall, 3), "unit": "s/solve",
+            "higher_is_better": False, "dtype": "f32 vectors + f64 reductions",
+            "config": {"workload": "long-range XXZ 3+23 spins (dim 2^26), alpha=1.2, Delta=0.8, "
+                                   "x-field 1.0, beta=2, n_v=4 (32 columns), k=80, two-pass"},
+            "apply_kernel_ms": round(1e3 * t_apply, 3), "norm_kernel_ms": round(res["t_norm_ms"], 3),
+            "roofline_apply": roofline(by, fl, t_apply), "two_pass": res["two_pass"],
+            "device_bytes": res["device_bytes"],
+            "rho": res["rho"][0].round(6).tolist(), "entropy": float(res["entropy"][0]),
+            "h_star_eigs": np.linalg.eigvalsh(res["h_star"][0]).round(6).tolist()}
+
+
+def bench_serve(args):
+    """Serving: requests with N ~ U{14..24}, d_s in {2,4}, ZZ chain J = 1 with
+    x-field h ~ U(0,2), beta log-uniform in [0.1,10], n_v = 8, k = 60, mixed
+    precision, submitted to the continuous-batching engine.  Reports the
+    closed-loop capacity and the latency of a Poisson arrival run."""
+    import threading
+    import torch
+    import paper_2204_08147_amd as rdm
+    from workloads import poisson_arrivals, tfim_request
+    n_warm = 20
+    reqs = [tfim_request(r) for r in range(args.requests + n_warm + 200)]
+    hs = [rdm.Hamiltonian.from_instance(i) for i in reqs]
+    srv = rdm.Server(hbm_budget=int(200e9), max_active=64, precision="mixed")
+    try:
+        # closed loop: everything submitted at once -> saturated capacity
+        t0 = time.perf_counter()
+        tk = [srv.submit(hs[i], reqs[i].betas, reqs[i].n_v, reqs[i].k, reqs[i].seed)
+              for i in range(n_warm, n_warm + 200)]
+        for t in tk:
+            assert srv.wait(t)["status"] == 0
+        capacity = 200 / (time.perf_counter() - t0)
+        # open loop: Poisson arrivals
+        arr = poisson_arrivals(args.requests, args.rate)
+        done = {}
+        pending = {}
+        lock = threading.Lock()
+        stop = [False]
+
+        def poller():
+            while not stop[0] or pending:
+                with lock:
+                    items = list(pending.items())
+                for t, i in items:
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[i] = (time.perf_counter(), r["status"])
+                        with lock:
+                            del pending[t]
+                time.sleep(0.0005)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        start = time.perf_counter()
+        sub = {}
+        base = n_warm + 200
+        for i in range(args.requests):
+            now = time.perf_counter() - start
+            if arr[i] > now:
+                time.sleep(arr[i] - now)
+            j = base + i
+            sub[i] = time.perf_counter()
+            t = srv.submit(hs[j % len(hs)], reqs[j % len(reqs)].betas, reqs[j % len(reqs)].n_v,
+                           reqs[j % len(reqs)].k, reqs[j % len(reqs)].seed)
+            with lock:
+                pending[t] = i
+        while True:
+            with lock:
+                if not pending:
+                    break
+            time.sleep(0.01)
+        stop[0] = True
+        th.join()
+        total = time.perf_counter() - start
+        stats = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array([done[i][0] - sub[i] for i in range(args.requests)])
+    assert all(done[i][1] == 0 for i in range(args.requests))
+    return {"metric": "serving: solves/s and p50/p99 latency", "value": round(args.requests / total, 3),
+            "unit": "solves/s", "dtype": "f32 vectors + f64 reductions",
+            "config": {"workload": f"Poisson arrivals {args.rate}/s of transverse-field ZZ-chain "
+                                   "requests, N in [14,24], d_s in {2,4}, beta log-U[0.1,10], n_v=8, k=60",
+                       "requests": args.requests},
+            "capacity_closed_loop": round(capacity, 3), "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+            "offered_rate": args.rate, "peak_active": stats["peak_active"],
+            "engine_steps": stats["steps"], "peak_device_bytes": stats["peak_bytes"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -115,6 +289,12 @@ def main():
     from workloads import LR_FIELDS, cfg_long_range
 
     torch.cuda.set_device(0)
+    if args.workload != "lr":
+        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve}[args.workload]
+        out = fn(args)
+        out.update({"n_gpus": 1, "data": "synthetic", "scaling": "weak"})
+        print(json.dumps(out))
+        return
     if args.copy_calibration:
         # a plain copy of known size: reads 1 GiB, writes 1 GiB
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

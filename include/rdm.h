@@ -85,8 +85,9 @@ typedef struct {
                           recurrence coefficients.                           */
   uint64_t hbm_budget; /* bytes of device memory the solve may use; 0 = free
                           device memory minus a 2 GiB reserve                */
-  int32_t slab;        /* apply kernel: 16-byte panels per lane (0 = tuned)   */
-  int32_t rows_per_lane;/* apply kernel: rows per lane (0 = tuned)            */
+  int32_t slab;        /* apply/norm kernels: 16-byte panels per lane, 1, 2 or
+                          4 (0 = tuned); results do not depend on it         */
+  int32_t rows_per_lane;/* Gram kernel: rows per lane (0 = tuned)             */
   double tau;          /* breakdown threshold (0 = 1e-12 FP64, 1e-5 mixed)    */
   int32_t reserved[4]; /* reserved[0] = 1: time the step kernels with HIP
                           events on hip_stream (results in rdm_result.diag);
@@ -122,7 +123,11 @@ void rdm_hamiltonian_destroy(rdm_hamiltonian* h);
 
 /* Table sizes of a built Hamiltonian: out[0]=N, [1]=n_s, [2]=n_b,
  * [3]=uniform-coefficient hops, [4]=parity-dependent hops, [5]=diagonal terms,
- * [6..8] the same three counts for H_b.  out: host array of 9 int64. */
+ * [6..8] the same three counts for H_b, [9] / [10] partner-tile groups the
+ * apply kernel stages in LDS for H_t / H_b (hops grouped by their flip bits
+ * above a 256-row tile; the own tile plus every tile read by at least three
+ * hops), [11] / [12] hops it gathers directly from memory instead.
+ * out: host array of 13 int64. */
 rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* out);
 
 /* Full solve (blocking; results on the host).  beta: host array of n_beta
@@ -163,6 +168,19 @@ typedef struct {
  * Returns the first failing item's status, RDM_OK if all succeeded. */
 rdm_status rdm_solve_batch(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
                            void* hip_stream);
+
+/* As rdm_solve_batch with caller-owned device memory (device pointer,
+ * 256-byte aligned, borrowed for the call): the waves are planned to fit
+ * ws_bytes (unless hbm_budget is smaller) and all reuse the same workspace.
+ * ws_bytes must be at least the min_bytes of rdm_batch_workspace_size. */
+rdm_status rdm_solve_batch_ws(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
+                              void* hip_stream, void* dev_workspace, uint64_t ws_bytes);
+
+/* Workspace bounds of a batch (host outputs): min_bytes runs the largest
+ * instance alone; all_bytes runs every valid instance in one wave.  Items
+ * failing validation get their status written and are left out. */
+rdm_status rdm_batch_workspace_size(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
+                                    uint64_t* min_bytes, uint64_t* all_bytes);
 
 /* ---- Kernel-level entry points (device pointers; used by tests/bench) ---- */
 

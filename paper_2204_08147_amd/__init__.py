@@ -96,10 +96,11 @@ class Hamiltonian:
         return cls(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
 
     def info(self) -> dict:
-        out = (C.c_int64 * 9)()
+        out = (C.c_int64 * 13)()
         _check(LIB.rdm_hamiltonian_info(self.handle, out), "rdm_hamiltonian_info")
         keys = ["n", "n_s", "n_b", "hops_uniform", "hops_parity", "diag_terms",
-                "bath_hops_uniform", "bath_hops_parity", "bath_diag_terms"]
+                "bath_hops_uniform", "bath_hops_parity", "bath_diag_terms", "tile_groups",
+                "bath_tile_groups", "direct_hops", "bath_direct_hops"]
         return dict(zip(keys, list(out)))
 
     def close(self):
@@ -166,9 +167,12 @@ def solve(h: Hamiltonian, betas: Sequence[float], n_v: int, k: int, seed: int, *
     return res.as_dict()
 
 
-def solve_batch(items: List[dict], *, stream=None, **opts) -> List[dict]:
+def solve_batch(items: List[dict], *, stream=None, library_alloc: bool = False,
+                reserve_bytes: int = 8 << 30, **opts) -> List[dict]:
     """items: dicts with keys h, betas, n_v, k, seed.  Returns per-item result
-    dicts (each with a 'status' entry)."""
+    dicts (each with a 'status' entry).  By default the workspace is a torch
+    tensor sized to run every instance in one wave when device memory allows
+    (less memory means more waves, never an error)."""
     o = make_options(**opts)
     n = len(items)
     arr = (_lib.BatchItem * max(n, 1))()
@@ -185,7 +189,21 @@ def solve_batch(items: List[dict], *, stream=None, **opts) -> List[dict]:
         arr[t].seed = it["seed"]
         arr[t].out = rb.c
     st = _stream_handle(stream)
-    LIB.rdm_solve_batch(n, arr, C.byref(o), st)
+    if library_alloc:
+        LIB.rdm_solve_batch(n, arr, C.byref(o), st)
+    else:
+        import torch
+        lo, hi = C.c_uint64(), C.c_uint64()
+        LIB.rdm_batch_workspace_size(n, arr, C.byref(o), C.byref(lo), C.byref(hi))
+        if hi.value:
+            free, _ = torch.cuda.mem_get_info()
+            cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
+            size = int(max(lo.value, min(hi.value, free + cached - reserve_bytes)))
+            ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+            LIB.rdm_solve_batch_ws(n, arr, C.byref(o), st, C.c_void_p(ws.data_ptr()), size)
+            del ws
+        else:
+            LIB.rdm_solve_batch(n, arr, C.byref(o), st)
     out = []
     for t in range(n):
         d = keep[t][1].as_dict()

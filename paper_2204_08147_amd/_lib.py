@@ -59,6 +59,10 @@ SIGNATURES = [
      [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
       C.POINTER(Options), C.c_void_p, C.POINTER(Result), C.c_void_p, C.c_uint64]),
     ("rdm_solve_batch", C.c_int32, [C.c_int32, C.POINTER(BatchItem), C.POINTER(Options), C.c_void_p]),
+    ("rdm_solve_batch_ws", C.c_int32,
+     [C.c_int32, C.POINTER(BatchItem), C.POINTER(Options), C.c_void_p, C.c_void_p, C.c_uint64]),
+    ("rdm_batch_workspace_size", C.c_int32,
+     [C.c_int32, C.POINTER(BatchItem), C.POINTER(Options), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("rdm_apply", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Options),
       C.c_void_p]),

@@ -1,4 +1,5 @@
 // extern "C" entry points of the solver (argument checks, planning, memory).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -129,7 +130,7 @@ static rdm_status solve_impl(const rdm_hamiltonian* h, const double* beta, int32
   runs[0].plan = &plans[0];
   runs[0].betas.assign(beta, beta + n_beta);
   runs[0].seed = seed;
-  s = execute(runs, ws, st, o.tau, o.profile);
+  s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0);
   if (s == RDM_OK) s = runs[0].status;
   if (s == RDM_OK) s = finalize(runs[0], out);
   if (owned) (void)hipFree(ws);
@@ -153,8 +154,59 @@ extern "C" rdm_status rdm_solve_ws(const rdm_hamiltonian* h, const double* beta,
   return solve_impl(h, beta, n_beta, n_v, k, seed, opt, hip_stream, out, dev_workspace, ws_bytes);
 }
 
-extern "C" rdm_status rdm_solve_batch(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
-                                      void* hip_stream) {
+namespace {
+
+// Plan every item; invalid ones get their status and are left out.
+rdm_status plan_batch(int32_t n_items, rdm_batch_item* items, const Opts& o, std::vector<InstPlan>& plans,
+                      std::vector<int>& valid) {
+  rdm_status first = RDM_OK;
+  plans.assign(n_items, InstPlan{});
+  valid.clear();
+  for (int i = 0; i < n_items; ++i) {
+    rdm_batch_item& it = items[i];
+    it.status = check_solve_args(it.h, it.beta, it.n_beta, it.n_v, it.k);
+    if (it.status == RDM_OK)
+      it.status = plan_instance(plans[i], it.h, it.n_beta, it.n_v, it.k, o.prec, o.mode, o.budget, o.slab,
+                                o.rpl);
+    if (it.status == RDM_OK)
+      valid.push_back(i);
+    else if (first == RDM_OK)
+      first = it.status;
+  }
+  return first;
+}
+
+// Greedy waves, largest instances first, each fitting in `budget` bytes.
+std::vector<std::vector<int>> make_waves(const std::vector<InstPlan>& plans, std::vector<int> valid,
+                                         uint64_t budget, size_t* max_need) {
+  std::sort(valid.begin(), valid.end(), [&](int a, int b) { return plans[a].bytes > plans[b].bytes; });
+  std::vector<std::vector<int>> waves;
+  *max_need = 0;
+  size_t pos = 0;
+  while (pos < valid.size()) {
+    std::vector<int> wave;
+    std::vector<InstPlan> wp;
+    size_t used = 0;
+    while (pos < valid.size()) {
+      const InstPlan& p = plans[valid[pos]];
+      wp.push_back(p);
+      const size_t need = batch_header_bytes(wp) + used + p.bytes;
+      if (!wave.empty() && need > budget) {
+        wp.pop_back();
+        break;
+      }
+      wave.push_back(valid[pos]);
+      used += p.bytes;
+      ++pos;
+    }
+    *max_need = std::max(*max_need, batch_header_bytes(wp) + used);
+    waves.push_back(wave);
+  }
+  return waves;
+}
+
+rdm_status batch_impl(int32_t n_items, rdm_batch_item* items, const rdm_options* opt, void* hip_stream,
+                      void* dev_ws, uint64_t ws_bytes) {
   Opts o;
   rdm_status s = read_opts(opt, o);
   if (s != RDM_OK) return s;
@@ -162,51 +214,36 @@ extern "C" rdm_status rdm_solve_batch(int32_t n_items, rdm_batch_item* items, co
     set_error("rdm_solve_batch: bad item list");
     return RDM_E_INVALID;
   }
+  if (dev_ws && !o.budget) o.budget = ws_bytes;
   if ((s = default_budget(o.budget)) != RDM_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
-  std::vector<InstPlan> plans(n_items);
-  rdm_status first = RDM_OK;
+  std::vector<InstPlan> plans;
   std::vector<int> valid;
-  for (int i = 0; i < n_items; ++i) {
-    rdm_batch_item& it = items[i];
-    it.status = check_solve_args(it.h, it.beta, it.n_beta, it.n_v, it.k);
-    if (it.status == RDM_OK)
-      it.status = plan_instance(plans[i], it.h, it.n_beta, it.n_v, it.k, o.prec, o.mode, o.budget,
-                                o.slab, o.rpl);
-    if (it.status == RDM_OK)
-      valid.push_back(i);
-    else if (first == RDM_OK)
-      first = it.status;
-  }
-  // waves of instances that fit in the budget together (largest first)
-  std::sort(valid.begin(), valid.end(), [&](int a, int b) { return plans[a].bytes > plans[b].bytes; });
-  size_t pos = 0;
-  while (pos < valid.size()) {
-    std::vector<InstPlan> wave_plans;
-    std::vector<int> wave;
-    size_t used = 0;
-    while (pos < valid.size()) {
-      const InstPlan& p = plans[valid[pos]];
-      std::vector<InstPlan> trial = wave_plans;
-      trial.push_back(p);
-      const size_t need = batch_header_bytes(trial) + used + p.bytes;
-      if (!wave.empty() && need > o.budget) break;
-      wave_plans.push_back(p);
-      wave.push_back(valid[pos]);
-      used += p.bytes;
-      ++pos;
+  rdm_status first = plan_batch(n_items, items, o, plans, valid);
+  size_t need = 0;
+  const auto waves = make_waves(plans, valid, o.budget, &need);
+  if (valid.empty()) return first;
+  char* ws = (char*)dev_ws;
+  bool owned = false;
+  if (ws) {
+    if (ws_bytes < need || ((uintptr_t)ws & 255)) {
+      set_error("batch workspace too small or not 256-byte aligned: need " + std::to_string(need));
+      return RDM_E_INVALID;
     }
-    const size_t need = batch_header_bytes(wave_plans) + used;
-    char* ws = nullptr;
-    RDM_HIP(hipMalloc(&ws, need));
+  } else {
+    RDM_HIP(hipMalloc(&ws, need));  // one allocation reused by every wave
+    owned = true;
+  }
+  for (const auto& wave : waves) {
+    std::vector<InstPlan> wave_plans;
+    for (int i : wave) wave_plans.push_back(plans[i]);
     std::vector<InstRun> runs(wave.size());
     for (size_t w = 0; w < wave.size(); ++w) {
       runs[w].plan = &wave_plans[w];
       runs[w].betas.assign(items[wave[w]].beta, items[wave[w]].beta + items[wave[w]].n_beta);
       runs[w].seed = items[wave[w]].seed;
     }
-    s = execute(runs, ws, st, o.tau, o.profile);
-    (void)hipFree(ws);
+    s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0);
     for (size_t w = 0; w < wave.size(); ++w) {
       rdm_batch_item& it = items[wave[w]];
       it.status = s != RDM_OK ? s : runs[w].status;
@@ -214,7 +251,50 @@ extern "C" rdm_status rdm_solve_batch(int32_t n_items, rdm_batch_item* items, co
       if (it.status != RDM_OK && first == RDM_OK) first = it.status;
     }
   }
+  if (owned) (void)hipFree(ws);
   return first;
+}
+
+}  // namespace
+
+extern "C" rdm_status rdm_solve_batch(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
+                                      void* hip_stream) {
+  return batch_impl(n_items, items, opt, hip_stream, nullptr, 0);
+}
+
+extern "C" rdm_status rdm_solve_batch_ws(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
+                                         void* hip_stream, void* dev_workspace, uint64_t ws_bytes) {
+  if (!dev_workspace) {
+    set_error("rdm_solve_batch_ws: NULL workspace");
+    return RDM_E_INVALID;
+  }
+  return batch_impl(n_items, items, opt, hip_stream, dev_workspace, ws_bytes);
+}
+
+extern "C" rdm_status rdm_batch_workspace_size(int32_t n_items, rdm_batch_item* items, const rdm_options* opt,
+                                               uint64_t* min_bytes, uint64_t* all_bytes) {
+  Opts o;
+  rdm_status s = read_opts(opt, o);
+  if (s != RDM_OK) return s;
+  if (n_items < 0 || (n_items > 0 && !items) || !min_bytes || !all_bytes) {
+    set_error("rdm_batch_workspace_size: bad arguments");
+    return RDM_E_INVALID;
+  }
+  if ((s = default_budget(o.budget)) != RDM_OK) return s;
+  std::vector<InstPlan> plans;
+  std::vector<int> valid;
+  plan_batch(n_items, items, o, plans, valid);
+  size_t mx = 0, sum = 0;
+  std::vector<InstPlan> all;
+  for (int i : valid) {
+    mx = std::max(mx, plans[i].bytes);
+    sum += plans[i].bytes;
+    all.push_back(plans[i]);
+  }
+  std::vector<InstPlan> one(valid.empty() ? 0 : 1);
+  *min_bytes = valid.empty() ? 0 : batch_header_bytes(one) + mx;
+  *all_bytes = valid.empty() ? 0 : batch_header_bytes(all) + sum;
+  return RDM_OK;
 }
 
 extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t precision,
@@ -236,12 +316,14 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   const int nbits = which == 0 ? h->n : h->n_b;
   plan_seg(g, nbits, n_cols, 1, precision, o.slab, o.rpl, 1, off);
   Seg sg{};
-  sg.hopU = op->hopU;
-  sg.hopP = op->hopP;
+  sg.hops = op->hops;
+  sg.groups = op->groups;
+  sg.thin = op->thin;
   sg.diag = op->diag;
-  sg.nU = op->nU;
-  sg.nP = op->nP;
-  sg.nPh = op->nPh;
+  sg.ngroups = op->ngroups;
+  sg.nt0 = op->nt[0];
+  sg.nt1 = op->nt[1];
+  sg.nt2 = op->nt[2];
   sg.nbits = nbits;
   sg.P = g.P;
   sg.S = g.S;
@@ -253,21 +335,20 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   sg.blk = g.blk;
   sg.Q = (void*)x;
   sg.R = y;
-  std::vector<Tile> tiles;
-  for (int rt = 0; rt < g.n_row_tiles; ++rt)
-    for (int p0 = 0; p0 < g.P; p0 += g.S)
-      tiles.push_back(Tile{0, (uint32_t)((uint64_t)rt * kBlock * g.rpl), p0, rt});
+  sg.n_row_tiles = g.n_row_tiles;
+  std::vector<Seg> one{sg};
+  const int ntiles = assign_tiles(one);
+  sg = one[0];
+  static_assert(sizeof(Seg) <= 256, "segment descriptor must fit its 256-byte buffer");
   char* d = nullptr;
-  const size_t tb = tiles.size() * sizeof(Tile);
-  RDM_HIP(hipMalloc(&d, 256 + tb));
+  RDM_HIP(hipMalloc(&d, 256));
   rdm_status r = RDM_OK;
   auto run = [&]() -> rdm_status {
     RDM_HIP(hipMemcpyAsync(d, &sg, sizeof(Seg), hipMemcpyHostToDevice, st));
-    RDM_HIP(hipMemcpyAsync(d + 256, tiles.data(), tb, hipMemcpyHostToDevice, st));
     if (precision == RDM_FP64)
-      RDM_HIP(launch_apply<double>((Seg*)d, (Tile*)(d + 256), (int)tiles.size(), g.S, st));
+      RDM_HIP(launch_apply<double>((Seg*)d, 1, ntiles, g.S, st));
     else
-      RDM_HIP(launch_apply<float>((Seg*)d, (Tile*)(d + 256), (int)tiles.size(), g.S, st));
+      RDM_HIP(launch_apply<float>((Seg*)d, 1, ntiles, g.S, st));
     RDM_HIP(hipStreamSynchronize(st));
     return RDM_OK;
   };

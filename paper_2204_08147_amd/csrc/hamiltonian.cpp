@@ -63,54 +63,96 @@ void compile(const rdm_hamiltonian& h, int first_site, OpTables& t) {
       t.uc.push_back(h.hx[s]);
     }
   }
-  // parity hops whose tested bits are all >= 6 first: within a wave of 64
-  // consecutive rows their coefficient is uniform
-  std::vector<size_t> order(t.pf.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-    return ((t.pm[a] & 63u) == 0u) > ((t.pm[b] & 63u) == 0u);
+  // grouped form: sort every hop by the partner tile it reads (flip bits above
+  // the 256-row tile), then by kind, keeping the input order otherwise
+  struct H {
+    uint32_t f, m;
+    double cs, cd;
+    int kind;
+  };
+  std::vector<H> all;
+  for (size_t i = 0; i < t.uf.size(); ++i) all.push_back(H{t.uf[i], 0u, t.uc[i], t.uc[i], 0});
+  for (size_t i = 0; i < t.pf.size(); ++i)
+    all.push_back(H{t.pf[i], t.pm[i], t.pcs[i], t.pcd[i], (t.pm[i] & 63u) == 0u ? 1 : 2});
+  const uint32_t lo_mask = (1u << kTileBits) - 1u;
+  std::stable_sort(all.begin(), all.end(), [&](const H& a, const H& b) {
+    const uint32_t ha = a.f & ~lo_mask, hb = b.f & ~lo_mask;
+    if (ha != hb) return ha < hb;
+    return a.kind < b.kind;
   });
-  OpTables s2 = t;
-  for (size_t i = 0; i < order.size(); ++i) {
-    t.pf[i] = s2.pf[order[i]];
-    t.pm[i] = s2.pm[order[i]];
-    t.pcs[i] = s2.pcs[order[i]];
-    t.pcd[i] = s2.pcd[order[i]];
+  // count the hops per partner tile; tiles used at least kFatGroup times (and
+  // the own tile) are staged in LDS, the other hops are gathered directly
+  std::map<uint32_t, int> uses;
+  for (const H& x : all) uses[x.f & ~lo_mask] += 1;
+  t.groups.clear();
+  t.groups.push_back(HopGroup{0u, 0, 0, 0, 0, 0, {0, 0}});  // the own tile always comes first
+  std::vector<H> thin[3];
+  for (size_t i = 0; i < all.size(); ++i) {
+    const uint32_t fhi = all[i].f & ~lo_mask;
+    if (fhi != 0u && uses[fhi] < kFatGroup) {
+      thin[all[i].kind].push_back(all[i]);
+      continue;
+    }
+    if (fhi != t.groups.back().fhi)
+      t.groups.push_back(HopGroup{fhi, (int32_t)t.g_flo.size(), 0, 0, 0, 0, {0, 0}});
+    HopGroup& g = t.groups.back();
+    (all[i].kind == 0 ? g.n0 : all[i].kind == 1 ? g.n1 : g.n2) += 1;
+    t.g_flo.push_back(all[i].f & lo_mask);
+    t.g_m.push_back(all[i].m);
+    t.g_cs.push_back(all[i].cs);
+    t.g_cd.push_back(all[i].cd);
   }
-  t.nPh = 0;
-  for (size_t i = 0; i < t.pm.size(); ++i) t.nPh += (t.pm[i] & 63u) == 0u;
+  for (size_t g = 1; g < t.groups.size(); ++g) {
+    HopGroup& gr = t.groups[g];
+    bool uni = gr.n0 == 0 && gr.n2 == 0 && gr.n1 > 0;
+    for (int h = gr.start; uni && h < gr.start + gr.n1; ++h) uni = (t.g_m[h] & lo_mask) == 0u;
+    gr.tile_uniform = uni ? 1 : 0;
+  }
+  for (int k = 0; k < 3; ++k) {
+    t.nt[k] = (int)thin[k].size();
+    for (const H& x : thin[k]) {
+      t.t_f.push_back(x.f);
+      t.t_m.push_back(x.m);
+      t.t_cs.push_back(x.cs);
+      t.t_cd.push_back(x.cd);
+    }
+  }
 }
 
 template <typename T>
 rdm_status upload(const OpTables& t, OpDevice& d, hipStream_t st) {
-  std::vector<HopU<T>> hu(t.uf.size());
-  for (size_t i = 0; i < hu.size(); ++i) hu[i] = HopU<T>{t.uf[i], 0, (T)t.uc[i]};
-  std::vector<HopP<T>> hp(t.pf.size());
-  for (size_t i = 0; i < hp.size(); ++i) hp[i] = HopP<T>{t.pf[i], t.pm[i], (T)t.pcs[i], (T)t.pcd[i]};
+  std::vector<GHop<T>> hops(t.g_flo.size());
+  for (size_t i = 0; i < hops.size(); ++i)
+    hops[i] = GHop<T>{t.g_flo[i], t.g_m[i], (T)t.g_cs[i], (T)t.g_cd[i]};
   const size_t dim = size_t(1) << t.nbits;
-  RDM_HIP(hipMalloc(&d.hopU, std::max<size_t>(16, hu.size() * sizeof(HopU<T>))));
-  RDM_HIP(hipMalloc(&d.hopP, std::max<size_t>(16, hp.size() * sizeof(HopP<T>))));
+  RDM_HIP(hipMalloc(&d.hops, std::max<size_t>(16, hops.size() * sizeof(GHop<T>))));
+  RDM_HIP(hipMalloc(&d.groups, std::max<size_t>(16, t.groups.size() * sizeof(HopGroup))));
+  std::vector<GHop<T>> thin(t.t_f.size());
+  for (size_t i = 0; i < thin.size(); ++i) thin[i] = GHop<T>{t.t_f[i], t.t_m[i], (T)t.t_cs[i], (T)t.t_cd[i]};
+  RDM_HIP(hipMalloc(&d.thin, std::max<size_t>(16, thin.size() * sizeof(GHop<T>))));
+  if (!thin.empty())
+    RDM_HIP(hipMemcpyAsync(d.thin, thin.data(), thin.size() * sizeof(GHop<T>), hipMemcpyHostToDevice, st));
+  for (int k = 0; k < 3; ++k) d.nt[k] = t.nt[k];
   RDM_HIP(hipMalloc(&d.dterms, std::max<size_t>(16, t.diag.size() * sizeof(DiagTerm))));
   RDM_HIP(hipMalloc(&d.diag, dim * sizeof(T)));
-  if (!hu.empty())
-    RDM_HIP(hipMemcpyAsync(d.hopU, hu.data(), hu.size() * sizeof(HopU<T>), hipMemcpyHostToDevice, st));
-  if (!hp.empty())
-    RDM_HIP(hipMemcpyAsync(d.hopP, hp.data(), hp.size() * sizeof(HopP<T>), hipMemcpyHostToDevice, st));
+  if (!hops.empty())
+    RDM_HIP(hipMemcpyAsync(d.hops, hops.data(), hops.size() * sizeof(GHop<T>), hipMemcpyHostToDevice, st));
+  RDM_HIP(hipMemcpyAsync(d.groups, t.groups.data(), t.groups.size() * sizeof(HopGroup),
+                         hipMemcpyHostToDevice, st));
   if (!t.diag.empty())
     RDM_HIP(hipMemcpyAsync(d.dterms, t.diag.data(), t.diag.size() * sizeof(DiagTerm),
                            hipMemcpyHostToDevice, st));
   RDM_HIP(launch_diag<T>((const DiagTerm*)d.dterms, (int)t.diag.size(), (T*)d.diag, t.nbits, st));
   RDM_HIP(hipStreamSynchronize(st));
-  d.nU = (int)hu.size();
-  d.nP = (int)hp.size();
-  d.nPh = t.nPh;
+  d.ngroups = (int)t.groups.size();
   d.ready = true;
   return RDM_OK;
 }
 
 void free_dev(rdm::OpDevice& d) {
-  if (d.hopU) (void)hipFree(d.hopU);
-  if (d.hopP) (void)hipFree(d.hopP);
+  if (d.hops) (void)hipFree(d.hops);
+  if (d.groups) (void)hipFree(d.groups);
+  if (d.thin) (void)hipFree(d.thin);
   if (d.diag) (void)hipFree(d.diag);
   if (d.dterms) (void)hipFree(d.dterms);
   d = rdm::OpDevice{};
@@ -215,6 +257,8 @@ extern "C" rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* ou
     out[3 + 3 * w] = (int64_t)h->op[w].uf.size();
     out[4 + 3 * w] = (int64_t)h->op[w].pf.size();
     out[5 + 3 * w] = (int64_t)h->op[w].diag.size();
+    out[9 + w] = (int64_t)h->op[w].groups.size();
+    out[11 + w] = (int64_t)h->op[w].t_f.size();
   }
   return RDM_OK;
 }

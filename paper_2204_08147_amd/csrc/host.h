@@ -30,18 +30,27 @@ struct OpTables {
   std::vector<double> uc;
   std::vector<uint32_t> pf, pm;  // parity-dependent hops
   std::vector<double> pcs, pcd;
-  int nPh = 0;  // leading parity hops with both tested bits >= 6
+  // grouped form used by the apply kernel (see GHop / HopGroup)
+  std::vector<uint32_t> g_flo, g_m;
+  std::vector<double> g_cs, g_cd;
+  std::vector<HopGroup> groups;
+  // hops of partner tiles used fewer than kFatGroup times: gathered directly
+  std::vector<uint32_t> t_f, t_m;
+  std::vector<double> t_cs, t_cd;
+  int nt[3] = {0, 0, 0};
 };
 
 // Device copy of an operator's tables in one precision.
 struct OpDevice {
   bool ready = false;
   int device = -1;
-  void* hopU = nullptr;
-  void* hopP = nullptr;
+  void* hops = nullptr;
+  void* groups = nullptr;
+  void* thin = nullptr;
+  int nt[3] = {0, 0, 0};
   void* diag = nullptr;
   void* dterms = nullptr;
-  int nU = 0, nP = 0, nPh = 0;
+  int ngroups = 0;
 };
 
 }  // namespace rdm

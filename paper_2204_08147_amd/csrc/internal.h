@@ -28,19 +28,30 @@ enum {
 enum { MODE_LANCZOS = 0, MODE_REGEN = 1, MODE_PLAIN = 2 };
 enum { START_SYSBATH = 0, START_BATH = 1 };
 
-// Hop with a coefficient that does not depend on the basis state.
+constexpr int kTileBits = 8;       // the apply stages 2^8 = kBlock-row partner tiles in LDS
+constexpr int kFatGroup = 3;       // partner tiles read by at least this many hops go through LDS
+
+// One off-diagonal term of H as the apply sees it: row idx couples to the
+// partner idx ^ f with coefficient c = (parity(idx & m) == 0) ? cs : cd.
+// f is split into the bits above the 256-row tile (fhi, shared by the hop's
+// group) and the bits inside it (flo).  An XX+YY pair has m = f, cs = jx - jy,
+// cd = jx + jy; when cs == cd (or for a one-site x-field) m = 0.
 template <typename T>
-struct alignas(16) HopU {
-  uint32_t f;      // flip mask
-  uint32_t pad;
-  T c;
-};
-// Hop whose coefficient depends on whether the two tested bits agree:
-// c = (parity(idx & m) == 0) ? cs : cd  (XX+YY pair: cs = jx - jy, cd = jx + jy).
-template <typename T>
-struct alignas(16) HopP {
-  uint32_t f, m;
+struct alignas(16) GHop {
+  uint32_t flo;
+  uint32_t m;
   T cs, cd;
+};
+// Hops sharing one partner tile (same fhi), stored contiguously in three kinds:
+// n0 with m = 0, n1 whose tested bits are all >= 6 (the coefficient is uniform
+// over a wave of 64 consecutive rows), n2 with a per-row coefficient.
+struct HopGroup {
+  uint32_t fhi;
+  int32_t start;
+  int32_t n0, n1, n2;
+  int32_t tile_uniform;  // 1: only n1 hops, all tested bits >= 8, so every
+                         // coefficient is uniform over a 256-row tile
+  int32_t pad[2];
 };
 // Diagonal term: c * (1 - 2 * parity(idx & mask)).
 struct DiagTerm {
@@ -52,11 +63,12 @@ struct DiagTerm {
 // One Lanczos problem inside a (possibly batched) launch.  Lives in device
 // memory; all kernels read it with uniform loads.
 struct Seg {
-  const void* hopU;
-  const void* hopP;
+  const void* hops;    // GHop<T>[] of the LDS-staged groups
+  const void* groups;  // HopGroup[ngroups]; group 0 has fhi = 0
+  const void* thin;    // GHop<T>[] gathered directly (flo holds the full flip mask)
   const void* diag;
-  int32_t nU, nP;
-  int32_t nPh;         // leading parity hops whose tested bits are all >= 6
+  int32_t ngroups;
+  int32_t nt0, nt1, nt2;  // direct hops by kind (m = 0, wave-uniform, per-row)
   int32_t nbits;       // log2(dim)
   int32_t P;           // panels
   int32_t S;           // panels per lane in apply/norm
@@ -70,7 +82,8 @@ struct Seg {
   int32_t ns_log;      // log2 d_s for START_SYSBATH
   int32_t nb;          // bath bits (RNG index range)
   int32_t n_beta;      // psi blocks (MODE_REGEN)
-  int32_t n_row_tiles; // partial-sum rows
+  int32_t n_row_tiles; // partial-sum rows (= row tiles of kBlock rows)
+  int32_t tile_base;   // first workgroup of this segment in a norm/apply launch
   uint64_t seed;
   uint64_t blk;        // elements per vector block = dim * cpad
   void* Q;
@@ -85,10 +98,10 @@ struct Seg {
   int32_t* stepc;      // [cpad] current step (1-based) per column
   int32_t* kc;         // [cpad] Krylov size after breakdown truncation
   double tau;
-  int32_t pad0;
 };
 
-// Work item of the apply / norm kernels.
+// Work item of the apply / norm kernels, derived from blockIdx.x: segment s
+// owns workgroups [tile_base, tile_base + n_row_tiles * P/S), slab-major.
 struct Tile {
   int32_t seg;
   uint32_t row0;
@@ -116,9 +129,9 @@ struct GTile {
 template <typename T>
 hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st);
 template <typename T>
-hipError_t launch_norm(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st);
+hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 template <typename T>
-hipError_t launch_apply(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st);
+hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st);

@@ -118,6 +118,43 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* 
   }
 }
 
+// per-column scalars of the recurrence for panel s of a tile (uniform loads)
+template <typename T, int S>
+__device__ __forceinline__ typename PanelT<T>::V scur_of(const CONST_AS double* st, int cp, int panel0,
+                                                         int s, bool plain) {
+  typename PanelT<T>::V v;
+#pragma unroll
+  for (int e = 0; e < PanelT<T>::W; ++e)
+    v[e] = plain ? T(1) : (T)st[ST_SCUR * cp + (panel0 + s) * PanelT<T>::W + e];
+  return v;
+}
+template <typename T, int S>
+__device__ __forceinline__ typename PanelT<T>::V bps_of(const CONST_AS double* st, int cp, int panel0,
+                                                        int s) {
+  typename PanelT<T>::V v;
+#pragma unroll
+  for (int e = 0; e < PanelT<T>::W; ++e) v[e] = (T)st[ST_BPS * cp + (panel0 + s) * PanelT<T>::W + e];
+  return v;
+}
+
+// The tile of this workgroup: binary search of blockIdx.x in the segments'
+// tile_base offsets (uniform, scalar loads), then slab-major inside the
+// segment so the workgroups in flight share one group of panels.
+__device__ __forceinline__ Tile tile_of(const Seg* segs, int nseg) {
+  const CONST_AS Seg* cs = (const CONST_AS Seg*)segs;
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cs[mid].tile_base <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int lt = b - cs[lo].tile_base;
+  const int nrt = cs[lo].n_row_tiles;
+  const int sl = lt / nrt, rt = lt - sl * nrt;
+  return Tile{lo, (uint32_t)rt * (uint32_t)kBlock, sl * cs[lo].S, rt};
+}
+
 template <typename T>
 __device__ __forceinline__ T* slot_ptr(const CONST_AS Seg& sg, int j) {
   const int idx = sg.ring ? ((j - 1) & 1) : (j - 1);
@@ -160,12 +197,11 @@ __global__ void k_init_state(const Seg* __restrict__ segs, int phase) {
 // psi_b = fma(y_{b,j}, u_j, psi_b).  S = panels per lane (exact).
 // ---------------------------------------------------------------------------
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_norm(const Seg* __restrict__ segs,
-                                                 const Tile* __restrict__ tiles) {
+__global__ __launch_bounds__(kBlock) void k_norm(const Seg* __restrict__ segs, int nseg) {
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
   __shared__ double lds[4 * S * W];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tile_of(segs, nseg);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const int j = sg.stepc[0];
   if (j > sg.k) return;
@@ -252,53 +288,25 @@ __global__ __launch_bounds__(kBlock) void k_norm(const Seg* __restrict__ segs,
 // apply kernel: r = s_j (H u_j) - (beta_{j-1} s_{j-1}) u_{j-1}, partial sums of
 // <u_j, r>.  MODE_PLAIN: Y = H X with X = Q, Y = R.
 //
-// One lane per basis row, S 16-byte panels (S*W columns) per lane.  The hop
-// tables are read with scalar loads (every lane of a wave walks the same
-// list); each hop gathers the partner row idx ^ f of every panel with one
-// coalesced 16-byte load per lane.  Hops are processed U at a time so U*S
-// gathers are in flight before the FMAs that consume them.
+// A workgroup owns a tile of 256 consecutive rows (one per lane) and S panels
+// (S*W columns).  Every off-diagonal term maps the tile onto one partner tile
+// (the flip bits above the tile, fhi) permuted inside by the low flip bits
+// (flo).  The hops are grouped by fhi on the host.  For a partner tile that
+// several hops share, the workgroup loads it once -- a coalesced 16-byte load
+// per lane and panel -- into LDS, and every hop of the group reads its operand
+// from LDS at lane ^ flo; the load of the next group's tile is issued before
+// the current group's FMAs (double-buffered LDS), so one barrier per group
+// separates the two.  Hops whose partner tile is shared by fewer than
+// kFatGroup hops skip the staging and gather directly.  Hop coefficients come
+// from scalar loads.
 // ---------------------------------------------------------------------------
-template <typename T, int S, int U>
-__device__ __forceinline__ void hops_uniform(const CONST_AS HopU<T>* hu, int n, uint32_t row,
-                                             const typename PanelT<T>::V* __restrict__ ub,
-                                             uint64_t pstride, typename PanelT<T>::V (&acc)[S]) {
-  using V = typename PanelT<T>::V;
-  constexpr int W = PanelT<T>::W;
-  int h = 0;
-  for (; h + U <= n; h += U) {
-    V x[U][S];
-    T c[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t p = row ^ hu[h + u].f;
-      c[u] = hu[h + u].c;
-#pragma unroll
-      for (int s = 0; s < S; ++s) x[u][s] = ldg(ub + s * pstride, p);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int s = 0; s < S; ++s) acc[s] += c[u] * x[u][s];
-    // issue every gather of the group before the FMAs that consume them
-    __builtin_amdgcn_sched_group_barrier(0x0020, U * S, 0);
-    __builtin_amdgcn_sched_group_barrier(0x0002, U * S * W, 0);
-  }
-  for (; h < n; ++h) {
-    const uint32_t p = row ^ hu[h].f;
-    const T c = hu[h].c;
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
-  }
-}
-
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs,
-                                                  const Tile* __restrict__ tiles) {
+__global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, int nseg) {
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
-  constexpr int U = S >= 4 ? 4 : (S == 2 ? 8 : 8);
+  __shared__ V tl[2][S][kBlock];
   __shared__ double lds[4 * S * W];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tile_of(segs, nseg);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const bool plain = sg.mode == MODE_PLAIN;
   int j = 1;
@@ -313,91 +321,212 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs,
   const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride
                                      : nullptr;
   V* out = (V*)sg.R + (uint64_t)t.panel0 * pstride;
-  const CONST_AS HopU<T>* hu = (const CONST_AS HopU<T>*)sg.hopU;
-  const CONST_AS HopP<T>* hp = (const CONST_AS HopP<T>*)sg.hopP;
+  const CONST_AS GHop<T>* hp = (const CONST_AS GHop<T>*)sg.hops;
+  const CONST_AS HopGroup* gr = (const CONST_AS HopGroup*)sg.groups;
+  const int ng = sg.ngroups;
   const T* dg = (const T*)sg.diag;
-  const int nU = sg.nU, nP = sg.nP, nPh = sg.nPh;
   const bool dots = sg.mode == MODE_LANCZOS;
   const CONST_AS double* st = (const CONST_AS double*)sg.st;
 
-  V scur[S], bps[S];
+  const uint32_t lane = threadIdx.x;
+  const uint32_t row = t.row0 + lane;
+  const bool valid = row < dim;
+  const uint32_t wbase = __builtin_amdgcn_readfirstlane(row & ~63u);
+
+  V xc[S], acc[S], xnext[S];
+  const T d = valid ? ldg_s(dg, row) : T(0);
 #pragma unroll
-  for (int s = 0; s < S; ++s)
+  for (int s = 0; s < S; ++s) {
+    if (valid) {
+      xc[s] = ldg(ub + s * pstride, row);
+    } else {
 #pragma unroll
-    for (int e = 0; e < W; ++e) {
-      const int c = (t.panel0 + s) * W + e;
-      scur[s][e] = plain ? T(1) : (T)st[ST_SCUR * cp + c];
-      bps[s][e] = plain ? T(0) : (T)st[ST_BPS * cp + c];
+      for (int e = 0; e < W; ++e) xc[s][e] = T(0);
     }
+    acc[s] = d * xc[s];
+    xnext[s] = xc[s];            // group 0 is the own tile
+  }
 
-  double dq[S * W];
-#pragma unroll
-  for (int i = 0; i < S * W; ++i) dq[i] = 0.0;
-
-  for (int rr = 0; rr < sg.rpl; ++rr) {
-    const uint32_t row = t.row0 + rr * kBlock + threadIdx.x;
-    const uint32_t wbase = __builtin_amdgcn_readfirstlane(row & ~63u);
-    if (wbase >= dim) break;
-    if (row < dim) {
-      const T d = ldg_s(dg, row);
-      V acc[S], xc[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        xc[s] = ldg(ub + s * pstride, row);
-        acc[s] = d * xc[s];
+  // next group that contributes to this tile: a tile-uniform group whose
+  // coefficients all vanish for this tile is skipped (no load, no barrier)
+  const uint32_t tbase = t.row0;
+  auto next_active = [&](int g) -> int {
+    for (; g < ng; ++g) {
+      if (!gr[g].tile_uniform) return g;
+      const int h0 = gr[g].start, n1 = gr[g].n1;
+      for (int h = h0; h < h0 + n1; ++h) {
+        const T c = (__builtin_popcount(tbase & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
+        if (c != T(0)) return g;
       }
-      hops_uniform<T, S, U>(hu, nU, row, ub, pstride, acc);
-      // parity hops whose two tested bits lie above the wave's 64 rows: the
-      // coefficient is the same for the whole wave, and zero ones are skipped
-      for (int h = 0; h < nPh; ++h) {
-        const uint32_t m = hp[h].m;
-        const T c = (__builtin_popcount(wbase & m) & 1u) ? hp[h].cd : hp[h].cs;
+    }
+    return ng;
+  };
+
+  int buf = 0;
+  for (int g = 0; g < ng; ++buf) {
+    const int b = buf & 1;
+    const int gn = next_active(g + 1);
+#pragma unroll
+    for (int s = 0; s < S; ++s) tl[b][s][lane] = xnext[s];
+    __syncthreads();
+    if (gn < ng && valid) {
+      const uint32_t p = row ^ gr[gn].fhi;
+#pragma unroll
+      for (int s = 0; s < S; ++s) xnext[s] = ldg(ub + s * pstride, p);
+    }
+    if (valid) {
+      const int h0 = gr[g].start, n0 = gr[g].n0, n1 = gr[g].n1, n2 = gr[g].n2;
+      // state-independent coefficients, U hops at a time: all U*S operand
+      // reads are issued before the FMAs that consume them
+      constexpr int U = 4;
+      int h = h0;
+      for (; h + U <= h0 + n0; h += U) {
+        uint32_t q[U];
+        T c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          q[u] = lane ^ hp[h + u].flo;
+          c[u] = hp[h + u].cs;
+        }
+        V a[U][S];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int s = 0; s < S; ++s) a[u][s] = tl[b][s][q[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int s = 0; s < S; ++s) acc[s] += c[u] * a[u][s];
+        __builtin_amdgcn_sched_group_barrier(0x0100, U * S, 0);
+        __builtin_amdgcn_sched_group_barrier(0x0002, U * S * W, 0);
+      }
+      for (; h < h0 + n0; ++h) {
+        const uint32_t q = lane ^ hp[h].flo;
+        const T c = hp[h].cs;
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] += c * tl[b][s][q];
+      }
+      // coefficient uniform over the wave; zero ones skipped
+      for (; h < h0 + n0 + n1; ++h) {
+        const T c = (__builtin_popcount(wbase & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
         if (c == T(0)) continue;
-        const uint32_t p = row ^ hp[h].f;
+        const uint32_t q = lane ^ hp[h].flo;
 #pragma unroll
-        for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
+        for (int s = 0; s < S; ++s) acc[s] += c * tl[b][s][q];
       }
-      // remaining parity hops: per-row coefficient
-      int h = nPh;
-      for (; h + 2 <= nP; h += 2) {
-        V x0[S], x1[S];
-        const uint32_t p0 = row ^ hp[h].f, p1 = row ^ hp[h + 1].f;
+      // per-row coefficient, two hops at a time
+      const int hend = h0 + n0 + n1 + n2;
+      for (; h + 2 <= hend; h += 2) {
+        const uint32_t q0 = lane ^ hp[h].flo, q1 = lane ^ hp[h + 1].flo;
+        V a0[S], a1[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          x0[s] = ldg(ub + s * pstride, p0);
-          x1[s] = ldg(ub + s * pstride, p1);
+          a0[s] = tl[b][s][q0];
+          a1[s] = tl[b][s][q1];
         }
         const T c0 = (__builtin_popcount(row & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
         const T c1 = (__builtin_popcount(row & hp[h + 1].m) & 1u) ? hp[h + 1].cd : hp[h + 1].cs;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          acc[s] += c0 * x0[s];
-          acc[s] += c1 * x1[s];
+          acc[s] += c0 * a0[s];
+          acc[s] += c1 * a1[s];
         }
+        __builtin_amdgcn_sched_group_barrier(0x0100, 2 * S, 0);
+        __builtin_amdgcn_sched_group_barrier(0x0002, 2 * S * W + 8, 0);
       }
-      for (; h < nP; ++h) {
-        const uint32_t p = row ^ hp[h].f;
+      if (h < hend) {
         const T c = (__builtin_popcount(row & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
+        const uint32_t q = lane ^ hp[h].flo;
 #pragma unroll
-        for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
+        for (int s = 0; s < S; ++s) acc[s] += c * tl[b][s][q];
       }
-      V up[S];
-      if (uprev) {
+    }
+    g = gn;
+  }
+
+  // hops whose partner tile few hops share: coalesced gathers straight from
+  // memory, U at a time so U*S loads are in flight
+  if (valid) {
+    const CONST_AS GHop<T>* th = (const CONST_AS GHop<T>*)sg.thin;
+    const int e0 = sg.nt0, e1 = e0 + sg.nt1, e2 = e1 + sg.nt2;
+    constexpr int U = S >= 4 ? 4 : 8;
+    int h = 0;
+    for (; h + U <= e0; h += U) {
+      V x[U][S];
+      T c[U];
 #pragma unroll
-        for (int s = 0; s < S; ++s) up[s] = ldg(uprev + s * pstride, row);
+      for (int u = 0; u < U; ++u) {
+        const uint32_t p = row ^ th[h + u].flo;
+        c[u] = th[h + u].cs;
+#pragma unroll
+        for (int s = 0; s < S; ++s) x[u][s] = ldg(ub + s * pstride, p);
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] += c[u] * x[u][s];
+      __builtin_amdgcn_sched_group_barrier(0x0020, U * S, 0);
+      __builtin_amdgcn_sched_group_barrier(0x0002, U * S * W, 0);
+    }
+    for (; h < e0; ++h) {
+      const uint32_t p = row ^ th[h].flo;
+      const T c = th[h].cs;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
+    }
+    // wave-uniform coefficient: zero ones skipped
+    for (; h < e1; ++h) {
+      const T c = (__builtin_popcount(wbase & th[h].m) & 1u) ? th[h].cd : th[h].cs;
+      if (c == T(0)) continue;
+      const uint32_t p = row ^ th[h].flo;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
+    }
+    for (; h + 2 <= e2; h += 2) {
+      V x0[S], x1[S];
+      const uint32_t p0 = row ^ th[h].flo, p1 = row ^ th[h + 1].flo;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        V r = scur[s] * acc[s];
-        if (uprev) {
+        x0[s] = ldg(ub + s * pstride, p0);
+        x1[s] = ldg(ub + s * pstride, p1);
+      }
+      const T c0 = (__builtin_popcount(row & th[h].m) & 1u) ? th[h].cd : th[h].cs;
+      const T c1 = (__builtin_popcount(row & th[h + 1].m) & 1u) ? th[h + 1].cd : th[h + 1].cs;
 #pragma unroll
-          for (int e = 0; e < W; ++e) r[e] = fma_s(-bps[s][e], up[s][e], r[e]);
-        }
-        stg(out + s * pstride, row, r);
-        if (dots) {
+      for (int s = 0; s < S; ++s) {
+        acc[s] += c0 * x0[s];
+        acc[s] += c1 * x1[s];
+      }
+    }
+    if (h < e2) {
+      const uint32_t p = row ^ th[h].flo;
+      const T c = (__builtin_popcount(row & th[h].m) & 1u) ? th[h].cd : th[h].cs;
 #pragma unroll
-          for (int e = 0; e < W; ++e) dq[s * W + e] += (double)xc[s][e] * (double)r[e];
-        }
+      for (int s = 0; s < S; ++s) acc[s] += c * ldg(ub + s * pstride, p);
+    }
+  }
+
+  double dq[S * W];
+#pragma unroll
+  for (int i = 0; i < S * W; ++i) dq[i] = 0.0;
+  if (valid) {
+    V up[S];
+    if (uprev) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) up[s] = ldg(uprev + s * pstride, row);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      V r = scur_of<T, S>(st, cp, t.panel0, s, plain) * acc[s];
+      if (uprev) {
+        const V bp = bps_of<T, S>(st, cp, t.panel0, s);
+#pragma unroll
+        for (int e = 0; e < W; ++e) r[e] = fma_s(-bp[e], up[s][e], r[e]);
+      }
+      stg(out + s * pstride, row, r);
+      if (dots) {
+#pragma unroll
+        for (int e = 0; e < W; ++e) dq[s * W + e] = (double)xc[s][e] * (double)r[e];
       }
     }
   }
@@ -408,26 +537,31 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs,
 }
 
 // ---------------------------------------------------------------------------
-// reductions of the per-tile partial sums, one thread per column; fixed order.
+// reductions of the per-tile partial sums: one workgroup per (segment,
+// column); lane i sums tiles i, i+256, ... and a fixed binary tree in LDS
+// combines the lanes, so the order never depends on scheduling.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double column_total(const Seg& sg, int c, double (*lds)[64]) {
-  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+__device__ __forceinline__ double column_total(const Seg& sg, int c, double* lds) {
   double s = 0.0;
-  if (c < sg.cpad)
-    for (int t = grp; t < sg.n_row_tiles; t += 4) s += sg.part[(uint64_t)t * sg.cpad + c];
-  lds[grp][cl] = s;
+  for (int t = threadIdx.x; t < sg.n_row_tiles; t += kBlock) s += sg.part[(uint64_t)t * sg.cpad + c];
+  lds[threadIdx.x] = s;
   __syncthreads();
-  return ((lds[0][cl] + lds[1][cl]) + lds[2][cl]) + lds[3][cl];
+#pragma unroll
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  return lds[0];
 }
 
 // beta_{j-1} = |u_j| (or |u_1| -> s_1 at j = 1), breakdown test, scales.
 __global__ __launch_bounds__(kBlock) void k_red_beta(const Seg* __restrict__ segs) {
   const Seg& sg = segs[blockIdx.x];
-  if ((int)blockIdx.y * 64 >= sg.cpad) return;
-  __shared__ double lds[4][64];
-  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int c = blockIdx.y;
+  if (c >= sg.cpad) return;
+  __shared__ double lds[kBlock];
   const double tot = column_total(sg, c, lds);
-  if ((threadIdx.x >> 6) != 0 || c >= sg.cpad) return;
+  if (threadIdx.x != 0) return;
   const int j = sg.stepc[c];
   if (j > sg.k) return;
   const int cp = sg.cpad;
@@ -469,11 +603,11 @@ __global__ __launch_bounds__(kBlock) void k_red_beta(const Seg* __restrict__ seg
 // alpha_j = s_j <u_j, r>; weight alpha_j s_j for the next step; advance.
 __global__ __launch_bounds__(kBlock) void k_red_alpha(const Seg* __restrict__ segs) {
   const Seg& sg = segs[blockIdx.x];
-  if ((int)blockIdx.y * 64 >= sg.cpad) return;
-  __shared__ double lds[4][64];
-  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int c = blockIdx.y;
+  if (c >= sg.cpad) return;
+  __shared__ double lds[kBlock];
   const double tot = column_total(sg, c, lds);
-  if ((threadIdx.x >> 6) != 0 || c >= sg.cpad) return;
+  if (threadIdx.x != 0) return;
   const int j = sg.stepc[c];
   if (j > sg.k) return;
   const int cp = sg.cpad;
@@ -645,36 +779,36 @@ hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStr
 }
 
 template <typename T>
-hipError_t launch_norm(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st) {
+hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   switch (slab) {
-    case 1: hipLaunchKernelGGL((k_norm<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
-    case 2: hipLaunchKernelGGL((k_norm<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
-    default: hipLaunchKernelGGL((k_norm<T, 4>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+    case 1: hipLaunchKernelGGL((k_norm<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
+    case 2: hipLaunchKernelGGL((k_norm<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
+    default: hipLaunchKernelGGL((k_norm<T, 4>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_apply(const Seg* segs, const Tile* tiles, int ntiles, int slab, hipStream_t st) {
+hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   switch (slab) {
-    case 1: hipLaunchKernelGGL((k_apply<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
-    case 2: hipLaunchKernelGGL((k_apply<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
-    default: hipLaunchKernelGGL((k_apply<T, 4>), dim3(ntiles), dim3(kBlock), 0, st, segs, tiles); break;
+    case 1: hipLaunchKernelGGL((k_apply<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
+    case 2: hipLaunchKernelGGL((k_apply<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
+    default: hipLaunchKernelGGL((k_apply<T, 4>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st) {
   if (nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_beta, dim3(nseg, (cmax + 63) / 64), dim3(kBlock), 0, st, segs);
+  hipLaunchKernelGGL(k_red_beta, dim3(nseg, cmax), dim3(kBlock), 0, st, segs);
   return hipGetLastError();
 }
 
 hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st) {
   if (nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_alpha, dim3(nseg, (cmax + 63) / 64), dim3(kBlock), 0, st, segs);
+  hipLaunchKernelGGL(k_red_alpha, dim3(nseg, cmax), dim3(kBlock), 0, st, segs);
   return hipGetLastError();
 }
 
@@ -727,10 +861,10 @@ hipError_t launch_start_block(int ns_log, int nb, int C, uint64_t seed, int kind
 
 template hipError_t launch_diag<float>(const DiagTerm*, int, float*, int, hipStream_t);
 template hipError_t launch_diag<double>(const DiagTerm*, int, double*, int, hipStream_t);
-template hipError_t launch_norm<float>(const Seg*, const Tile*, int, int, hipStream_t);
-template hipError_t launch_norm<double>(const Seg*, const Tile*, int, int, hipStream_t);
-template hipError_t launch_apply<float>(const Seg*, const Tile*, int, int, hipStream_t);
-template hipError_t launch_apply<double>(const Seg*, const Tile*, int, int, hipStream_t);
+template hipError_t launch_norm<float>(const Seg*, int, int, int, hipStream_t);
+template hipError_t launch_norm<double>(const Seg*, int, int, int, hipStream_t);
+template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
+template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);

@@ -104,12 +104,10 @@ struct rdm_server {
   char* arena_mem = nullptr;
   Seg* dsegs = nullptr;
   size_t segs_cap = 0;
-  Tile* dtiles = nullptr;
-  size_t tiles_cap = 0;
   int64_t n_submitted = 0, n_completed = 0, n_steps = 0, peak_active = 0, peak_bytes = 0, used = 0;
 
   void run();
-  rdm_status ensure_tables(size_t nseg, size_t ntiles);
+  rdm_status ensure_tables(size_t nseg);
   void complete(Req* r, rdm_status s);
 };
 
@@ -124,16 +122,11 @@ void rdm_server::complete(Req* r, rdm_status s) {
   cv_done.notify_all();
 }
 
-rdm_status rdm_server::ensure_tables(size_t nseg, size_t ntiles) {
+rdm_status rdm_server::ensure_tables(size_t nseg) {
   if (nseg > segs_cap) {
     if (dsegs) RDM_HIP(hipFree(dsegs));
     segs_cap = std::max<size_t>(nseg, 2 * segs_cap);
     RDM_HIP(hipMalloc(&dsegs, segs_cap * sizeof(Seg)));
-  }
-  if (ntiles > tiles_cap) {
-    if (dtiles) RDM_HIP(hipFree(dtiles));
-    tiles_cap = std::max<size_t>(ntiles, 2 * tiles_cap);
-    RDM_HIP(hipMalloc(&dtiles, tiles_cap * sizeof(Tile)));
   }
   return RDM_OK;
 }
@@ -141,7 +134,6 @@ rdm_status rdm_server::ensure_tables(size_t nseg, size_t ntiles) {
 void rdm_server::run() {
   (void)hipSetDevice(device);
   std::vector<Seg> segs;
-  std::vector<Tile> tiles;
   while (true) {
     std::vector<Req*> admitted;
     {
@@ -190,7 +182,6 @@ void rdm_server::run() {
 
     // segment table of the resident batch
     segs.clear();
-    tiles.clear();
     std::vector<std::pair<int, int>> init_ranges;  // (first seg, phase) of segments to initialise
     int cmax = 0;
     for (Req* r : active) {
@@ -206,23 +197,17 @@ void rdm_server::run() {
         r->need_init = false;
       }
     }
-    const int slab = common_slab(segs);
-    for (size_t i = 0; i < segs.size(); ++i) {
-      seg_tiles(segs[i], (int)i, tiles);
-      cmax = std::max(cmax, segs[i].cpad);
-    }
-    rdm_status s = ensure_tables(segs.size(), tiles.size());
+    const int slab = tuned_slab(prec, segs);
+    const int ntiles = assign_tiles(segs);
+    for (const auto& sg : segs) cmax = std::max(cmax, sg.cpad);
+    rdm_status s = ensure_tables(segs.size());
     if (s == RDM_OK && hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg),
-                                      hipMemcpyHostToDevice, stream) != hipSuccess)
-      s = RDM_E_DEVICE;
-    if (s == RDM_OK && hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(Tile),
                                       hipMemcpyHostToDevice, stream) != hipSuccess)
       s = RDM_E_DEVICE;
     for (auto& ir : init_ranges)
       if (s == RDM_OK && launch_init_state(dsegs + ir.first, 1, cmax, ir.second, stream) != hipSuccess)
         s = RDM_E_DEVICE;
-    if (s == RDM_OK) s = launch_step(prec, dsegs, (int)segs.size(), dtiles, (int)tiles.size(), slab, cmax,
-                                     stream, nullptr);
+    if (s == RDM_OK) s = launch_step(prec, dsegs, (int)segs.size(), ntiles, slab, cmax, stream, nullptr);
     // the host tables must stay valid until the copies above completed
     if (s == RDM_OK && hipStreamSynchronize(stream) != hipSuccess) s = RDM_E_DEVICE;
     ++n_steps;
@@ -329,7 +314,12 @@ extern "C" rdm_status rdm_server_submit(rdm_server* s, const rdm_hamiltonian* h,
   r->out = out;
   r->run.betas.assign(beta, beta + n_beta);
   r->run.seed = seed;
-  const rdm_status ps = plan_instance(r->plan, h, n_beta, n_v, k, s->prec, RDM_AUTO, s->budget, 0, 0);
+  // a request keeps all its Lanczos vectors only if that takes at most a
+  // quarter of the arena; larger ones run two-pass so that several requests
+  // can stay resident together
+  rdm_status ps = plan_instance(r->plan, h, n_beta, n_v, k, s->prec, RDM_AUTO, s->budget / 4, 0, 0);
+  if (ps == RDM_E_NOMEM)
+    ps = plan_instance(r->plan, h, n_beta, n_v, k, s->prec, RDM_TWO_PASS, s->budget, 0, 0);
   if (ps != RDM_OK) {
     delete r;
     return ps;
@@ -409,7 +399,6 @@ extern "C" void rdm_server_destroy(rdm_server* s) {
   if (s->worker.joinable()) s->worker.join();
   for (auto& kv : s->reqs) delete kv.second;
   if (s->dsegs) (void)hipFree(s->dsegs);
-  if (s->dtiles) (void)hipFree(s->dtiles);
   if (s->arena_mem) (void)hipFree(s->arena_mem);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;

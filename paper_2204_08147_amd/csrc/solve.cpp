@@ -5,6 +5,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <thread>
 
 #include "host.h"
@@ -61,14 +64,10 @@ void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int r
   S = std::min(S, kMaxSlab);
   while (S > 1 && (g.P % S) != 0) S >>= 1;
   g.S = std::max(S, 1);
-  int rpl = rpl_opt;
-  if (rpl <= 0) {
-    // enough row tiles to fill 256 CUs several times over
-    const uint64_t slabs = g.P / g.S;
-    const uint64_t want_tiles = 4096;
-    uint64_t r = (g.dim * slabs) / (kBlock * want_tiles);
-    rpl = (int)std::max<uint64_t>(1, std::min<uint64_t>(r, 16));
-  }
+  // the apply stages one partner tile of kBlock rows per workgroup, one row
+  // per lane; the norm kernel uses the same tiles
+  (void)rpl_opt;
+  const int rpl = 1;
   g.rpl = rpl;
   g.n_row_tiles = (int)((g.dim + (uint64_t)kBlock * rpl - 1) / ((uint64_t)kBlock * rpl));
   g.blk = g.dim * g.cpad;
@@ -123,7 +122,7 @@ rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int 
     p.o_y = off; off = al(off + (size_t)n_beta * p.k * p.tot.cpad * sb);
     // Gram tiling
     uint64_t r = (p.tot.dim * p.n_cblocks) / (kBlock * 4096ull);
-    p.g_rpl = (int)std::max<uint64_t>(1, std::min<uint64_t>(r, 16));
+    p.g_rpl = rpl_opt > 0 ? rpl_opt : (int)std::max<uint64_t>(1, std::min<uint64_t>(r, 16));
     p.g_rtiles = (int)((p.tot.dim + (uint64_t)kBlock * p.g_rpl - 1) / ((uint64_t)kBlock * p.g_rpl));
     p.o_gpart = off; off = al(off + (size_t)p.g_rtiles * n_beta * n_v * p.ds * p.ds * 8);
     p.o_gsum = off; off = al(off + (size_t)n_beta * n_v * p.ds * p.ds * 8);
@@ -158,12 +157,14 @@ namespace {
 Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int start_kind, int ns_log,
              int nb, uint64_t seed, double tau) {
   Seg s{};
-  s.hopU = op->hopU;
-  s.hopP = op->hopP;
+  s.hops = op->hops;
+  s.groups = op->groups;
+  s.thin = op->thin;
   s.diag = op->diag;
-  s.nU = op->nU;
-  s.nP = op->nP;
-  s.nPh = op->nPh;
+  s.ngroups = op->ngroups;
+  s.nt0 = op->nt[0];
+  s.nt1 = op->nt[1];
+  s.nt2 = op->nt[2];
   s.nbits = g.nbits;
   s.P = g.P;
   s.S = g.S;
@@ -263,26 +264,25 @@ int common_slab(std::vector<Seg>& segs) {
   return slab;
 }
 
-void seg_tiles(const Seg& sg, int seg_index, std::vector<Tile>& tiles) {
-  // slab-major: the blocks in flight share one group of panels, so the
-  // gathered vector's working set is one slab (dim * S * 16 bytes)
-  const int rows = kBlock * sg.rpl;
-  const int nrt = sg.n_row_tiles;
-  for (int p0 = 0; p0 < sg.P; p0 += sg.S)
-    for (int rt = 0; rt < nrt; ++rt)
-      tiles.push_back(Tile{seg_index, (uint32_t)((uint64_t)rt * rows), p0, rt});
+int assign_tiles(std::vector<Seg>& segs) {
+  int64_t base = 0;
+  for (auto& sg : segs) {
+    sg.tile_base = (int32_t)base;
+    base += (int64_t)sg.n_row_tiles * (sg.P / sg.S);
+  }
+  return (int)base;
 }
 
-rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Tile* dtiles, int ntiles, int slab,
-                       int cmax, hipStream_t st, StepTimers* tm) {
+rdm_status launch_step(int prec, const Seg* dsegs, int nseg, int ntiles, int slab, int cmax, hipStream_t st,
+                       StepTimers* tm) {
   if (tm) RDM_HIP(tm->norm.mark(st));
-  RDM_HIP(prec == RDM_FP64 ? launch_norm<double>(dsegs, dtiles, ntiles, slab, st)
-                           : launch_norm<float>(dsegs, dtiles, ntiles, slab, st));
+  RDM_HIP(prec == RDM_FP64 ? launch_norm<double>(dsegs, nseg, ntiles, slab, st)
+                           : launch_norm<float>(dsegs, nseg, ntiles, slab, st));
   if (tm) RDM_HIP(tm->norm.mark(st));
   RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
-  RDM_HIP(prec == RDM_FP64 ? launch_apply<double>(dsegs, dtiles, ntiles, slab, st)
-                           : launch_apply<float>(dsegs, dtiles, ntiles, slab, st));
+  RDM_HIP(prec == RDM_FP64 ? launch_apply<double>(dsegs, nseg, ntiles, slab, st)
+                           : launch_apply<float>(dsegs, nseg, ntiles, slab, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(launch_red_alpha(dsegs, nseg, cmax, st));
   return RDM_OK;
@@ -408,59 +408,134 @@ rdm_status gram_phase(InstRun& r, hipStream_t st, Timers* tg) {
   return RDM_OK;
 }
 
-// Tiles of a segment when a launch lowers its slab to one panel per lane (the
-// most a shared launch can ever create for it).
-size_t max_tiles(const SegPlan& g) { return (size_t)g.n_row_tiles * g.P; }
-
-size_t batch_tile_capacity(const std::vector<InstPlan>& plans) {
-  size_t nt = 0;
-  for (auto& p : plans) nt += max_tiles(p.tot) + max_tiles(p.bath);
-  return std::max<size_t>(nt, 1);
-}
-
 size_t batch_header_bytes(const std::vector<InstPlan>& plans) {
-  return al(sizeof(Seg) * 2 * plans.size()) + al(sizeof(Tile) * batch_tile_capacity(plans));
+  return al(sizeof(Seg) * 2 * plans.size());
 }
 
-rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, size_t tile_cap, int prec,
-                     int phase, hipStream_t st, StepTimers* tm) {
-  if (hsegs.empty()) return RDM_OK;
-  std::vector<Tile> tiles;
-  int kmax = 0, cmax = 0;
-  const int slab = common_slab(hsegs);
-  for (size_t i = 0; i < hsegs.size(); ++i) {
-    seg_tiles(hsegs[i], (int)i, tiles);
-    kmax = std::max(kmax, hsegs[i].k);
-    cmax = std::max(cmax, hsegs[i].cpad);
+namespace {
+
+// Panels per lane chosen by measurement, per shape of the largest segment of a
+// launch (the slab never changes results, only speed).
+struct SlabKey {
+  int prec, nbits, cpad, ngroups, nthin;
+  bool operator<(const SlabKey& o) const {
+    return std::tie(prec, nbits, cpad, ngroups, nthin) < std::tie(o.prec, o.nbits, o.cpad, o.ngroups, o.nthin);
   }
-  if (tiles.size() > tile_cap) {
-    set_error("internal: tile table of " + std::to_string(tiles.size()) + " entries exceeds its buffer (" +
-              std::to_string(tile_cap) + ")");
-    return RDM_E_INVALID;
+};
+std::mutex g_slab_mu;
+std::map<SlabKey, int> g_slab_best;
+
+SlabKey slab_key(int prec, const std::vector<Seg>& segs) {
+  const Seg* big = &segs[0];
+  for (const auto& sg : segs)
+    if (((uint64_t)sg.cpad << sg.nbits) > ((uint64_t)big->cpad << big->nbits)) big = &sg;
+  return SlabKey{prec, big->nbits, big->cpad, big->ngroups, big->nt0 + big->nt1 + big->nt2};
+}
+
+void set_slab(std::vector<Seg>& segs, int slab) {
+  for (auto& sg : segs) sg.S = slab;
+}
+
+}  // namespace
+
+int tuned_slab(int prec, std::vector<Seg>& segs) {
+  const int smax = common_slab(segs);
+  std::lock_guard<std::mutex> lk(g_slab_mu);
+  auto it = g_slab_best.find(slab_key(prec, segs));
+  const int s = it == g_slab_best.end() ? 1 : std::min(it->second, smax);
+  set_slab(segs, s);
+  return s;
+}
+
+rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
+                     StepTimers* tm, bool tune) {
+  if (hsegs.empty()) return RDM_OK;
+  int kmax = 0, cmax = 0;
+  for (const auto& sg : hsegs) {
+    kmax = std::max(kmax, sg.k);
+    cmax = std::max(cmax, sg.cpad);
   }
   const int nseg = (int)hsegs.size();
+  int slab = common_slab(hsegs);
+  int j = 1;
+  if (tune) {
+    const SlabKey key = slab_key(prec, hsegs);
+    int cached = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_slab_mu);
+      auto it = g_slab_best.find(key);
+      if (it != g_slab_best.end()) cached = it->second;
+    }
+    std::vector<int> cands;
+    for (int c = 1; c <= slab; c *= 2) cands.push_back(c);
+    const int reps = 2;
+    if (cached > 0) {
+      slab = std::min(cached, slab);
+    } else if (cands.size() > 1 && kmax >= 2 + reps * (int)cands.size()) {
+      // steps 2.. run each candidate `reps` times between events; the best
+      // one is kept for the remaining steps and for later launches of the
+      // same shape
+      std::vector<std::vector<Seg>> tabs(cands.size(), hsegs);
+      std::vector<int> nt(cands.size());
+      for (size_t c = 0; c < cands.size(); ++c) {
+        set_slab(tabs[c], cands[c]);
+        nt[c] = assign_tiles(tabs[c]);
+      }
+      std::vector<hipEvent_t> ev(2 * cands.size());
+      for (auto& e : ev) RDM_HIP(hipEventCreate(&e));
+      rdm_status s = RDM_OK;
+      RDM_HIP(hipMemcpyAsync(dsegs, tabs[0].data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
+      RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
+      s = launch_step(prec, dsegs, nseg, nt[0], cands[0], cmax, st, tm);
+      ++j;
+      for (size_t c = 0; c < cands.size() && s == RDM_OK; ++c) {
+        RDM_HIP(hipMemcpyAsync(dsegs, tabs[c].data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
+        RDM_HIP(hipEventRecord(ev[2 * c], st));
+        for (int r = 0; r < reps && s == RDM_OK; ++r, ++j) s = launch_step(prec, dsegs, nseg, nt[c], cands[c], cmax, st, tm);
+        RDM_HIP(hipEventRecord(ev[2 * c + 1], st));
+      }
+      RDM_HIP(hipStreamSynchronize(st));
+      int best = 0;
+      float best_ms = 1e30f;
+      for (size_t c = 0; c < cands.size(); ++c) {
+        float ms = 0.f;
+        RDM_HIP(hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = (int)c;
+        }
+      }
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      if (s != RDM_OK) return s;
+      slab = cands[best];
+      std::lock_guard<std::mutex> lk(g_slab_mu);
+      g_slab_best[key] = slab;
+    } else {
+      slab = 1;
+    }
+  }
+  set_slab(hsegs, slab);
+  const int ntiles = assign_tiles(hsegs);
   RDM_HIP(hipMemcpyAsync(dsegs, hsegs.data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
-  RDM_HIP(hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
-  RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
-  for (int j = 1; j <= kmax; ++j) {
-    rdm_status s = launch_step(prec, dsegs, nseg, dtiles, (int)tiles.size(), slab, cmax, st, tm);
+  if (j == 1) RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
+  for (; j <= kmax; ++j) {
+    rdm_status s = launch_step(prec, dsegs, nseg, ntiles, slab, cmax, st, tm);
     if (s != RDM_OK) return s;
   }
-  // the host vectors above must outlive the asynchronous copies
+  // the host table above must outlive the asynchronous copy
   RDM_HIP(hipStreamSynchronize(st));
   return RDM_OK;
 }
 
-rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile) {
+rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
+                   bool tune) {
   const int ni = (int)runs.size();
   if (ni == 0) return RDM_OK;
   const int prec = runs[0].plan->prec;
   std::vector<InstPlan> plans;
   for (auto& r : runs) plans.push_back(*r.plan);
   const size_t header = batch_header_bytes(plans);
-  const size_t tile_cap = batch_tile_capacity(plans);
   Seg* dsegs = (Seg*)ws;
-  Tile* dtiles = (Tile*)(ws + al(sizeof(Seg) * 2 * ni));
   size_t inst_off = header;
   for (auto& r : runs) {
     r.base = ws + inst_off;
@@ -476,14 +551,14 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     segs.push_back(seg_of(r, 0, MODE_LANCZOS, tau));
     segs.push_back(seg_of(r, 1, MODE_LANCZOS, tau));
   }
-  rdm_status s = run_phase(segs, dsegs, dtiles, tile_cap, prec, 0, st, profile ? &tm : nullptr);
+  rdm_status s = run_phase(segs, dsegs, prec, 0, st, profile ? &tm : nullptr, tune);
   if (s != RDM_OK) return s;
   for (auto& r : runs) r.status = host_phase(r, st);
   // pass 2 (two-pass plans): regenerate u_j from the stored coefficients
   segs.clear();
   for (auto& r : runs)
     if (r.plan->two_pass && r.status == RDM_OK) segs.push_back(seg_of(r, 0, MODE_REGEN, tau));
-  if ((s = run_phase(segs, dsegs, dtiles, tile_cap, prec, 1, st, nullptr)) != RDM_OK) return s;
+  if ((s = run_phase(segs, dsegs, prec, 1, st, nullptr, tune)) != RDM_OK) return s;
   Timers tg;
   tg.on = profile;
   for (auto& r : runs) {
@@ -581,18 +656,12 @@ rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uin
                         int slab, int rpl, double tau, hipStream_t st, double* alpha, double* beta,
                         int32_t* kc) {
   SegPlan g;
-  size_t off = al(sizeof(Seg));
-  const size_t o_tiles = off;
   const int nbits = which == 0 ? h->n : h->n_b;
   const int C = which == 0 ? (1 << h->n_s) * n_v : n_v;
   const int kk = (int)std::min<uint64_t>((uint64_t)k, 1ull << nbits);
-  // tiles first need the geometry; plan into a scratch offset, then shift
-  size_t tmp = 0;
-  plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, tmp);
-  const size_t ntiles = max_tiles(g);
-  off = al(o_tiles + ntiles * sizeof(Tile));
-  const size_t base_off = off;
-  off += tmp;
+  const size_t base_off = al(sizeof(Seg));
+  size_t off = base_off;
+  plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, off);
   char* ws = nullptr;
   RDM_HIP(hipMalloc(&ws, off));
   const OpDevice* op = nullptr;
@@ -602,11 +671,13 @@ rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uin
     return s;
   }
   std::vector<Seg> segs;
-  segs.push_back(make_seg(g, op, ws + base_off, MODE_LANCZOS, which == 0 ? START_SYSBATH : START_BATH,
-                          h->n_s, h->n_b, seed, tau));
-  s = run_phase(segs, (Seg*)ws, (Tile*)(ws + o_tiles), ntiles, prec, 0, st, nullptr);
+  // plan_seg laid the segment out from offset base_off, so its offsets are
+  // relative to ws itself
+  segs.push_back(make_seg(g, op, ws, MODE_LANCZOS, which == 0 ? START_SYSBATH : START_BATH, h->n_s, h->n_b,
+                          seed, tau));
+  s = run_phase(segs, (Seg*)ws, prec, 0, st, nullptr, slab == 0);
   HostHist hh;
-  if (s == RDM_OK) s = fetch_hist(g, ws + base_off, hh, st);
+  if (s == RDM_OK) s = fetch_hist(g, ws, hh, st);
   if (s == RDM_OK && hipStreamSynchronize(st) != hipSuccess) {
     set_error("hipStreamSynchronize failed");
     s = RDM_E_DEVICE;

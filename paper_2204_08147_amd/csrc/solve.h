@@ -82,20 +82,25 @@ void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int r
               size_t& off);
 rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
                          int mode_req, uint64_t budget, int slab_opt, int rpl_opt);
-size_t max_tiles(const SegPlan& g);
-size_t batch_tile_capacity(const std::vector<InstPlan>& plans);
 size_t batch_header_bytes(const std::vector<InstPlan>& plans);
-rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile);
+rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
+                   bool tune);
 
 // Phases (used by execute and by the serving engine).
 rdm_status bind_ops(InstRun& r, hipStream_t st);
 Seg seg_of(const InstRun& r, int which, int mode, double tau);
 int common_slab(std::vector<Seg>& segs);
-void seg_tiles(const Seg& sg, int seg_index, std::vector<Tile>& tiles);
-rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Tile* dtiles, int ntiles, int slab,
-                       int cmax, hipStream_t st, StepTimers* tm);
-rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, Tile* dtiles, size_t tile_cap, int prec,
-                     int phase, hipStream_t st, StepTimers* tm);
+// sets every segment's tile_base; returns the workgroups of a norm/apply launch
+int assign_tiles(std::vector<Seg>& segs);
+rdm_status launch_step(int prec, const Seg* dsegs, int nseg, int ntiles, int slab, int cmax, hipStream_t st,
+                       StepTimers* tm);
+// Runs every step of a phase.  tune: choose the panels per lane by timing the
+// first steps (cached per shape); otherwise the segments' own value is used.
+rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
+                     StepTimers* tm, bool tune);
+// Panels per lane for a launch over these segments: the cached measurement
+// for the shape of the largest one, else one panel.
+int tuned_slab(int prec, std::vector<Seg>& segs);
 rdm_status host_phase(InstRun& r, hipStream_t st);   // synchronous
 rdm_status gram_phase(InstRun& r, hipStream_t st, Timers* tg);  // synchronous
 rdm_status finalize(const InstRun& r, rdm_result* out);

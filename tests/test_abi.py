@@ -41,6 +41,14 @@ def test_hamiltonian_tables():
     assert info["diag_terms"] == n * (n - 1) // 2
     nb = inst.n_b
     assert info["bath_hops_uniform"] == nb * (nb - 1) // 2 + nb
+    # partner tiles (flip bits above a 256-row tile): the own tile and one per
+    # single high bit (8 pair hops + 1 field each) are staged in LDS; a pair of
+    # high bits is used by a single hop, which is gathered directly
+    hi = n - 8
+    assert info["tile_groups"] == 1 + hi
+    assert info["direct_hops"] == hi * (hi - 1) // 2
+    full = rdm.Hamiltonian.from_instance(cfg_long_range(0)).info()
+    assert full["tile_groups"] == 13 and full["direct_hops"] == 66
     # XXZ with J^x = J^y: parity-dependent hops
     h2 = rdm.Hamiltonian.from_instance(cfg_small_chain())
     i2 = h2.info()
