@@ -88,7 +88,13 @@ def cpu_baseline(inst, budget_s=20.0):
     """The oracle's FP64 Lanczos path (as it stands) on a bounded sample: a few
     Lanczos steps of one start column, scaled to a full solve (every column,
     k steps, plus the bath run)."""
+    from threadpoolctl import threadpool_limits
     from oracle import exact, lanczos as olz, spin
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(inst, budget_s, exact, olz, spin)
+
+
+def _cpu_baseline(inst, budget_s, exact, olz, spin):
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
     x0 = exact.start_columns(inst)[:, 0]
     t0 = time.perf_counter()
@@ -106,7 +112,7 @@ def cpu_baseline(inst, budget_s=20.0):
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} FP64 Lanczos steps of 1 of {inst.n_cols} start columns "
                       f"(dim 2^{inst.n}), {t:.1f} s, scaled x{inst.k / steps:.0f} steps "
-                      f"x{cols:.2f} columns (NumPy, single-threaded element-wise kernels)"}
+                      f"x{cols:.2f} columns (NumPy, BLAS limited to one thread)"}
 
 
 def apply_work(insts, prec_bytes):

@@ -196,7 +196,8 @@ rdm_status rdm_batch_workspace_size(int32_t n_items, rdm_batch_item* items, cons
  * matrix-free spin-Hamiltonian apply of the hot path (H is accessed only
  * through such products, Section "Past algorithms").  x, y: device, panel
  * layout above with n_cols columns, FP64 (precision RDM_FP64) or FP32
- * (RDM_MIXED); x and y must not overlap.  Asynchronous on hip_stream. */
+ * (RDM_MIXED); x and y must not overlap.  Runs on hip_stream and returns
+ * after it completes (blocking). */
 rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t precision, int32_t n_cols,
                      const void* x, void* y, const rdm_options* opt, void* hip_stream);
 
