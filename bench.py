@@ -53,13 +53,6 @@ def parse():
     return ap.parse_args()
 
 
-def nnz_per_row(info_tot):
-    """Average non-zeros per row of H: the diagonal, every uniform hop, and the
-    parity hops weighted by how often their coefficient is non-zero (1/2 for
-    XXZ pairs with J^x = J^y)."""
-    return 1 + info_tot["hops_uniform"] + info_tot["hops_parity_nonzero"]
-
-
 def kernel_source_hash():
     src = open(os.path.join(ROOT, "paper_2204_08147_amd", "csrc", "kernels.hip"), "rb").read()
     return hashlib.sha256(src).hexdigest()[:16]
@@ -115,20 +108,40 @@ def _cpu_baseline(inst, budget_s, exact, olz, spin):
                       f"x{cols:.2f} columns (NumPy, BLAS limited to one thread)"}
 
 
+def operator_work(nbits, cols, nnz, transform, s, k):
+    """Algorithmic bytes and flops of one apply launch on one operator (2^nbits
+    rows, cols columns padded to whole 16-byte panels, s bytes per scalar),
+    averaged over k steps (the previous vector is absent at the first step).
+
+    Hop tables: read u_j and u_(j-1), write r, read the diagonal once:
+    (2 + (k-1)/k) vectors + dim*s bytes; 2*nnz flops per element.
+    Transform (D_Z + W D_X W, three passes over each 16-byte panel):
+    A reads u and writes t, B reads and writes t and reads D_X, C reads t, u,
+    u_(j-1) and D_Z and writes r: (7 + (k-1)/k) vectors + 2 diagonals per
+    panel; 2*nbits + 4 flops per element."""
+    dim = 1 << nbits
+    w = 16 // s
+    cp = (cols + w - 1) // w * w
+    vec = dim * cp * s
+    prev = (k - 1) / k
+    if transform:
+        return vec * (7 + prev) + 2 * (cp // w) * dim * s, (2.0 * nbits + 4) * dim * cp
+    return vec * (2 + prev) + dim * s, 2.0 * nnz * dim * cols
+
+
 def apply_work(insts, prec_bytes):
     """Algorithmic bytes and flops of one apply launch over the H_t and H_b
-    segments of the given instances (averaged over the k steps: the previous
-    vector is absent at the first step)."""
+    segments of the given instances."""
     import paper_2204_08147_amd as rdm
     by = fl = 0.0
     for inst in insts:
         info = rdm.Hamiltonian.from_instance(inst).info()
         nnz = 1 + info["hops_uniform"] + 0.5 * info["hops_parity"]
         nnz_b = 1 + info["bath_hops_uniform"] + 0.5 * info["bath_hops_parity"]
-        prev = (inst.k - 1) / inst.k
-        for dim, cols, z in ((inst.dim, inst.n_cols, nnz), (inst.d_b, inst.n_v, nnz_b)):
-            by += dim * cols * prec_bytes * (2 + prev) + dim * prec_bytes
-            fl += 2.0 * z * dim * cols
+        b1, f1 = operator_work(inst.n, inst.n_cols, nnz, info["transform"], prec_bytes, inst.k)
+        b2, f2 = operator_work(inst.n_b, inst.n_v, nnz_b, info["bath_transform"], prec_bytes, inst.k)
+        by += b1 + b2
+        fl += f1 + f2
     return by, fl
 
 
@@ -358,32 +371,12 @@ def main():
 
     # roofline of the dominant kernel: the apply launch (H_t and H_b segments)
     info = hs[0].info()
-    info["hops_parity_nonzero"] = info["hops_parity"] * 0.5
-    nnz = nnz_per_row(info)
-    infob = {"hops_uniform": info["bath_hops_uniform"],
-             "hops_parity_nonzero": info["bath_hops_parity"] * 0.5}
-    nnz_b = nnz_per_row(infob)
-    dim, db, C, nv, k = inst0.dim, inst0.d_b, inst0.n_cols, inst0.n_v, inst0.k
-    s32 = 4
-    # per launch (average over the k steps): read u_j, read u_{j-1} (absent at
-    # j = 1), write r, read the diagonal
-    prev_frac = (k - 1) / k
-    bytes_tot = dim * C * s32 * (2 + prev_frac) + dim * s32
-    bytes_bath = db * nv * s32 * (2 + prev_frac) + db * s32
-    flops = 2.0 * nnz * dim * C + 2.0 * nnz_b * db * nv
+    nnz = 1 + info["hops_uniform"] + 0.5 * info["hops_parity"]
+    bytes_alg, flops = apply_work([inst0], 4)
     t_apply = float(np.mean(ap_m)) * 1e-3
-    achieved_tflops = flops / t_apply / 1e12
-    achieved_gbs = (bytes_tot + bytes_bath) / t_apply / 1e9
-    t_hbm = (bytes_tot + bytes_bath) / (HBM_PEAK_GBS * 1e9)
-    t_alu = flops / (VALU_PEAK_TFLOPS * 1e12)
+    achieved_gbs = bytes_alg / t_apply / 1e9
     traffic = read_traffic("apply_lr_xxzz_2+18_mixed_counters.txt")
-    if t_alu >= t_hbm:
-        roof = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / VALU_PEAK_TFLOPS, 4),
-                "traffic": traffic}
-    else:
-        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+    roof = roofline(bytes_alg, flops, t_apply, traffic)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -397,7 +390,8 @@ def main():
         "config": {"workload": f"long-range XX+ZZ, N_s=2 + N_b={args.n_b} (dim 2^{2 + args.n_b}), "
                                "J_ij=|i-j|^-1.5, x-field h in {0.5,1.0,1.5}, beta in {0.5,1,2,4}, "
                                "n_v=16 Rademacher, k=60; one step = the three fields",
-                   "solves_per_step": len(insts), "n_columns": C, "nnz_per_row": nnz},
+                   "solves_per_step": len(insts), "n_columns": inst0.n_cols, "nnz_per_row": nnz,
+                   "apply": "transform (D_Z + W D_X W, 3 passes)" if info["transform"] else "hop tables"},
         "p50_ms": round(1e3 * float(np.percentile(lat_m, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat_m, 99)), 3),
         "apply_gbs_algorithmic": round(achieved_gbs, 1),

@@ -126,8 +126,11 @@ void rdm_hamiltonian_destroy(rdm_hamiltonian* h);
  * [6..8] the same three counts for H_b, [9] / [10] partner-tile groups the
  * apply kernel stages in LDS for H_t / H_b (hops grouped by their flip bits
  * above a 256-row tile; the own tile plus every tile read by at least three
- * hops), [11] / [12] hops it gathers directly from memory instead.
- * out: host array of 13 int64. */
+ * hops), [11] / [12] hops it gathers directly from memory instead, [13] /
+ * [14] 1 when H_t / H_b is applied as D_Z + W D_X W instead (every
+ * off-diagonal term X-type, i.e. J^y = 0 on every pair, and 16..20 sites; W
+ * is the Walsh-Hadamard transform, in whose basis X-type terms are diagonal).
+ * out: host array of 15 int64. */
 rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* out);
 
 /* Full solve (blocking; results on the host).  beta: host array of n_beta

@@ -96,11 +96,11 @@ class Hamiltonian:
         return cls(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
 
     def info(self) -> dict:
-        out = (C.c_int64 * 13)()
+        out = (C.c_int64 * 15)()
         _check(LIB.rdm_hamiltonian_info(self.handle, out), "rdm_hamiltonian_info")
         keys = ["n", "n_s", "n_b", "hops_uniform", "hops_parity", "diag_terms",
                 "bath_hops_uniform", "bath_hops_parity", "bath_diag_terms", "tile_groups",
-                "bath_tile_groups", "direct_hops", "bath_direct_hops"]
+                "bath_tile_groups", "direct_hops", "bath_direct_hops", "transform", "bath_transform"]
         return dict(zip(keys, list(out)))
 
     def close(self):

@@ -316,15 +316,9 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   const int nbits = which == 0 ? h->n : h->n_b;
   plan_seg(g, nbits, n_cols, 1, precision, o.slab, o.rpl, 1, off);
   Seg sg{};
-  sg.hops = op->hops;
-  sg.groups = op->groups;
-  sg.thin = op->thin;
-  sg.diag = op->diag;
-  sg.ngroups = op->ngroups;
-  sg.nt0 = op->nt[0];
-  sg.nt1 = op->nt[1];
-  sg.nt2 = op->nt[2];
   sg.nbits = nbits;
+  sg.n_row_tiles = g.n_row_tiles;
+  bind_apply(sg, op);
   sg.P = g.P;
   sg.S = g.S;
   sg.rpl = g.rpl;
@@ -335,9 +329,8 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   sg.blk = g.blk;
   sg.Q = (void*)x;
   sg.R = y;
-  sg.n_row_tiles = g.n_row_tiles;
   std::vector<Seg> one{sg};
-  const int ntiles = assign_tiles(one);
+  const Launch L = assign_tiles(one);
   sg = one[0];
   static_assert(sizeof(Seg) <= 256, "segment descriptor must fit its 256-byte buffer");
   char* d = nullptr;
@@ -345,10 +338,13 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   rdm_status r = RDM_OK;
   auto run = [&]() -> rdm_status {
     RDM_HIP(hipMemcpyAsync(d, &sg, sizeof(Seg), hipMemcpyHostToDevice, st));
-    if (precision == RDM_FP64)
-      RDM_HIP(launch_apply<double>((Seg*)d, 1, ntiles, g.S, st));
-    else
-      RDM_HIP(launch_apply<float>((Seg*)d, 1, ntiles, g.S, st));
+    if (precision == RDM_FP64) {
+      RDM_HIP(launch_apply<double>((Seg*)d, 1, L.apply, g.S, st));
+      RDM_HIP(launch_apply_xz<double>((Seg*)d, 1, L.xz, st));
+    } else {
+      RDM_HIP(launch_apply<float>((Seg*)d, 1, L.apply, g.S, st));
+      RDM_HIP(launch_apply_xz<float>((Seg*)d, 1, L.xz, st));
+    }
     RDM_HIP(hipStreamSynchronize(st));
     return RDM_OK;
   };

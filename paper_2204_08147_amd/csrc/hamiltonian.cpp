@@ -108,6 +108,12 @@ void compile(const rdm_hamiltonian& h, int first_site, OpTables& t) {
     for (int h = gr.start; uni && h < gr.start + gr.n1; ++h) uni = (t.g_m[h] & lo_mask) == 0u;
     gr.tile_uniform = uni ? 1 : 0;
   }
+  // an operator whose hops are all X-type (no YY part, so every coefficient
+  // is independent of the bits) is D_Z + W D_X W / 2^N with W the Hadamard
+  // transform; D_X has one term per hop, c (1 - 2 parity(s & f))
+  t.xz = t.pf.empty() && !t.uf.empty() && t.nbits >= kXzMinBits && t.nbits <= kXzMaxBits;
+  if (t.xz)
+    for (size_t i = 0; i < t.uf.size(); ++i) t.xterms.push_back(DiagTerm{t.uf[i], 0, std::ldexp(t.uc[i], -t.nbits)});
   for (int k = 0; k < 3; ++k) {
     t.nt[k] = (int)thin[k].size();
     for (const H& x : thin[k]) {
@@ -143,6 +149,14 @@ rdm_status upload(const OpTables& t, OpDevice& d, hipStream_t st) {
     RDM_HIP(hipMemcpyAsync(d.dterms, t.diag.data(), t.diag.size() * sizeof(DiagTerm),
                            hipMemcpyHostToDevice, st));
   RDM_HIP(launch_diag<T>((const DiagTerm*)d.dterms, (int)t.diag.size(), (T*)d.diag, t.nbits, st));
+  d.xz = t.xz;
+  if (t.xz) {
+    RDM_HIP(hipMalloc(&d.xterms, t.xterms.size() * sizeof(DiagTerm)));
+    RDM_HIP(hipMalloc(&d.dx, dim * sizeof(T)));
+    RDM_HIP(hipMemcpyAsync(d.xterms, t.xterms.data(), t.xterms.size() * sizeof(DiagTerm),
+                           hipMemcpyHostToDevice, st));
+    RDM_HIP(launch_diag<T>((const DiagTerm*)d.xterms, (int)t.xterms.size(), (T*)d.dx, t.nbits, st));
+  }
   RDM_HIP(hipStreamSynchronize(st));
   d.ngroups = (int)t.groups.size();
   d.ready = true;
@@ -154,6 +168,8 @@ void free_dev(rdm::OpDevice& d) {
   if (d.groups) (void)hipFree(d.groups);
   if (d.thin) (void)hipFree(d.thin);
   if (d.diag) (void)hipFree(d.diag);
+  if (d.dx) (void)hipFree(d.dx);
+  if (d.xterms) (void)hipFree(d.xterms);
   if (d.dterms) (void)hipFree(d.dterms);
   d = rdm::OpDevice{};
 }
@@ -259,6 +275,7 @@ extern "C" rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* ou
     out[5 + 3 * w] = (int64_t)h->op[w].diag.size();
     out[9 + w] = (int64_t)h->op[w].groups.size();
     out[11 + w] = (int64_t)h->op[w].t_f.size();
+    out[13 + w] = h->op[w].xz ? 1 : 0;
   }
   return RDM_OK;
 }

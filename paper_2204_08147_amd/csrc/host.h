@@ -38,6 +38,10 @@ struct OpTables {
   std::vector<uint32_t> t_f, t_m;
   std::vector<double> t_cs, t_cd;
   int nt[3] = {0, 0, 0};
+  // transform apply (only X-type off-diagonal terms, kXzMinBits..kXzMaxBits
+  // bits): D_X terms, coefficients already scaled by 2^-nbits
+  bool xz = false;
+  std::vector<DiagTerm> xterms;
 };
 
 // Device copy of an operator's tables in one precision.
@@ -51,6 +55,9 @@ struct OpDevice {
   void* diag = nullptr;
   void* dterms = nullptr;
   int ngroups = 0;
+  bool xz = false;
+  void* dx = nullptr;      // D_X / 2^N per row (transform apply)
+  void* xterms = nullptr;
 };
 
 }  // namespace rdm

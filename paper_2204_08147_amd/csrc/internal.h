@@ -29,6 +29,10 @@ enum { MODE_LANCZOS = 0, MODE_REGEN = 1, MODE_PLAIN = 2 };
 enum { START_SYSBATH = 0, START_BATH = 1 };
 
 constexpr int kTileBits = 8;       // the apply stages 2^8 = kBlock-row partner tiles in LDS
+constexpr int kXzTileBits = 12;    // transform apply: 4096-element tiles ...
+constexpr int kXzRegs = 16;        // ... as kBlock lanes x 16 registers
+constexpr int kXzMinBits = 16;     // operators on 16..20 bits use the transform apply
+constexpr int kXzMaxBits = 20;
 constexpr int kFatGroup = 3;       // partner tiles read by at least this many hops go through LDS
 
 // One off-diagonal term of H as the apply sees it: row idx couples to the
@@ -83,7 +87,13 @@ struct Seg {
   int32_t nb;          // bath bits (RNG index range)
   int32_t n_beta;      // psi blocks (MODE_REGEN)
   int32_t n_row_tiles; // partial-sum rows (= row tiles of kBlock rows)
-  int32_t tile_base;   // first workgroup of this segment in a norm/apply launch
+  int32_t tile_base;   // first workgroup of this segment in a norm launch
+  int32_t ap_base;     // first workgroup of this segment in a (256-row) apply launch
+  int32_t ap_rows;     // partial-sum rows the apply writes (row tiles of its kind)
+  int32_t xz;          // 1: transform apply (D_Z + W D_X W), 0: hop tables
+  int32_t x_tiles;     // transform apply: tiles of 2^kXzTileBits rows
+  int32_t x_base;      // transform apply: first workgroup of this segment
+  const void* dx;      // transform apply: D_X / 2^N per row, in T
   uint64_t seed;
   uint64_t blk;        // elements per vector block = dim * cpad
   void* Q;
@@ -132,6 +142,9 @@ template <typename T>
 hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 template <typename T>
 hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
+// the three passes of the transform apply over the segments with xz = 1
+template <typename T>
+hipError_t launch_apply_xz(const Seg* segs, int nseg, int ntiles, hipStream_t st);
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st);

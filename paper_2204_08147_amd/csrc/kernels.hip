@@ -140,16 +140,17 @@ __device__ __forceinline__ typename PanelT<T>::V bps_of(const CONST_AS double* s
 // The tile of this workgroup: binary search of blockIdx.x in the segments'
 // tile_base offsets (uniform, scalar loads), then slab-major inside the
 // segment so the workgroups in flight share one group of panels.
+template <bool APPLY>
 __device__ __forceinline__ Tile tile_of(const Seg* segs, int nseg) {
   const CONST_AS Seg* cs = (const CONST_AS Seg*)segs;
   const int b = (int)blockIdx.x;
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (cs[mid].tile_base <= b) lo = mid;
+    if ((APPLY ? cs[mid].ap_base : cs[mid].tile_base) <= b) lo = mid;
     else hi = mid - 1;
   }
-  const int lt = b - cs[lo].tile_base;
+  const int lt = b - (APPLY ? cs[lo].ap_base : cs[lo].tile_base);
   const int nrt = cs[lo].n_row_tiles;
   const int sl = lt / nrt, rt = lt - sl * nrt;
   return Tile{lo, (uint32_t)rt * (uint32_t)kBlock, sl * cs[lo].S, rt};
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_norm(const Seg* __restrict__ segs, i
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
   __shared__ double lds[4 * S * W];
-  const Tile t = tile_of(segs, nseg);
+  const Tile t = tile_of<false>(segs, nseg);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const int j = sg.stepc[0];
   if (j > sg.k) return;
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
   constexpr int W = PanelT<T>::W;
   __shared__ V tl[2][S][kBlock];
   __shared__ double lds[4 * S * W];
-  const Tile t = tile_of(segs, nseg);
+  const Tile t = tile_of<true>(segs, nseg);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const bool plain = sg.mode == MODE_PLAIN;
   int j = 1;
@@ -537,13 +538,183 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
 }
 
 // ---------------------------------------------------------------------------
+// Transform apply for operators whose off-diagonal part has only X-type terms
+// (XX couplings and x-fields, no YY): in the Hadamard basis such a term is
+// diagonal, so H = D_Z + W D_X W with W the unnormalised Walsh-Hadamard
+// transform on all N bits and D_X (with the 2^-N of W^2 folded in) the X-term
+// energies.  The product runs as three streaming passes over the panel, each
+// workgroup transforming a 4096-row tile in registers and LDS:
+//   A: t = W_lo u            (bits 0..11, contiguous tiles)
+//   B: t = W_hi D_X W_hi t   (bits 12..N-1, tiles of 2^(24-N)-row runs)
+//   C: r = s_j (D_Z u + W_lo t) - beta s u_{j-1}, partial <u_j, r>
+// t lives in the output block R (each workgroup rewrites only its own rows).
+//
+// A tile is 4096 elements indexed by a 12-bit coordinate tau; lane l holds 16
+// of them in registers q.  Three arrangements: 0: tau = q*256 + l (q = bits
+// 8..11); 1: tau = l*16 + q (q = bits 0..3); 2: q = bits 4..7, l = bits 0..3
+// and 8..11.  Butterflies act on register bits; an LDS round trip changes the
+// arrangement.  The LDS slot of tau is tau ^ ((tau >> 4) & 15), which keeps
+// every 16-lane group of a 16-byte access on distinct banks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xz_tau(int arr, uint32_t l, int q) {
+  return arr == 0 ? (uint32_t)q * 256u + l
+       : arr == 1 ? (l << 4) | (uint32_t)q
+                  : (l & 15u) | ((uint32_t)q << 4) | ((l >> 4) << 8);
+}
+__device__ __forceinline__ uint32_t xz_slot(uint32_t tau) { return tau ^ ((tau >> 4) & 15u); }
+
+// butterflies (a, b) -> (a + b, a - b) over the register bits set in mask
+template <typename V>
+__device__ __forceinline__ void xz_bfly(V (&v)[kXzRegs], int mask) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!((mask >> k) & 1)) continue;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      if (q & (1 << k)) continue;
+      const V a = v[q], b = v[q | (1 << k)];
+      v[q] = a + b;
+      v[q | (1 << k)] = a - b;
+    }
+  }
+}
+
+template <typename V>
+__device__ __forceinline__ void xz_rearrange(V (&v)[kXzRegs], V* lds, int from, int to) {
+  const uint32_t l = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) lds[xz_slot(xz_tau(from, l, q))] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) v[q] = lds[xz_slot(xz_tau(to, l, q))];
+  __syncthreads();
+}
+
+__device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg) {
+  const CONST_AS Seg* cs = (const CONST_AS Seg*)segs;
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cs[mid].x_base <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int lt = b - cs[lo].x_base;
+  const int nrt = cs[lo].x_tiles;
+  const int sl = lt / nrt, rt = lt - sl * nrt;
+  return Tile{lo, (uint32_t)rt << kXzTileBits, sl, rt};
+}
+
+// Pass A (phase 0), B (phase 1) or C (phase 2) of the transform apply.
+template <typename T, int PHASE>
+__global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ segs, int nseg) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  __shared__ V lds[1 << kXzTileBits];
+  __shared__ double red[4 * W];
+  const Tile t = xz_tile_of(segs, nseg);
+  const CONST_AS CSeg& sg = cseg(segs, t.seg);
+  const bool plain = sg.mode == MODE_PLAIN;
+  int j = 1;
+  if (!plain) {
+    j = sg.stepc[0];
+    if (j > sg.k) return;
+  }
+  const uint32_t dim = 1u << sg.nbits;
+  const uint64_t pstride = (uint64_t)dim;
+  const V* ub = (plain ? (const V*)sg.Q : (const V*)slot_ptr<T>(sg, j)) + (uint64_t)t.panel0 * pstride;
+  V* rb = (V*)sg.R + (uint64_t)t.panel0 * pstride;
+  const uint32_t l = threadIdx.x;
+  V v[kXzRegs];
+
+  if (PHASE == 0 || PHASE == 2) {
+    // contiguous tile: row = row0 + tau; arrangement 0 loads and stores coalesced
+    const V* src = PHASE == 0 ? ub : (const V*)rb;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg(src, t.row0 + xz_tau(0, l, q));
+    xz_bfly(v, 0xF);                 // bits 8..11
+    xz_rearrange(v, lds, 0, 1);
+    xz_bfly(v, 0xF);                 // bits 0..3
+    xz_rearrange(v, lds, 1, 2);
+    xz_bfly(v, 0xF);                 // bits 4..7
+    xz_rearrange(v, lds, 2, 0);
+    if (PHASE == 0) {
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q) stg(rb, t.row0 + xz_tau(0, l, q), v[q]);
+      return;
+    }
+    const int cp = sg.cpad;
+    const bool dots = sg.mode == MODE_LANCZOS;
+    const CONST_AS double* st = (const CONST_AS double*)sg.st;
+    const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride
+                                       : nullptr;
+    const T* dg = (const T*)sg.diag;
+    const V sc = scur_of<T, 1>(st, cp, t.panel0, 0, plain);
+    V bp;
+#pragma unroll
+    for (int e = 0; e < W; ++e) bp[e] = T(0);
+    if (uprev) bp = bps_of<T, 1>(st, cp, t.panel0, 0);
+    double dq[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) dq[e] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const uint32_t row = t.row0 + xz_tau(0, l, q);
+      const V u = ldg(ub, row);
+      const T d = ldg_s(dg, row);
+      V r = sc * (d * u + v[q]);
+      if (uprev) {
+        const V up = ldg(uprev, row);
+#pragma unroll
+        for (int e = 0; e < W; ++e) r[e] = fma_s(-bp[e], up[e], r[e]);
+      }
+      stg(rb, row, r);
+      if (dots) {
+#pragma unroll
+        for (int e = 0; e < W; ++e) dq[e] += (double)u[e] * (double)r[e];
+      }
+    }
+    if (!dots) return;
+    double tot;
+    block_sum<W>(dq, red, &tot);
+    if (threadIdx.x < W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
+  } else {
+    // strided tile: tau = hi * Lr + lr  ->  row = hi * 4096 + rt * Lr + lr,
+    // hb = N - 12 high bits (4 <= hb <= 8), Lr = 2^(12 - hb) >= 16
+    const int hb = sg.nbits - kXzTileBits;
+    const int lrb = kXzTileBits - hb;
+    const uint32_t lrm = (1u << lrb) - 1u;
+    const uint32_t base = (uint32_t)t.rtile << lrb;
+    const T* dx = (const T*)sg.dx;
+    auto row_of = [&](uint32_t tau) -> uint32_t {
+      return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
+    };
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg((const V*)rb, row_of(xz_tau(0, l, q)));
+    // tau bits lrb..11 are the row's high bits: 8..11 in arrangement 0, the
+    // part of 4..7 at or above lrb in arrangement 2
+    const int m2 = 0xF & ~((1 << (lrb > 4 ? lrb - 4 : 0)) - 1);
+    xz_bfly(v, 0xF);
+    xz_rearrange(v, lds, 0, 2);
+    xz_bfly(v, m2);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dx, row_of(xz_tau(2, l, q))) * v[q];
+    xz_bfly(v, m2);
+    xz_rearrange(v, lds, 2, 0);
+    xz_bfly(v, 0xF);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg(rb, row_of(xz_tau(0, l, q)), v[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // reductions of the per-tile partial sums: one workgroup per (segment,
 // column); lane i sums tiles i, i+256, ... and a fixed binary tree in LDS
 // combines the lanes, so the order never depends on scheduling.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double column_total(const Seg& sg, int c, double* lds) {
+__device__ __forceinline__ double column_total(const Seg& sg, int nrows, int c, double* lds) {
   double s = 0.0;
-  for (int t = threadIdx.x; t < sg.n_row_tiles; t += kBlock) s += sg.part[(uint64_t)t * sg.cpad + c];
+  for (int t = threadIdx.x; t < nrows; t += kBlock) s += sg.part[(uint64_t)t * sg.cpad + c];
   lds[threadIdx.x] = s;
   __syncthreads();
 #pragma unroll
@@ -560,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_red_beta(const Seg* __restrict__ seg
   const int c = blockIdx.y;
   if (c >= sg.cpad) return;
   __shared__ double lds[kBlock];
-  const double tot = column_total(sg, c, lds);
+  const double tot = column_total(sg, sg.n_row_tiles, c, lds);
   if (threadIdx.x != 0) return;
   const int j = sg.stepc[c];
   if (j > sg.k) return;
@@ -606,7 +777,7 @@ __global__ __launch_bounds__(kBlock) void k_red_alpha(const Seg* __restrict__ se
   const int c = blockIdx.y;
   if (c >= sg.cpad) return;
   __shared__ double lds[kBlock];
-  const double tot = column_total(sg, c, lds);
+  const double tot = column_total(sg, sg.ap_rows, c, lds);
   if (threadIdx.x != 0) return;
   const int j = sg.stepc[c];
   if (j > sg.k) return;
@@ -800,6 +971,15 @@ hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStre
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_apply_xz(const Seg* segs, int nseg, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_apply_xz<T, 0>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg);
+  hipLaunchKernelGGL((k_apply_xz<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg);
+  hipLaunchKernelGGL((k_apply_xz<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg);
+  return hipGetLastError();
+}
+
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st) {
   if (nseg <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_red_beta, dim3(nseg, cmax), dim3(kBlock), 0, st, segs);
@@ -865,6 +1045,8 @@ template hipError_t launch_norm<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_norm<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
+template hipError_t launch_apply_xz<float>(const Seg*, int, int, hipStream_t);
+template hipError_t launch_apply_xz<double>(const Seg*, int, int, hipStream_t);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);

@@ -198,7 +198,7 @@ void rdm_server::run() {
       }
     }
     const int slab = tuned_slab(prec, segs);
-    const int ntiles = assign_tiles(segs);
+    const Launch ntiles = assign_tiles(segs);
     for (const auto& sg : segs) cmax = std::max(cmax, sg.cpad);
     rdm_status s = ensure_tables(segs.size());
     if (s == RDM_OK && hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg),

@@ -157,15 +157,9 @@ namespace {
 Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int start_kind, int ns_log,
              int nb, uint64_t seed, double tau) {
   Seg s{};
-  s.hops = op->hops;
-  s.groups = op->groups;
-  s.thin = op->thin;
-  s.diag = op->diag;
-  s.ngroups = op->ngroups;
-  s.nt0 = op->nt[0];
-  s.nt1 = op->nt[1];
-  s.nt2 = op->nt[2];
   s.nbits = g.nbits;
+  s.n_row_tiles = g.n_row_tiles;
+  bind_apply(s, op);
   s.P = g.P;
   s.S = g.S;
   s.rpl = g.rpl;
@@ -178,7 +172,6 @@ Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int sta
   s.ns_log = ns_log;
   s.nb = nb;
   s.n_beta = 0;
-  s.n_row_tiles = g.n_row_tiles;
   s.seed = seed;
   s.blk = g.blk;
   s.Q = base + g.o_Q;
@@ -264,25 +257,50 @@ int common_slab(std::vector<Seg>& segs) {
   return slab;
 }
 
-int assign_tiles(std::vector<Seg>& segs) {
-  int64_t base = 0;
-  for (auto& sg : segs) {
-    sg.tile_base = (int32_t)base;
-    base += (int64_t)sg.n_row_tiles * (sg.P / sg.S);
-  }
-  return (int)base;
+void bind_apply(Seg& s, const OpDevice* op) {
+  s.hops = op->hops;
+  s.groups = op->groups;
+  s.thin = op->thin;
+  s.diag = op->diag;
+  s.ngroups = op->ngroups;
+  s.nt0 = op->nt[0];
+  s.nt1 = op->nt[1];
+  s.nt2 = op->nt[2];
+  s.xz = op->xz ? 1 : 0;
+  s.dx = op->dx;
+  s.x_tiles = op->xz ? 1 << (s.nbits - kXzTileBits) : 0;
+  s.ap_rows = op->xz ? s.x_tiles : s.n_row_tiles;
 }
 
-rdm_status launch_step(int prec, const Seg* dsegs, int nseg, int ntiles, int slab, int cmax, hipStream_t st,
+Launch assign_tiles(std::vector<Seg>& segs) {
+  // norm launches cover every segment; an apply launch covers either the
+  // hop-table segments or (three passes) the transform segments.  Segments of
+  // the other kind get no workgroups (their base is the running count, which
+  // the kernels' binary search never resolves to them).
+  Launch L;
+  for (auto& sg : segs) {
+    sg.tile_base = L.norm;
+    L.norm += sg.n_row_tiles * (sg.P / sg.S);
+    sg.ap_base = L.apply;
+    if (!sg.xz) L.apply += sg.n_row_tiles * (sg.P / sg.S);
+    sg.x_base = L.xz;
+    if (sg.xz) L.xz += sg.x_tiles * sg.P;
+  }
+  return L;
+}
+
+rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, hipStream_t st,
                        StepTimers* tm) {
   if (tm) RDM_HIP(tm->norm.mark(st));
-  RDM_HIP(prec == RDM_FP64 ? launch_norm<double>(dsegs, nseg, ntiles, slab, st)
-                           : launch_norm<float>(dsegs, nseg, ntiles, slab, st));
+  RDM_HIP(prec == RDM_FP64 ? launch_norm<double>(dsegs, nseg, L.norm, slab, st)
+                           : launch_norm<float>(dsegs, nseg, L.norm, slab, st));
   if (tm) RDM_HIP(tm->norm.mark(st));
   RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
-  RDM_HIP(prec == RDM_FP64 ? launch_apply<double>(dsegs, nseg, ntiles, slab, st)
-                           : launch_apply<float>(dsegs, nseg, ntiles, slab, st));
+  RDM_HIP(prec == RDM_FP64 ? launch_apply<double>(dsegs, nseg, L.apply, slab, st)
+                           : launch_apply<float>(dsegs, nseg, L.apply, slab, st));
+  RDM_HIP(prec == RDM_FP64 ? launch_apply_xz<double>(dsegs, nseg, L.xz, st)
+                           : launch_apply_xz<float>(dsegs, nseg, L.xz, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(launch_red_alpha(dsegs, nseg, cmax, st));
   return RDM_OK;
@@ -476,7 +494,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
       // one is kept for the remaining steps and for later launches of the
       // same shape
       std::vector<std::vector<Seg>> tabs(cands.size(), hsegs);
-      std::vector<int> nt(cands.size());
+      std::vector<Launch> nt(cands.size());
       for (size_t c = 0; c < cands.size(); ++c) {
         set_slab(tabs[c], cands[c]);
         nt[c] = assign_tiles(tabs[c]);
@@ -515,7 +533,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
     }
   }
   set_slab(hsegs, slab);
-  const int ntiles = assign_tiles(hsegs);
+  const Launch ntiles = assign_tiles(hsegs);
   RDM_HIP(hipMemcpyAsync(dsegs, hsegs.data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
   if (j == 1) RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
   for (; j <= kmax; ++j) {

@@ -90,9 +90,16 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
 rdm_status bind_ops(InstRun& r, hipStream_t st);
 Seg seg_of(const InstRun& r, int which, int mode, double tau);
 int common_slab(std::vector<Seg>& segs);
-// sets every segment's tile_base; returns the workgroups of a norm/apply launch
-int assign_tiles(std::vector<Seg>& segs);
-rdm_status launch_step(int prec, const Seg* dsegs, int nseg, int ntiles, int slab, int cmax, hipStream_t st,
+// Operator tables of a segment's apply (hop tables or transform).  Needs
+// nbits and n_row_tiles set.
+void bind_apply(Seg& s, const OpDevice* op);
+// workgroups of the norm launch and of the two kinds of apply launch
+struct Launch {
+  int norm = 0, apply = 0, xz = 0;
+};
+// sets every segment's tile_base / ap_base / x_base
+Launch assign_tiles(std::vector<Seg>& segs);
+rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, hipStream_t st,
                        StepTimers* tm);
 // Runs every step of a phase.  tune: choose the panels per lane by timing the
 // first steps (cached per shape); otherwise the segments' own value is used.

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import lanczos as olz
-from workloads import cfg_long_range, cfg_small_chain, random_dense_terms
+from workloads import long_range_xxz, cfg_long_range, cfg_small_chain, random_dense_terms
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 rdm = pytest.importorskip("paper_2204_08147_amd")
@@ -53,6 +53,22 @@ def test_hamiltonian_tables():
     h2 = rdm.Hamiltonian.from_instance(cfg_small_chain())
     i2 = h2.info()
     assert i2["hops_parity"] == 9 and i2["hops_uniform"] == 0 and i2["diag_terms"] == 9 + 10
+
+
+def test_transform_apply_selection():
+    # operators whose hops are all X-type (J^y = 0) on 16..20 bits are applied
+    # as D_Z + W D_X W; anything with a YY part, or outside that size range,
+    # keeps the hop tables
+    full = rdm.Hamiltonian.from_instance(cfg_long_range(0)).info()      # 2 + 18
+    assert full["transform"] == 1 and full["bath_transform"] == 1
+    small = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=8)).info()  # 2 + 8
+    assert small["transform"] == 0 and small["bath_transform"] == 0
+    mid = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=15)).info()   # 2 + 15: bath 15 bits
+    assert mid["transform"] == 1 and mid["bath_transform"] == 0
+    big = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=20)).info()   # 22 bits
+    assert big["transform"] == 0
+    xxz = rdm.Hamiltonian.from_instance(long_range_xxz(2, 16, 1)).info()   # J^x = J^y
+    assert xxz["transform"] == 0 and xxz["bath_transform"] == 0
 
 
 @pytest.mark.parametrize("bad", [

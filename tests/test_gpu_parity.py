@@ -78,6 +78,8 @@ APPLY_CASES = [
     lambda: long_range_xx_zz(2, 11, 1.0, 54),     # uniform hops only
     lambda: long_range_xxz(3, 10, 55),            # parity hops with c_same = 0
     lambda: random_sparse_xxz(3007, n_range=(12, 14)),
+    lambda: long_range_xx_zz(2, 14, 1.0, 57),     # 16 bits, X-type only: transform apply
+    lambda: tfim_request(7, n_range=(17, 17)),    # 17 bits, ZZ chain + x-field: transform apply
 ]
 
 
@@ -116,6 +118,28 @@ def test_apply_bath_operator(prec):
     want = opb.apply(x if prec == "fp64" else x.astype(np.float32).astype(np.float64))
     tol = 1e-13 if prec == "fp64" else 3e-6
     assert np.abs(got - want).max() < tol * np.abs(want).max() * 10
+
+
+def test_transform_apply_bath_and_total():
+    # 2 + 16 spins, X-type hops only: both H_t (18 bits) and H_b (16 bits)
+    # take the transform apply
+    inst = long_range_xx_zz(2, 16, 0.7, 58)
+    h = H(inst)
+    info = h.info()
+    assert info["transform"] == 1 and info["bath_transform"] == 1
+    rng = np.random.default_rng(3)
+    for which, dim, op in ((0, inst.dim, spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)),
+                           (1, inst.d_b, spin.sparse_bath_hamiltonian(inst.n_s, inst.n_b, inst.couplings,
+                                                                      inst.hx, inst.hz))):
+        x = rng.normal(size=(dim, 6))
+        for prec, tol in (("fp64", 1e-13), ("mixed", 3e-6)):
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            xd = rdm.to_panels(torch.tensor(x, dtype=dt, device="cuda"), prec)
+            yd = torch.full_like(xd, float("nan"))
+            rdm.apply(h, xd, yd, which=which, precision=prec, n_cols=6)
+            got = rdm.from_panels(yd, dim, 6, prec).double().cpu().numpy()
+            want = op.apply(x if prec == "fp64" else x.astype(np.float32).astype(np.float64))
+            assert np.abs(got - want).max() < tol * np.abs(want).max() * 10, (which, prec)
 
 
 @pytest.mark.parametrize("make,cols", [(lambda: cfg_long_range(2), 64), (lambda: tfim_request(3, n_range=(24, 24)), 32)])
@@ -198,13 +222,24 @@ SOLVE_CASES = {
     "lr_2+9": lambda: long_range_xx_zz(2, 9, 1.5, 73, betas=(0.5, 1.0, 2.0, 4.0), n_v=5, k=60),
     "xxz_chain_2+10": lambda: nn_xxz_chain(2, 10, 74, betas=(0.7, 5.0), n_v=4, k=50),
     "sparse": lambda: random_sparse_xxz(3011, n_range=(12, 13)),
+    # 16 bits, X-type hops only: the transform apply (H_t) next to hop tables (H_b)
+    "xz_2+14": lambda: long_range_xx_zz(2, 14, 1.0, 75, betas=(0.5, 2.0), n_v=2, k=30),
 }
+
+_ORACLE = {}
+
+
+def oracle_solve(name):
+    # O3 results per case, computed once per session
+    if name not in _ORACLE:
+        _ORACLE[name] = olz.solve(SOLVE_CASES[name]())["results"]
+    return _ORACLE[name]
 
 
 @pytest.mark.parametrize("name", list(SOLVE_CASES))
 def test_solve_fp64_matches_oracle(name):
     inst = SOLVE_CASES[name]()
-    want = olz.solve(inst)["results"]
+    want = oracle_solve(name)
     got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
     check_result(got, want, 1e-10, name)
 
@@ -212,7 +247,7 @@ def test_solve_fp64_matches_oracle(name):
 @pytest.mark.parametrize("name", list(SOLVE_CASES))
 def test_solve_mixed_matches_oracle(name):
     inst = SOLVE_CASES[name]()
-    want = olz.solve(inst)["results"]
+    want = oracle_solve(name)
     got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed")
     check_result(got, want, 1e-5, name)
 
@@ -228,8 +263,9 @@ def test_solve_outputs_are_density_matrices():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_two_pass_is_bitwise_stored(prec):
-    inst = SOLVE_CASES["lr_2+9"]()
+@pytest.mark.parametrize("name", ["lr_2+9", "xz_2+14"])
+def test_two_pass_is_bitwise_stored(prec, name):
+    inst = SOLVE_CASES[name]()
     h = H(inst)
     a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision=prec, mode="stored")
     b = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision=prec, mode="two_pass")
@@ -286,7 +322,8 @@ def test_k_capped_at_dimension():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_equals_solo(prec):
-    insts = [SOLVE_CASES[n]() for n in ("chain_1+9", "random_2+6", "random_3+5", "lr_2+9", "sparse")]
+    insts = [SOLVE_CASES[n]() for n in ("chain_1+9", "random_2+6", "xz_2+14", "random_3+5", "lr_2+9",
+                                        "sparse")]
     hs = [H(i) for i in insts]
     items = [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
     batch = rdm.solve_batch(items, precision=prec)
