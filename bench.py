@@ -59,8 +59,8 @@ def kernel_source_hash():
 
 
 def read_traffic(name):
-    """HBM bytes per dispatch from the committed rocprofv3 counter summary, or
-    None if absent or taken on a different kernel source."""
+    """HBM bytes per Lanczos step from the committed rocprofv3 counter
+    summary, or None if absent or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -72,7 +72,7 @@ def read_traffic(name):
     if vals.get("kernels_hip_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_dispatch"])
+        return float(vals["hbm_bytes_per_step"])
     except (KeyError, ValueError):
         return None
 
@@ -109,28 +109,30 @@ def _cpu_baseline(inst, budget_s, exact, olz, spin):
 
 
 def operator_work(nbits, cols, nnz, transform, s, k):
-    """Algorithmic bytes and flops of one apply launch on one operator (2^nbits
-    rows, cols columns padded to whole 16-byte panels, s bytes per scalar),
-    averaged over k steps (the previous vector is absent at the first step).
+    """Algorithmic bytes and flops of one Lanczos step (norm step + apply) on
+    one operator: 2^nbits rows, cols columns padded to whole 16-byte panels,
+    s bytes per scalar, averaged over k steps (p = (k-1)/k: r and u_(j-1)
+    are absent at the first step).
 
-    Hop tables: read u_j and u_(j-1), write r, read the diagonal once:
-    (2 + (k-1)/k) vectors + dim*s bytes; 2*nnz flops per element.
-    Transform (D_Z + W D_X W, three passes over each 16-byte panel):
-    A reads u and writes t, B reads and writes t and reads D_X, C reads t, u,
-    u_(j-1) and D_Z and writes r: (7 + (k-1)/k) vectors + 2 diagonals per
-    panel; 2*nbits + 4 flops per element."""
+    Hop tables: norm reads r and u_(j-1) and writes u_j, apply reads u_j and
+    u_(j-1), writes r and reads the diagonal: (3 + 3p) vectors + dim*s;
+    2*nnz flops per element.
+    Transform (D_Z + W D_X W): pass 0 reads r and u_(j-1), writes u_j and t;
+    pass 1 reads and writes t and reads D_X; pass 2 reads t, u_j, u_(j-1)
+    and D_Z and writes r: (7 + 3p) vectors + 2 diagonals per panel;
+    2*nbits + 4 flops per element."""
     dim = 1 << nbits
     w = 16 // s
     cp = (cols + w - 1) // w * w
     vec = dim * cp * s
-    prev = (k - 1) / k
+    p = (k - 1) / k
     if transform:
-        return vec * (7 + prev) + 2 * (cp // w) * dim * s, (2.0 * nbits + 4) * dim * cp
-    return vec * (2 + prev) + dim * s, 2.0 * nnz * dim * cols
+        return vec * (7 + 3 * p) + 2 * (cp // w) * dim * s, (2.0 * nbits + 4) * dim * cp
+    return vec * (3 + 3 * p) + dim * s, 2.0 * nnz * dim * cols
 
 
-def apply_work(insts, prec_bytes):
-    """Algorithmic bytes and flops of one apply launch over the H_t and H_b
+def step_work(insts, prec_bytes):
+    """Algorithmic bytes and flops of one Lanczos step over the H_t and H_b
     segments of the given instances."""
     import paper_2204_08147_amd as rdm
     by = fl = 0.0
@@ -143,6 +145,12 @@ def apply_work(insts, prec_bytes):
         by += b1 + b2
         fl += f1 + f2
     return by, fl
+
+
+def step_ms(res):
+    """Mean device time of one Lanczos step's vector kernels (norm step and
+    apply, either kind) from the library's event timing."""
+    return res["t_norm_ms"] + res["t_xz0_ms"] + res["t_apply_ms"]
 
 
 def roofline(bytes_, flops, t_s, traffic=None):
@@ -174,10 +182,10 @@ def bench_batch(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert all(o["status"] == 0 for o in out), [o["status"] for o in out]
-    by, fl = apply_work(insts, 4)
+    by, fl = step_work(insts, 4)
     # one apply launch covers every instance resident in a wave; with several
     # waves the event average is per launch of the wave, so report the sum
-    t_apply = float(np.mean([o["t_apply_ms"] for o in out])) * 1e-3
+    t_step = float(np.mean([step_ms(o) for o in out])) * 1e-3
     n = len(insts) * args.steps
     return {"metric": "batched solves/s (64 heterogeneous instances)", "value": round(n / wall, 3),
             "unit": "solves/s", "ms_per_step": round(1e3 * wall / args.steps, 2), "steps": args.steps,
@@ -185,7 +193,7 @@ def bench_batch(args):
             "config": {"workload": "64 random sparse XXZ instances, N in [12,22], N_s in {1,2,3}, "
                                    "degree 4, beta log-U[0.1,10], n_v=8, k=50",
                        "dims": sorted(int(i.n) for i in insts)},
-            "apply_kernel_ms_mean": round(1e3 * t_apply, 4),
+            "step_kernels_ms_mean": round(1e3 * t_step, 4),
             "two_pass_instances": int(sum(o["two_pass"] for o in out))}
 
 
@@ -204,14 +212,14 @@ def bench_large(args):
                     profile=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    by, fl = apply_work([inst], 4)
-    t_apply = res["t_apply_ms"] * 1e-3
+    by, fl = step_work([inst], 4)
+    t_step = step_ms(res) * 1e-3
     return {"metric": "large-instance solve time", "value": round(wall, 3), "unit": "s/solve",
             "higher_is_better": False, "dtype": "f32 vectors + f64 reductions",
             "config": {"workload": "long-range XXZ 3+23 spins (dim 2^26), alpha=1.2, Delta=0.8, "
                                    "x-field 1.0, beta=2, n_v=4 (32 columns), k=80, two-pass"},
-            "apply_kernel_ms": round(1e3 * t_apply, 3), "norm_kernel_ms": round(res["t_norm_ms"], 3),
-            "roofline_apply": roofline(by, fl, t_apply), "two_pass": res["two_pass"],
+            "apply_kernel_ms": round(res["t_apply_ms"], 3), "norm_kernel_ms": round(res["t_norm_ms"], 3),
+            "roofline_step": roofline(by, fl, t_step), "two_pass": res["two_pass"],
             "device_bytes": res["device_bytes"],
             "rho": res["rho"][0].round(6).tolist(), "entropy": float(res["entropy"][0]),
             "h_star_eigs": np.linalg.eigvalsh(res["h_star"][0]).round(6).tolist()}
@@ -332,6 +340,7 @@ def main():
 
     def run(prec, steps, warmup, ws, profile):
         lat, apply_ms, norm_ms, gram_ms, res = [], [], [], [], None
+        xz0_ms = []
         for s in range(warmup + steps):
             if s == warmup:
                 torch.cuda.synchronize()
@@ -345,25 +354,27 @@ def main():
                     if profile:
                         apply_ms.append(res["t_apply_ms"])
                         norm_ms.append(res["t_norm_ms"])
+                        xz0_ms.append(res["t_xz0_ms"])
                         gram_ms.append(res["t_gram_ms"])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, lat, apply_ms, norm_ms, gram_ms, res
+        return wall, lat, apply_ms, norm_ms, gram_ms, res, xz0_ms
 
     ws_m = make_ws("mixed")
-    wall_m, lat_m, ap_m, no_m, gr_m, res_m = run("mixed", args.steps, args.warmup, ws_m, True)
+    wall_m, lat_m, ap_m, no_m, gr_m, res_m, x0_m = run("mixed", args.steps, args.warmup, ws_m, True)
     del ws_m
     torch.cuda.empty_cache()
     fp64 = None
     if not args.no_fp64:
         ws_d = make_ws("fp64")
-        wall_d, lat_d, ap_d, no_d, gr_d, res_d = run("fp64", max(1, args.steps // 2), args.warmup, ws_d, True)
+        wall_d, lat_d, ap_d, no_d, gr_d, res_d, x0_d = run("fp64", max(1, args.steps // 2), args.warmup, ws_d,
+                                                           True)
         del ws_d
         torch.cuda.empty_cache()
         n_d = len(lat_d)
         fp64 = {"solves_per_s": n_d / wall_d, "p50_ms": 1e3 * float(np.percentile(lat_d, 50)),
                 "p99_ms": 1e3 * float(np.percentile(lat_d, 99)),
-                "apply_kernel_ms": float(np.mean(ap_d))}
+                "step_kernels_ms": float(np.mean(ap_d) + np.mean(no_d) + np.mean(x0_d))}
 
     n_solves = len(lat_m)
     value = n_solves / wall_m
@@ -372,11 +383,11 @@ def main():
     # roofline of the dominant kernel: the apply launch (H_t and H_b segments)
     info = hs[0].info()
     nnz = 1 + info["hops_uniform"] + 0.5 * info["hops_parity"]
-    bytes_alg, flops = apply_work([inst0], 4)
-    t_apply = float(np.mean(ap_m)) * 1e-3
-    achieved_gbs = bytes_alg / t_apply / 1e9
-    traffic = read_traffic("apply_lr_xxzz_2+18_mixed_counters.txt")
-    roof = roofline(bytes_alg, flops, t_apply, traffic)
+    bytes_alg, flops = step_work([inst0], 4)
+    t_step = float(np.mean(ap_m) + np.mean(no_m) + np.mean(x0_m)) * 1e-3
+    achieved_gbs = bytes_alg / t_step / 1e9
+    traffic = read_traffic("lanczos_step_lr_xxzz_2+18_mixed_counters.txt")
+    roof = roofline(bytes_alg, flops, t_step, traffic)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -394,9 +405,11 @@ def main():
                    "apply": "transform (D_Z + W D_X W, 3 passes)" if info["transform"] else "hop tables"},
         "p50_ms": round(1e3 * float(np.percentile(lat_m, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat_m, 99)), 3),
-        "apply_gbs_algorithmic": round(achieved_gbs, 1),
-        "apply_kernel_ms": round(1e3 * t_apply, 4),
+        "step_gbs_algorithmic": round(achieved_gbs, 1),
+        "step_kernels_ms": round(1e3 * t_step, 4),
+        "apply_kernel_ms": round(float(np.mean(ap_m)), 4),
         "norm_kernel_ms": round(float(np.mean(no_m)), 4),
+        "transform_pass0_ms": round(float(np.mean(x0_m)), 4),
         "gram_kernel_ms": round(float(np.mean(gr_m)), 4),
         "fp64": None if fp64 is None else {k2: round(v, 4) for k2, v in fp64.items()},
         "mixed_over_fp64": None if fp64 is None else round(value / fp64["solves_per_s"], 3),

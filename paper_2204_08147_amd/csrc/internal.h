@@ -87,9 +87,10 @@ struct Seg {
   int32_t nb;          // bath bits (RNG index range)
   int32_t n_beta;      // psi blocks (MODE_REGEN)
   int32_t n_row_tiles; // partial-sum rows (= row tiles of kBlock rows)
-  int32_t tile_base;   // first workgroup of this segment in a norm launch
+  int32_t tile_base;   // first workgroup of this segment in a norm launch (hop-table segments)
   int32_t ap_base;     // first workgroup of this segment in a (256-row) apply launch
   int32_t ap_rows;     // partial-sum rows the apply writes (row tiles of its kind)
+  int32_t nm_rows;     // partial-sum rows the norm step writes
   int32_t xz;          // 1: transform apply (D_Z + W D_X W), 0: hop tables
   int32_t x_tiles;     // transform apply: tiles of 2^kXzTileBits rows
   int32_t x_base;      // transform apply: first workgroup of this segment
@@ -142,9 +143,10 @@ template <typename T>
 hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 template <typename T>
 hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
-// the three passes of the transform apply over the segments with xz = 1
+// pass 0, 1 or 2 of the transform apply over the segments with xz = 1 (pass 0
+// also does the norm step outside MODE_PLAIN)
 template <typename T>
-hipError_t launch_apply_xz(const Seg* segs, int nseg, int ntiles, hipStream_t st);
+hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st);
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st);

@@ -548,6 +548,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
 //   B: t = W_hi D_X W_hi t   (bits 12..N-1, tiles of 2^(24-N)-row runs)
 //   C: r = s_j (D_Z u + W_lo t) - beta s u_{j-1}, partial <u_j, r>
 // t lives in the output block R (each workgroup rewrites only its own rows).
+// In a Lanczos step pass A also does the norm kernel's work for its tile: it
+// forms u_j = r - (alpha s) u_{j-1} (or the start block), stores it, adds the
+// partial |u_j|^2 (and psi in the regeneration pass), then transforms it.
 //
 // A tile is 4096 elements indexed by a 12-bit coordinate tau; lane l holds 16
 // of them in registers q.  Three arrangements: 0: tau = q*256 + l (q = bits
@@ -627,11 +630,95 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
   const uint32_t l = threadIdx.x;
   V v[kXzRegs];
 
-  if (PHASE == 0 || PHASE == 2) {
+  if (PHASE == 0 && !plain) {
+    // u_j from r and u_{j-1} (norm step), kept in registers for the transform
+    const int cp = sg.cpad;
+    const CONST_AS double* st = (const CONST_AS double*)sg.st;
+    V* ucur = (V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
+    const V* uprev = j > 1 ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride : nullptr;
+    V acur;
+#pragma unroll
+    for (int e = 0; e < W; ++e) acur[e] = (T)st[ST_ACUR * cp + t.panel0 * W + e];
+    const T amp = amp_of<T>(sg.nb);
+    double dsum[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) dsum[e] = 0.0;
+    if (j == 1) {
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q)
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+          v[q][e] = start_value<T>(sg.start_kind, sg.ns_log, sg.nb, sg.seed, t.row0 + xz_tau(0, l, q),
+                                   t.panel0 * W + e, sg.C, amp);
+    } else {
+      V up[kXzRegs];
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q) {
+        v[q] = ldg((const V*)rb, t.row0 + xz_tau(0, l, q));
+        up[q] = ldg(uprev, t.row0 + xz_tau(0, l, q));
+      }
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q)
+#pragma unroll
+        for (int e = 0; e < W; ++e) v[q][e] = fma_s(-acur[e], up[q][e], v[q][e]);
+    }
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      stg(ucur, t.row0 + xz_tau(0, l, q), v[q]);
+#pragma unroll
+      for (int e = 0; e < W; ++e) dsum[e] += (double)v[q][e] * (double)v[q][e];
+    }
+    if (sg.mode == MODE_REGEN) {
+      const CONST_AS T* yt = (const CONST_AS T*)sg.ytab;
+      for (int b = 0; b < sg.n_beta; ++b) {
+        V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + (uint64_t)t.panel0 * pstride;
+        V y;
+#pragma unroll
+        for (int e = 0; e < W; ++e) y[e] = yt[((uint64_t)b * sg.k + (j - 1)) * cp + t.panel0 * W + e];
+#pragma unroll
+        for (int q = 0; q < kXzRegs; ++q) {
+          const uint32_t row = t.row0 + xz_tau(0, l, q);
+          V old;
+          if (j == 1) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) old[e] = T(0);
+          } else {
+            old = ldg((const V*)pb, row);
+          }
+          V nw;
+#pragma unroll
+          for (int e = 0; e < W; ++e) nw[e] = fma_s(y[e], v[q][e], old[e]);
+          stg(pb, row, nw);
+        }
+      }
+    }
+    double tot;
+    block_sum<W>(dsum, red, &tot);
+    if (threadIdx.x < W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
+    xz_bfly(v, 0xF);                 // bits 8..11
+    xz_rearrange(v, lds, 0, 1);
+    xz_bfly(v, 0xF);                 // bits 0..3
+    xz_rearrange(v, lds, 1, 2);
+    xz_bfly(v, 0xF);                 // bits 4..7
+    xz_rearrange(v, lds, 2, 0);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg(rb, t.row0 + xz_tau(0, l, q), v[q]);
+  } else if (PHASE == 0 || PHASE == 2) {
     // contiguous tile: row = row0 + tau; arrangement 0 loads and stores coalesced
     const V* src = PHASE == 0 ? ub : (const V*)rb;
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) v[q] = ldg(src, t.row0 + xz_tau(0, l, q));
+    // pass C: the epilogue's operands are loaded while the tile is transformed
+    V u[PHASE == 2 ? kXzRegs : 1];
+    T d[PHASE == 2 ? kXzRegs : 1];
+    if (PHASE == 2) {
+      const T* dg = (const T*)sg.diag;
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q) {
+        u[q] = ldg(ub, t.row0 + xz_tau(0, l, q));
+        d[q] = ldg_s(dg, t.row0 + xz_tau(0, l, q));
+      }
+    }
     xz_bfly(v, 0xF);                 // bits 8..11
     xz_rearrange(v, lds, 0, 1);
     xz_bfly(v, 0xF);                 // bits 0..3
@@ -648,7 +735,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     const CONST_AS double* st = (const CONST_AS double*)sg.st;
     const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride
                                        : nullptr;
-    const T* dg = (const T*)sg.diag;
     const V sc = scur_of<T, 1>(st, cp, t.panel0, 0, plain);
     V bp;
 #pragma unroll
@@ -660,9 +746,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) {
       const uint32_t row = t.row0 + xz_tau(0, l, q);
-      const V u = ldg(ub, row);
-      const T d = ldg_s(dg, row);
-      V r = sc * (d * u + v[q]);
+      V r = sc * (d[q] * u[q] + v[q]);
       if (uprev) {
         const V up = ldg(uprev, row);
 #pragma unroll
@@ -671,7 +755,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
       stg(rb, row, r);
       if (dots) {
 #pragma unroll
-        for (int e = 0; e < W; ++e) dq[e] += (double)u[e] * (double)r[e];
+        for (int e = 0; e < W; ++e) dq[e] += (double)u[q][e] * (double)r[e];
       }
     }
     if (!dots) return;
@@ -731,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_red_beta(const Seg* __restrict__ seg
   const int c = blockIdx.y;
   if (c >= sg.cpad) return;
   __shared__ double lds[kBlock];
-  const double tot = column_total(sg, sg.n_row_tiles, c, lds);
+  const double tot = column_total(sg, sg.nm_rows, c, lds);
   if (threadIdx.x != 0) return;
   const int j = sg.stepc[c];
   if (j > sg.k) return;
@@ -972,11 +1056,13 @@ hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStre
 }
 
 template <typename T>
-hipError_t launch_apply_xz(const Seg* segs, int nseg, int ntiles, hipStream_t st) {
+hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_apply_xz<T, 0>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg);
-  hipLaunchKernelGGL((k_apply_xz<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg);
-  hipLaunchKernelGGL((k_apply_xz<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg);
+  switch (pass) {
+    case 0: hipLaunchKernelGGL((k_apply_xz<T, 0>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
+    case 1: hipLaunchKernelGGL((k_apply_xz<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
+    default: hipLaunchKernelGGL((k_apply_xz<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
+  }
   return hipGetLastError();
 }
 
@@ -1045,8 +1131,8 @@ template hipError_t launch_norm<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_norm<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
-template hipError_t launch_apply_xz<float>(const Seg*, int, int, hipStream_t);
-template hipError_t launch_apply_xz<double>(const Seg*, int, int, hipStream_t);
+template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t);
+template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);

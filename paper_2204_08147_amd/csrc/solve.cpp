@@ -270,17 +270,18 @@ void bind_apply(Seg& s, const OpDevice* op) {
   s.dx = op->dx;
   s.x_tiles = op->xz ? 1 << (s.nbits - kXzTileBits) : 0;
   s.ap_rows = op->xz ? s.x_tiles : s.n_row_tiles;
+  s.nm_rows = s.ap_rows;
 }
 
 Launch assign_tiles(std::vector<Seg>& segs) {
-  // norm launches cover every segment; an apply launch covers either the
-  // hop-table segments or (three passes) the transform segments.  Segments of
+  // the norm and apply launches cover the hop-table segments, the three
+  // transform passes the others (pass 0 doing their norm step).  Segments of
   // the other kind get no workgroups (their base is the running count, which
   // the kernels' binary search never resolves to them).
   Launch L;
   for (auto& sg : segs) {
     sg.tile_base = L.norm;
-    L.norm += sg.n_row_tiles * (sg.P / sg.S);
+    if (!sg.xz) L.norm += sg.n_row_tiles * (sg.P / sg.S);
     sg.ap_base = L.apply;
     if (!sg.xz) L.apply += sg.n_row_tiles * (sg.P / sg.S);
     sg.x_base = L.xz;
@@ -291,16 +292,20 @@ Launch assign_tiles(std::vector<Seg>& segs) {
 
 rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, hipStream_t st,
                        StepTimers* tm) {
+  const bool d = prec == RDM_FP64;
   if (tm) RDM_HIP(tm->norm.mark(st));
-  RDM_HIP(prec == RDM_FP64 ? launch_norm<double>(dsegs, nseg, L.norm, slab, st)
-                           : launch_norm<float>(dsegs, nseg, L.norm, slab, st));
+  RDM_HIP(d ? launch_norm<double>(dsegs, nseg, L.norm, slab, st) : launch_norm<float>(dsegs, nseg, L.norm, slab, st));
   if (tm) RDM_HIP(tm->norm.mark(st));
+  if (tm) RDM_HIP(tm->xz0.mark(st));
+  RDM_HIP(d ? launch_xz_pass<double>(0, dsegs, nseg, L.xz, st) : launch_xz_pass<float>(0, dsegs, nseg, L.xz, st));
+  if (tm) RDM_HIP(tm->xz0.mark(st));
   RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
-  RDM_HIP(prec == RDM_FP64 ? launch_apply<double>(dsegs, nseg, L.apply, slab, st)
-                           : launch_apply<float>(dsegs, nseg, L.apply, slab, st));
-  RDM_HIP(prec == RDM_FP64 ? launch_apply_xz<double>(dsegs, nseg, L.xz, st)
-                           : launch_apply_xz<float>(dsegs, nseg, L.xz, st));
+  RDM_HIP(d ? launch_apply<double>(dsegs, nseg, L.apply, slab, st)
+            : launch_apply<float>(dsegs, nseg, L.apply, slab, st));
+  for (int pass = 1; pass <= 2; ++pass)
+    RDM_HIP(d ? launch_xz_pass<double>(pass, dsegs, nseg, L.xz, st)
+              : launch_xz_pass<float>(pass, dsegs, nseg, L.xz, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(launch_red_alpha(dsegs, nseg, cmax, st));
   return RDM_OK;
@@ -562,7 +567,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     if (s != RDM_OK) return s;
   }
   StepTimers tm;
-  tm.apply.on = tm.norm.on = profile;
+  tm.apply.on = tm.norm.on = tm.xz0.on = profile;
   // pass 1: every total and bath segment in the same launches
   std::vector<Seg> segs;
   for (auto& r : runs) {
@@ -587,6 +592,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     for (auto& r : runs) {
       r.t_apply_ms = tm.apply.avg_ms();
       r.t_norm_ms = tm.norm.avg_ms();
+      r.t_xz0_ms = tm.xz0.avg_ms();
       r.t_gram_ms = tg.avg_ms();
     }
   return RDM_OK;
@@ -665,7 +671,8 @@ rdm_status finalize(const InstRun& r, rdm_result* out) {
     d[7] = r.t_apply_ms;
     d[8] = r.t_norm_ms;
     d[9] = r.t_gram_ms;
-    for (int t = 10; t < kDiagFixed; ++t) d[t] = 0.0;
+    d[10] = r.t_xz0_ms;
+    for (int t = 11; t < kDiagFixed; ++t) d[t] = 0.0;
   }
   return RDM_OK;
 }

@@ -60,8 +60,10 @@ struct Timers {
     return n ? tot / n : 0.0;
   }
 };
+// apply: hop-table apply and transform passes 1-2; norm: the norm kernel;
+// xz0: transform pass 0 (norm step + first transform)
 struct StepTimers {
-  Timers apply, norm;
+  Timers apply, norm, xz0;
 };
 
 struct InstRun {
@@ -75,7 +77,7 @@ struct InstRun {
   double e0 = 0, e0b = 0;
   int n_break_t = 0, n_break_b = 0;
   std::vector<double> mb, gsum;
-  double t_apply_ms = 0, t_norm_ms = 0, t_gram_ms = 0;
+  double t_apply_ms = 0, t_norm_ms = 0, t_gram_ms = 0, t_xz0_ms = 0;
 };
 
 void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
