@@ -314,10 +314,10 @@ extern "C" rdm_status rdm_server_submit(rdm_server* s, const rdm_hamiltonian* h,
   r->out = out;
   r->run.betas.assign(beta, beta + n_beta);
   r->run.seed = seed;
-  // a request keeps all its Lanczos vectors only if that takes at most a
-  // quarter of the arena; larger ones run two-pass so that several requests
-  // can stay resident together
-  rdm_status ps = plan_instance(r->plan, h, n_beta, n_v, k, s->prec, RDM_AUTO, s->budget / 4, 0, 0);
+  // a request keeps all its Lanczos vectors if that takes at most half of
+  // the arena (the regeneration pass of a two-pass plan costs as much as the
+  // first one); larger ones run two-pass so that others stay resident too
+  rdm_status ps = plan_instance(r->plan, h, n_beta, n_v, k, s->prec, RDM_AUTO, s->budget / 2, 0, 0);
   if (ps == RDM_E_NOMEM)
     ps = plan_instance(r->plan, h, n_beta, n_v, k, s->prec, RDM_TWO_PASS, s->budget, 0, 0);
   if (ps != RDM_OK) {

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -29,20 +30,70 @@ int ilog2(uint64_t x) {
   return r;
 }
 
+// Worker threads for the host eigen-work, created on first use and kept for
+// the life of the process (the pool is never destroyed, so no thread is
+// joined during static destruction).  One job at a time; a caller that finds
+// the pool busy runs its loop itself.
+class Pool {
+ public:
+  explicit Pool(int nworkers) {
+    for (int t = 0; t < nworkers; ++t) std::thread([this] { work(); }).detach();
+    nworkers_ = nworkers;
+  }
+  void run(int n, const std::function<void(int)>& fn) {
+    std::unique_lock<std::mutex> busy(job_mu_, std::try_to_lock);
+    if (!busy.owns_lock() || nworkers_ == 0) {
+      for (int i = 0; i < n; ++i) fn(i);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      n_ = n;
+      next_ = 0;
+      active_ = nworkers_;
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (int i = next_++; i < n; i = next_++) fn(i);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return active_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void work() {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int)>* fn;
+      int n;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        fn = fn_;
+        n = n_;
+      }
+      for (int i = next_++; i < n; i = next_++) (*fn)(i);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--active_ == 0) done_cv_.notify_one();
+    }
+  }
+  std::mutex job_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int n_ = 0, active_ = 0, nworkers_ = 0;
+  uint64_t gen_ = 0;
+  std::atomic<int> next_{0};
+};
+
 void parallel_for(int n, const std::function<void(int)>& fn) {
-  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-  const int nt = std::min({n, hw, 16});
-  if (nt <= 1) {
+  static Pool* pool = new Pool(std::min(16, (int)std::max(1u, std::thread::hardware_concurrency())) - 1);
+  if (n <= 1) {
     for (int i = 0; i < n; ++i) fn(i);
     return;
   }
-  std::atomic<int> next(0);
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&] {
-      for (int i = next++; i < n; i = next++) fn(i);
-    });
-  for (auto& x : th) x.join();
+  pool->run(n, fn);
 }
 
 }  // namespace
