@@ -90,8 +90,14 @@ typedef struct {
   int32_t rows_per_lane;/* Gram kernel: rows per lane (0 = tuned)             */
   double tau;          /* breakdown threshold (0 = 1e-12 FP64, 1e-5 mixed)    */
   int32_t reserved[4]; /* reserved[0] = 1: time the step kernels with HIP
-                          events on hip_stream (results in rdm_result.diag);
-                          others must be 0                                   */
+                          events on hip_stream (results in rdm_result.diag;
+                          the steps are then launched one by one).
+                          reserved[1] = 1: launch every Lanczos step's
+                          kernels one by one; by default the steps of a solve
+                          or batch run as one captured hipGraph, replayed
+                          by later calls with the same workspace and shape
+                          (same kernels and arguments, identical results).
+                          Others must be 0.                                  */
 } rdm_options;
 
 /* Outputs of a solve, per inverse temperature (caller-owned host arrays). */

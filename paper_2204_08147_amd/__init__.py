@@ -54,7 +54,7 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_lane=0, tau=0.0,
-                 profile=False) -> _lib.Options:
+                 profile=False, eager=False) -> _lib.Options:
     o = _lib.Options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -63,6 +63,7 @@ def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_l
     o.rows_per_lane = int(rows_per_lane)
     o.tau = float(tau)
     o.reserved[0] = 1 if profile else 0
+    o.reserved[1] = 1 if eager else 0
     return o
 
 

@@ -15,6 +15,7 @@ struct Opts {
   uint64_t budget = 0;
   double tau = 0;
   bool profile = false;
+  bool eager = false;  // no hipGraph replay of the Lanczos steps
 };
 
 rdm_status read_opts(const rdm_options* o, Opts& r) {
@@ -26,6 +27,7 @@ rdm_status read_opts(const rdm_options* o, Opts& r) {
     r.rpl = o->rows_per_lane;
     r.tau = o->tau;
     r.profile = o->reserved[0] != 0;
+    r.eager = o->reserved[1] != 0;
   }
   if (r.prec != RDM_FP64 && r.prec != RDM_MIXED) {
     set_error("options: precision must be RDM_FP64 or RDM_MIXED");
@@ -130,7 +132,7 @@ static rdm_status solve_impl(const rdm_hamiltonian* h, const double* beta, int32
   runs[0].plan = &plans[0];
   runs[0].betas.assign(beta, beta + n_beta);
   runs[0].seed = seed;
-  s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0);
+  s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0, !o.eager);
   if (s == RDM_OK) s = runs[0].status;
   if (s == RDM_OK) s = finalize(runs[0], out);
   if (owned) (void)hipFree(ws);
@@ -243,7 +245,7 @@ rdm_status batch_impl(int32_t n_items, rdm_batch_item* items, const rdm_options*
       runs[w].betas.assign(items[wave[w]].beta, items[wave[w]].beta + items[wave[w]].n_beta);
       runs[w].seed = items[wave[w]].seed;
     }
-    s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0);
+    s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0, !o.eager);
     for (size_t w = 0; w < wave.size(); ++w) {
       rdm_batch_item& it = items[wave[w]];
       it.status = s != RDM_OK ? s : runs[w].status;

@@ -521,8 +521,93 @@ int tuned_slab(int prec, std::vector<Seg>& segs) {
   return s;
 }
 
+namespace {
+
+// The remaining Lanczos steps of a phase as one captured hipGraph.  Every
+// step launches the same kernels with the same arguments (the step index and
+// all per-column scalars live in device memory), so a graph captured once per
+// (segment table address, launch shape, step count) is replayed by later
+// solves that reuse the workspace; the segment table itself is uploaded
+// before each phase.  Capture and replay run on a private stream per device
+// that is ordered after / before the caller's stream with events, so the
+// caller's stream may be the legacy default stream.
+struct GraphKey {
+  int device;
+  const void* dsegs;
+  int nseg, norm, apply, xz, slab, cmax, prec, nsteps;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(device, dsegs, nseg, norm, apply, xz, slab, cmax, prec, nsteps) <
+           std::tie(o.device, o.dsegs, o.nseg, o.norm, o.apply, o.xz, o.slab, o.cmax, o.prec, o.nsteps);
+  }
+};
+constexpr size_t kMaxGraphs = 64;
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+std::vector<GraphKey> g_graph_order;  // insertion order, for eviction
+std::map<int, hipStream_t> g_graph_stream;
+
+rdm_status graph_steps(int prec, Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, int nsteps,
+                       hipStream_t st) {
+  int dev = 0;
+  RDM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  hipStream_t gs;
+  auto its = g_graph_stream.find(dev);
+  if (its == g_graph_stream.end()) {
+    RDM_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    g_graph_stream[dev] = gs;
+  } else {
+    gs = its->second;
+  }
+  const GraphKey key{dev, dsegs, nseg, L.norm, L.apply, L.xz, slab, cmax, prec, nsteps};
+  hipGraphExec_t exec = nullptr;
+  auto it = g_graphs.find(key);
+  if (it != g_graphs.end()) {
+    exec = it->second;
+  } else {
+    hipGraph_t graph = nullptr;
+    RDM_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    rdm_status s = RDM_OK;
+    for (int i = 0; i < nsteps && s == RDM_OK; ++i) s = launch_step(prec, dsegs, nseg, L, slab, cmax, gs, nullptr);
+    const hipError_t e = hipStreamEndCapture(gs, &graph);
+    if (s != RDM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    RDM_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    RDM_HIP(ei);
+    if (g_graphs.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(g_graphs[g_graph_order.front()]);
+      g_graphs.erase(g_graph_order.front());
+      g_graph_order.erase(g_graph_order.begin());
+    }
+    g_graphs[key] = exec;
+    g_graph_order.push_back(key);
+  }
+  hipEvent_t before, after;
+  RDM_HIP(hipEventCreateWithFlags(&before, hipEventDisableTiming));
+  const hipError_t e1 = hipEventCreateWithFlags(&after, hipEventDisableTiming);
+  if (e1 != hipSuccess) {
+    (void)hipEventDestroy(before);
+    RDM_HIP(e1);
+  }
+  hipError_t e = hipEventRecord(before, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(gs, before, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, gs);
+  if (e == hipSuccess) e = hipEventRecord(after, gs);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, after, 0);
+  (void)hipEventDestroy(before);
+  (void)hipEventDestroy(after);
+  RDM_HIP(e);
+  return RDM_OK;
+}
+
+}  // namespace
+
 rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
-                     StepTimers* tm, bool tune) {
+                     StepTimers* tm, bool tune, bool graph) {
   if (hsegs.empty()) return RDM_OK;
   int kmax = 0, cmax = 0;
   for (const auto& sg : hsegs) {
@@ -592,6 +677,11 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
   const Launch ntiles = assign_tiles(hsegs);
   RDM_HIP(hipMemcpyAsync(dsegs, hsegs.data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
   if (j == 1) RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
+  if (graph && !tm && kmax - j + 1 >= 2) {
+    rdm_status s = graph_steps(prec, dsegs, nseg, ntiles, slab, cmax, kmax - j + 1, st);
+    if (s != RDM_OK) return s;
+    j = kmax + 1;
+  }
   for (; j <= kmax; ++j) {
     rdm_status s = launch_step(prec, dsegs, nseg, ntiles, slab, cmax, st, tm);
     if (s != RDM_OK) return s;
@@ -602,7 +692,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
 }
 
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
-                   bool tune) {
+                   bool tune, bool graph) {
   const int ni = (int)runs.size();
   if (ni == 0) return RDM_OK;
   const int prec = runs[0].plan->prec;
@@ -625,14 +715,14 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     segs.push_back(seg_of(r, 0, MODE_LANCZOS, tau));
     segs.push_back(seg_of(r, 1, MODE_LANCZOS, tau));
   }
-  rdm_status s = run_phase(segs, dsegs, prec, 0, st, profile ? &tm : nullptr, tune);
+  rdm_status s = run_phase(segs, dsegs, prec, 0, st, profile ? &tm : nullptr, tune, graph);
   if (s != RDM_OK) return s;
   for (auto& r : runs) r.status = host_phase(r, st);
   // pass 2 (two-pass plans): regenerate u_j from the stored coefficients
   segs.clear();
   for (auto& r : runs)
     if (r.plan->two_pass && r.status == RDM_OK) segs.push_back(seg_of(r, 0, MODE_REGEN, tau));
-  if ((s = run_phase(segs, dsegs, prec, 1, st, nullptr, tune)) != RDM_OK) return s;
+  if ((s = run_phase(segs, dsegs, prec, 1, st, nullptr, tune, graph)) != RDM_OK) return s;
   Timers tg;
   tg.on = profile;
   for (auto& r : runs) {
@@ -751,7 +841,7 @@ rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uin
   // relative to ws itself
   segs.push_back(make_seg(g, op, ws, MODE_LANCZOS, which == 0 ? START_SYSBATH : START_BATH, h->n_s, h->n_b,
                           seed, tau));
-  s = run_phase(segs, (Seg*)ws, prec, 0, st, nullptr, slab == 0);
+  s = run_phase(segs, (Seg*)ws, prec, 0, st, nullptr, slab == 0, false);
   HostHist hh;
   if (s == RDM_OK) s = fetch_hist(g, ws, hh, st);
   if (s == RDM_OK && hipStreamSynchronize(st) != hipSuccess) {

@@ -85,8 +85,9 @@ void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int r
 rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
                          int mode_req, uint64_t budget, int slab_opt, int rpl_opt);
 size_t batch_header_bytes(const std::vector<InstPlan>& plans);
+// graph: replay the Lanczos steps as a captured hipGraph (unless profiling)
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
-                   bool tune);
+                   bool tune, bool graph);
 
 // Phases (used by execute and by the serving engine).
 rdm_status bind_ops(InstRun& r, hipStream_t st);
@@ -105,8 +106,9 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
                        StepTimers* tm);
 // Runs every step of a phase.  tune: choose the panels per lane by timing the
 // first steps (cached per shape); otherwise the segments' own value is used.
+// graph: the steps after tuning run as one captured hipGraph (not with tm).
 rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
-                     StepTimers* tm, bool tune);
+                     StepTimers* tm, bool tune, bool graph);
 // Panels per lane for a launch over these segments: the cached measurement
 // for the shape of the largest one, else one panel.
 int tuned_slab(int prec, std::vector<Seg>& segs);

@@ -274,6 +274,37 @@ def test_two_pass_is_bitwise_stored(prec, name):
         assert np.array_equal(a[key], b[key]), key
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(prec):
+    # the default path replays the captured Lanczos steps as one hipGraph;
+    # several replays, with eager solves and other device work in between,
+    # must each give exactly the eager result
+    names = ["lr_2+9", "xz_2+14"]
+    insts = {n: SOLVE_CASES[n]() for n in names}
+    hs = {n: H(i) for n, i in insts.items()}
+    ws = {n: torch.empty(rdm.workspace_size(hs[n], len(i.betas), i.n_v, i.k, precision=prec),
+                         dtype=torch.uint8, device="cuda") for n, i in insts.items()}
+    eager = {n: rdm.solve(hs[n], i.betas, i.n_v, i.k, i.seed, precision=prec, workspace=ws[n], eager=True)
+             for n, i in insts.items()}
+    for rep in range(3):
+        for n, i in insts.items():
+            got = rdm.solve(hs[n], i.betas, i.n_v, i.k, i.seed, precision=prec, workspace=ws[n])
+            for key in ("rho", "h_star", "log_z", "entropy"):
+                assert np.array_equal(got[key], eager[n][key]), (rep, n, key)
+            junk = torch.randn(1 << 20, device="cuda")
+            (junk * 2).sum().item()
+        again = rdm.solve(hs[names[0]], insts[names[0]].betas, insts[names[0]].n_v, insts[names[0]].k,
+                          insts[names[0]].seed, precision=prec, workspace=ws[names[0]], eager=True)
+        assert np.array_equal(again["rho"], eager[names[0]]["rho"])
+    # a batch (one graph over all segments) equals the eager batch
+    items = [dict(h=hs[n], betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for n, i in insts.items()]
+    b1 = rdm.solve_batch(items, precision=prec, eager=True)
+    for rep in range(2):
+        b2 = rdm.solve_batch(items, precision=prec)
+        for x, y in zip(b1, b2):
+            assert np.array_equal(x["rho"], y["rho"]) and np.array_equal(x["log_z"], y["log_z"])
+
+
 def test_auto_mode_falls_back_to_two_pass_under_budget():
     inst = SOLVE_CASES["lr_2+9"]()
     h = H(inst)
