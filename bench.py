@@ -46,7 +46,9 @@ def parse():
                     help="lr: the metric's workload (default); batch: 64 heterogeneous sparse XXZ "
                          "instances in one batched solve; large: 3+23 spins (dim 2^26) two-pass; "
                          "serve: Poisson arrivals of transverse-field requests")
-    ap.add_argument("--requests", type=int, default=400, help="serve: timed requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests at the offered rate")
+    ap.add_argument("--steady-requests", type=int, default=300,
+                    help="serve: requests at 0.7x the measured capacity")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
@@ -77,35 +79,39 @@ def read_traffic(name):
         return None
 
 
-def cpu_baseline(inst, budget_s=20.0):
-    """The oracle's FP64 Lanczos path (as it stands) on a bounded sample: a few
-    Lanczos steps of one start column, scaled to a full solve (every column,
-    k steps, plus the bath run)."""
+def _oracle_worker(h_index, n_b, column, steps):
+    """One host process: the oracle's FP64 Lanczos on one start column of the
+    long-range instance; returns the seconds the steps took."""
     from threadpoolctl import threadpool_limits
     from oracle import exact, lanczos as olz, spin
-    with threadpool_limits(limits=1):
-        return _cpu_baseline(inst, budget_s, exact, olz, spin)
-
-
-def _cpu_baseline(inst, budget_s, exact, olz, spin):
+    from workloads import cfg_long_range
+    inst = cfg_long_range(h_index, n_b=n_b)
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
-    x0 = exact.start_columns(inst)[:, 0]
-    t0 = time.perf_counter()
-    olz.lanczos(op.apply, x0, 1, keep_q=False)
-    t = time.perf_counter() - t0
-    steps = 1
-    if t < budget_s / 4:
-        steps = max(2, min(inst.k, int(budget_s / max(t, 1e-3))))
+    x0 = exact.start_columns(inst)[:, column]
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         olz.lanczos(op.apply, x0, steps, keep_q=False)
-        t = time.perf_counter() - t0
-    per_step_col = t / steps
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(inst, h_index, n_b, steps=2):
+    """The oracle's FP64 Lanczos path (as it stands), parallel over start
+    columns with one process per host core (at most 16), on a bounded sample:
+    `steps` Lanczos steps of one column per process.  Throughput = processes x
+    steps / slowest process, scaled to a whole solve (every column, k steps,
+    plus the bath run)."""
+    import multiprocessing as mp
+    nproc = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")  # fresh interpreters: the parent holds a GPU context
+    with ctx.Pool(nproc) as pool:
+        times = pool.starmap(_oracle_worker, [(h_index, n_b, c % inst.n_cols, steps) for c in range(nproc)])
+    col_steps_per_s = nproc * steps / max(times)
     cols = inst.n_cols + inst.n_v * (inst.d_b / inst.dim)  # bath columns are 1/d_s the size
-    t_solve = per_step_col * inst.k * cols
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 Lanczos steps of 1 of {inst.n_cols} start columns "
-                      f"(dim 2^{inst.n}), {t:.1f} s, scaled x{inst.k / steps:.0f} steps "
-                      f"x{cols:.2f} columns (NumPy, BLAS limited to one thread)"}
+    t_solve = inst.k * cols / col_steps_per_s
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{steps} FP64 Lanczos steps of one start column in each of {nproc} processes "
+                      f"(dim 2^{inst.n}), slowest {max(times):.1f} s, scaled to {inst.k} steps x "
+                      f"{cols:.2f} columns (NumPy, BLAS one thread per process)"}
 
 
 def operator_work(nbits, cols, nnz, transform, s, k):
@@ -229,28 +235,27 @@ def bench_large(args):
 def bench_serve(args):
     """Serving: requests with N ~ U{14..24}, d_s in {2,4}, ZZ chain J = 1 with
     x-field h ~ U(0,2), beta log-uniform in [0.1,10], n_v = 8, k = 60, mixed
-    precision, submitted to the continuous-batching engine.  Reports the
-    closed-loop capacity and the latency of a Poisson arrival run."""
+    precision, submitted to the continuous-batching engine.  Three runs:
+    closed loop (200 requests submitted at once: saturated capacity), Poisson
+    arrivals at the offered rate (args.requests requests; above capacity the
+    queue, and so the latency, grows with the run's length), and Poisson
+    arrivals at 0.7x the measured capacity (steady state)."""
     import threading
-    import torch
     import paper_2204_08147_amd as rdm
     from workloads import poisson_arrivals, tfim_request
-    n_warm = 20
-    reqs = [tfim_request(r) for r in range(args.requests + n_warm + 200)]
-    hs = [rdm.Hamiltonian.from_instance(i) for i in reqs]
     srv = rdm.Server(hbm_budget=int(200e9), max_active=64, precision="mixed")
-    try:
-        # closed loop: everything submitted at once -> saturated capacity
-        t0 = time.perf_counter()
-        tk = [srv.submit(hs[i], reqs[i].betas, reqs[i].n_v, reqs[i].k, reqs[i].seed)
-              for i in range(n_warm, n_warm + 200)]
-        for t in tk:
-            assert srv.wait(t)["status"] == 0
-        capacity = 200 / (time.perf_counter() - t0)
-        # open loop: Poisson arrivals
-        arr = poisson_arrivals(args.requests, args.rate)
-        done = {}
-        pending = {}
+    next_req = [0]
+    keep = []  # Hamiltonians stay alive (and their device tables resident) until the end
+
+    def new_request():
+        inst = tfim_request(next_req[0])
+        next_req[0] += 1
+        return inst, rdm.Hamiltonian.from_instance(inst)
+
+    def open_loop(n, rate):
+        """n Poisson arrivals at rate/s; returns (solves/s, latencies in s)."""
+        arr = poisson_arrivals(n, rate, seed=int(rate * 1000) + n)
+        done, pending = {}, {}
         lock = threading.Lock()
         stop = [False]
 
@@ -270,39 +275,64 @@ def bench_serve(args):
         th.start()
         start = time.perf_counter()
         sub = {}
-        base = n_warm + 200
-        for i in range(args.requests):
+        for i in range(n):
             now = time.perf_counter() - start
             if arr[i] > now:
                 time.sleep(arr[i] - now)
-            j = base + i
+            if i % 200 == 0:
+                print(f"[serve] rate {rate:.1f}/s: submitted {i} of {n}, {len(done)} done", file=sys.stderr,
+                      flush=True)
+            inst, h = new_request()
+            keep.append(h)
             sub[i] = time.perf_counter()
-            t = srv.submit(hs[j % len(hs)], reqs[j % len(reqs)].betas, reqs[j % len(reqs)].n_v,
-                           reqs[j % len(reqs)].k, reqs[j % len(reqs)].seed)
+            t = srv.submit(h, inst.betas, inst.n_v, inst.k, inst.seed)
             with lock:
                 pending[t] = i
+        last = time.perf_counter()
         while True:
             with lock:
                 if not pending:
                     break
             time.sleep(0.01)
+            if time.perf_counter() - last > 20:
+                last = time.perf_counter()
+                print(f"[serve] draining: {len(pending)} pending", file=sys.stderr, flush=True)
         stop[0] = True
         th.join()
         total = time.perf_counter() - start
+        assert all(done[i][1] == 0 for i in range(n))
+        return n / total, np.array([done[i][0] - sub[i] for i in range(n)])
+
+    try:
+        # closed loop: everything submitted at once -> saturated capacity
+        batch = [new_request() for _ in range(200)]
+        t0 = time.perf_counter()
+        tk = [srv.submit(h, i.betas, i.n_v, i.k, i.seed) for i, h in batch]
+        for t in tk:
+            assert srv.wait(t)["status"] == 0
+        capacity = 200 / (time.perf_counter() - t0)
+        keep.extend(h for _, h in batch)
+        print(f"[serve] closed-loop capacity {capacity:.2f} solves/s", file=sys.stderr, flush=True)
+        rate_a, lat_a = open_loop(args.requests, args.rate)
+        steady = 0.7 * capacity
+        rate_b, lat_b = open_loop(args.steady_requests, steady)
         stats = srv.stats()
     finally:
         srv.close()
-    lat = np.array([done[i][0] - sub[i] for i in range(args.requests)])
-    assert all(done[i][1] == 0 for i in range(args.requests))
-    return {"metric": "serving: solves/s and p50/p99 latency", "value": round(args.requests / total, 3),
+        for h in keep:
+            h.close()
+    pct = lambda lat, q: round(1e3 * float(np.percentile(lat, q)), 2)  # noqa: E731
+    return {"metric": "serving: solves/s and p50/p99 latency", "value": round(rate_a, 3),
             "unit": "solves/s", "dtype": "f32 vectors + f64 reductions",
             "config": {"workload": f"Poisson arrivals {args.rate}/s of transverse-field ZZ-chain "
                                    "requests, N in [14,24], d_s in {2,4}, beta log-U[0.1,10], n_v=8, k=60",
                        "requests": args.requests},
-            "capacity_closed_loop": round(capacity, 3), "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
-            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
-            "offered_rate": args.rate, "peak_active": stats["peak_active"],
-            "engine_steps": stats["steps"], "peak_device_bytes": stats["peak_bytes"]}
+            "capacity_closed_loop": round(capacity, 3),
+            "p50_ms": pct(lat_a, 50), "p99_ms": pct(lat_a, 99), "offered_rate": args.rate,
+            "steady": {"offered_rate": round(steady, 3), "requests": args.steady_requests,
+                       "solves_per_s": round(rate_b, 3), "p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99)},
+            "peak_active": stats["peak_active"], "engine_steps": stats["steps"],
+            "peak_device_bytes": stats["peak_bytes"]}
 
 
 def main():
@@ -387,6 +417,20 @@ def main():
     value = n_solves / wall_m
     ms_per_step = 1e3 * wall_m / args.steps
 
+    # measured stream-copy ceiling: 1 GiB -> 1 GiB device copy
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+
     # roofline of the dominant kernel: the apply launch (H_t and H_b segments)
     info = hs[0].info()
     nnz = 1 + info["hops_uniform"] + 0.5 * info["hops_parity"]
@@ -398,7 +442,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(inst0)
+        cpu = cpu_baseline(inst0, 0, args.n_b)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,
@@ -421,6 +465,7 @@ def main():
         "fp64": None if fp64 is None else {k2: round(v, 4) for k2, v in fp64.items()},
         "mixed_over_fp64": None if fp64 is None else round(value / fp64["solves_per_s"], 3),
         "roofline": roof,
+        "copy_ceiling": {"gbs": round(copy_gbs, 1), "step_frac_of_copy": round(achieved_gbs / copy_gbs, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
