@@ -59,7 +59,8 @@ typedef enum {
 } rdm_status;
 
 enum { RDM_FP64 = 0, RDM_MIXED = 1 };                 /* rdm_options.precision */
-enum { RDM_AUTO = 0, RDM_STORED_Q = 1, RDM_TWO_PASS = 2 }; /* rdm_options.mode  */
+enum { RDM_AUTO = 0, RDM_STORED_Q = 1, RDM_TWO_PASS = 2 };  /* rdm_options.mode */
+enum { RDM_PER_COLUMN = 0, RDM_BLOCK = 1 };           /* rdm_options.method */
 
 /* One two-site term: jx sx_i sx_j + jy sy_i sy_j + jz sz_i sz_j (Pauli),
  * eqn:Ht.  0 <= i, j < N, i != j; (i, j) and (j, i) denote the same pair. */
@@ -89,15 +90,23 @@ typedef struct {
                           4 (0 = tuned); results do not depend on it         */
   int32_t rows_per_lane;/* Gram kernel: rows per lane (0 = tuned)             */
   double tau;          /* breakdown threshold (0 = 1e-12 FP64, 1e-5 mixed)    */
-  int32_t reserved[4]; /* reserved[0] = 1: time the step kernels with HIP
-                          events on hip_stream (results in rdm_result.diag;
-                          the steps are then launched one by one).
-                          reserved[1] = 1: launch every Lanczos step's
-                          kernels one by one; by default the steps of a solve
-                          or batch run as one captured hipGraph, replayed
-                          by later calls with the same workspace and shape
-                          (same kernels and arguments, identical results).
-                          Others must be 0.                                  */
+  int32_t profile;      /* 1: time the step kernels with HIP events on
+                           hip_stream (results in rdm_result.diag; the steps
+                           are then launched one by one)                      */
+  int32_t eager;        /* 1: launch every Lanczos step's kernels one by one;
+                           by default the steps of a solve or batch run as one
+                           captured hipGraph, replayed by later calls with
+                           the same workspace and shape (same kernels and
+                           arguments, identical results)                      */
+  int32_t method;       /* RDM_PER_COLUMN (0): Lanczos on every start column
+                           and exp(-beta H/2) by function approximation, then
+                           the Gram of the recombined columns (the hot path).
+                           RDM_BLOCK (1): the block Lanczos of Algorithm 1 on
+                           each bath vector's d_s start columns and the block
+                           Gauss quadrature E_1^T exp(-beta T) E_1 (eqn:fT,
+                           eqn:trB_est); single solves only (rdm_solve,
+                           rdm_solve_ws), no Lanczos basis is kept            */
+  int32_t reserved;     /* must be 0                                          */
 } rdm_options;
 
 /* Outputs of a solve, per inverse temperature (caller-owned host arrays). */
@@ -116,7 +125,7 @@ typedef struct {
                        (ms; hop-table operators), [9] mean Gram kernel time
                        (ms), [10] mean transform pass 0 time (ms; norm step
                        and first transform) -- [7..10] only when
-                       rdm_options.reserved[0] = 1 (event timing), else 0 --
+                       rdm_options.profile = 1 (event timing), else 0 --
                        [11..15] zero; then per beta {ln Z_t, ln Z_b}.        */
 } rdm_result;
 
@@ -238,6 +247,16 @@ rdm_status rdm_lanczos(const rdm_hamiltonian* h, int32_t which, int32_t n_v, int
  * rotations are replayed on e_1 instead of forming the eigenvectors. */
 rdm_status rdm_tridiag_fa(int32_t kk, const double* alpha, const double* beta, int32_t n_beta,
                           const double* betas, double e0, double* theta, double* y, double* quad);
+
+/* Host routine of the block variant (Algorithm 1 + eqn:fT): for a symmetric
+ * n x n matrix t (host, row-major; the block tridiagonal T of a block
+ * Lanczos run with blocks of b columns) form E_1^T exp(-beta (t - e0)) E_1,
+ * the leading b x b block, for each of n_beta inverse temperatures
+ * (f: host out, n_beta x b x b row-major), and the smallest eigenvalue of t
+ * (min_eig: host out, may be NULL).  Householder reduction to tridiagonal
+ * form, then implicit symmetric QR; the eigenvectors are never formed. */
+rdm_status rdm_block_quadrature(int32_t n, int32_t b, const double* t, int32_t n_beta,
+                                const double* betas, double e0, double* min_eig, double* f);
 
 /* ---- Serving: continuous batching over one device stream ---- */
 

@@ -53,8 +53,11 @@ def _stream_handle(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
+METHODS = {"per_column": 0, "block": 1}
+
+
 def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_lane=0, tau=0.0,
-                 profile=False, eager=False) -> _lib.Options:
+                 profile=False, eager=False, method="per_column") -> _lib.Options:
     o = _lib.Options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -62,8 +65,9 @@ def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_l
     o.slab = int(slab)
     o.rows_per_lane = int(rows_per_lane)
     o.tau = float(tau)
-    o.reserved[0] = 1 if profile else 0
-    o.reserved[1] = 1 if eager else 0
+    o.profile = 1 if profile else 0
+    o.eager = 1 if eager else 0
+    o.method = METHODS[method] if isinstance(method, str) else int(method)
     return o
 
 
@@ -239,6 +243,19 @@ def lanczos(h: Hamiltonian, *, which: int, n_v: int, k: int, seed: int, stream=N
                            _dptr(a), _dptr(b), kc.ctypes.data_as(C.POINTER(C.c_int32))),
            "rdm_lanczos")
     return a, b, kc
+
+
+def block_quadrature(t, b: int, betas, e0: float):
+    """Host routine: E_1^T exp(-beta (T - e0)) E_1 (b x b) for a symmetric T and
+    each beta, and the smallest eigenvalue of T."""
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    bt = np.ascontiguousarray(betas, dtype=np.float64)
+    n = tt.shape[0]
+    f = np.zeros((len(bt), b, b))
+    mn = C.c_double(0.0)
+    _check(LIB.rdm_block_quadrature(n, b, _dptr(tt), len(bt), _dptr(bt), float(e0), C.byref(mn), _dptr(f)),
+           "rdm_block_quadrature")
+    return f, mn.value
 
 
 def tridiag_fa(alpha, beta, betas, e0: float):

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "librdm.so")
 RDM_OK, RDM_E_INVALID, RDM_E_NOMEM, RDM_E_DEVICE, RDM_E_NONFINITE, RDM_E_BUSY = 0, -1, -2, -3, -4, -5
 RDM_FP64, RDM_MIXED = 0, 1
 RDM_AUTO, RDM_STORED_Q, RDM_TWO_PASS = 0, 1, 2
+RDM_PER_COLUMN, RDM_BLOCK = 0, 1
 DIAG_FIXED = 16
 
 STATUS_NAMES = {0: "RDM_OK", -1: "RDM_E_INVALID", -2: "RDM_E_NOMEM", -3: "RDM_E_DEVICE",
@@ -28,7 +29,7 @@ class Coupling(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("mode", C.c_int32), ("hbm_budget", C.c_uint64),
                 ("slab", C.c_int32), ("rows_per_lane", C.c_int32), ("tau", C.c_double),
-                ("reserved", C.c_int32 * 4)]
+                ("profile", C.c_int32), ("eager", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -74,6 +75,9 @@ SIGNATURES = [
     ("rdm_tridiag_fa", C.c_int32,
      [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
       C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("rdm_block_quadrature", C.c_int32,
+     [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double), C.c_double,
+      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("rdm_server_create", C.c_int32, [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
     ("rdm_server_submit", C.c_int32,
      [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
@@ -94,7 +98,7 @@ def load(path: str = LIB_PATH):
     # kernels; loading librdm.so first would put two HIP runtimes in the process.
     import torch  # noqa: F401
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with `python -m paper_2204_08147_amd.build` "
+        raise ImportError(f"{path} is missing: build it with `python paper_2204_08147_amd/build.py` "
                           "(there is no fallback implementation)")
     lib = C.CDLL(path)
     for name, res, args in SIGNATURES:

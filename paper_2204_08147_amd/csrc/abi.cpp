@@ -16,6 +16,7 @@ struct Opts {
   double tau = 0;
   bool profile = false;
   bool eager = false;  // no hipGraph replay of the Lanczos steps
+  int method = RDM_PER_COLUMN;
 };
 
 rdm_status read_opts(const rdm_options* o, Opts& r) {
@@ -26,8 +27,13 @@ rdm_status read_opts(const rdm_options* o, Opts& r) {
     r.slab = o->slab;
     r.rpl = o->rows_per_lane;
     r.tau = o->tau;
-    r.profile = o->reserved[0] != 0;
-    r.eager = o->reserved[1] != 0;
+    r.profile = o->profile != 0;
+    r.eager = o->eager != 0;
+    r.method = o->method;
+    if (o->reserved != 0) {
+      set_error("options: reserved must be 0");
+      return RDM_E_INVALID;
+    }
   }
   if (r.prec != RDM_FP64 && r.prec != RDM_MIXED) {
     set_error("options: precision must be RDM_FP64 or RDM_MIXED");
@@ -43,6 +49,10 @@ rdm_status read_opts(const rdm_options* o, Opts& r) {
   }
   if (!(r.tau >= 0.0) || !std::isfinite(r.tau)) {
     set_error("options: tau must be finite and >= 0");
+    return RDM_E_INVALID;
+  }
+  if (r.method != RDM_PER_COLUMN && r.method != RDM_BLOCK) {
+    set_error("options: method must be RDM_PER_COLUMN or RDM_BLOCK");
     return RDM_E_INVALID;
   }
   if (r.tau == 0.0) r.tau = r.prec == RDM_FP64 ? 1e-12 : 1e-5;
@@ -92,6 +102,12 @@ extern "C" rdm_status rdm_workspace_size(const rdm_hamiltonian* h, int32_t n_bet
     return RDM_E_INVALID;
   }
   if ((s = default_budget(o.budget)) != RDM_OK) return s;
+  if (o.method == RDM_BLOCK) {
+    BlockPlan bp;
+    if ((s = block_plan(bp, h, n_beta, n_v, k, o.prec, o.budget)) != RDM_OK) return s;
+    *bytes = bp.bytes;
+    return RDM_OK;
+  }
   std::vector<InstPlan> plans(1);
   s = plan_instance(plans[0], h, n_beta, n_v, k, o.prec, o.mode, o.budget, o.slab, o.rpl);
   if (s != RDM_OK) return s;
@@ -112,11 +128,29 @@ static rdm_status solve_impl(const rdm_hamiltonian* h, const double* beta, int32
   }
   if (dev_ws && !o.budget) o.budget = ws_bytes;
   if ((s = default_budget(o.budget)) != RDM_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (o.method == RDM_BLOCK) {
+    BlockPlan bp;
+    if ((s = block_plan(bp, h, n_beta, n_v, k, o.prec, o.budget)) != RDM_OK) return s;
+    char* ws = (char*)dev_ws;
+    bool owned = false;
+    if (ws) {
+      if (ws_bytes < bp.bytes || ((uintptr_t)ws & 255)) {
+        set_error("workspace too small or not 256-byte aligned: need " + std::to_string(bp.bytes));
+        return RDM_E_INVALID;
+      }
+    } else {
+      RDM_HIP(hipMalloc(&ws, bp.bytes));
+      owned = true;
+    }
+    s = block_solve(bp, beta, seed, o.tau, ws, st, o.profile, out);
+    if (owned) (void)hipFree(ws);
+    return s;
+  }
   std::vector<InstPlan> plans(1);
   s = plan_instance(plans[0], h, n_beta, n_v, k, o.prec, o.mode, o.budget, o.slab, o.rpl);
   if (s != RDM_OK) return s;
   const size_t need = batch_header_bytes(plans) + plans[0].bytes;
-  hipStream_t st = (hipStream_t)hip_stream;
   char* ws = (char*)dev_ws;
   bool owned = false;
   if (ws) {
@@ -214,6 +248,10 @@ rdm_status batch_impl(int32_t n_items, rdm_batch_item* items, const rdm_options*
   if (s != RDM_OK) return s;
   if (n_items < 0 || (n_items > 0 && !items)) {
     set_error("rdm_solve_batch: bad item list");
+    return RDM_E_INVALID;
+  }
+  if (o.method != RDM_PER_COLUMN) {
+    set_error("batched solves use the per-column method");
     return RDM_E_INVALID;
   }
   if (dev_ws && !o.budget) o.budget = ws_bytes;

@@ -91,6 +91,21 @@ struct TridiagEig {
   void solve(const double* alpha, const double* beta, int n);
   // y = S diag(g) S^T e_1 for g_i given.
   void apply_fn(const double* g, double* y) const;
+  // y = S diag(g) S^T x for any x (n).
+  void apply_fn_vec(const double* g, const double* x, double* y) const;
+};
+
+// Eigensystem of a dense symmetric matrix through Householder reduction to
+// tridiagonal form (A = P T P^T) and TridiagEig on T.  quad() forms the
+// leading b x b block of f(A) for f(x) = exp(-beta (x - e0)).
+struct DenseSymEig {
+  int n = 0;
+  std::vector<double> p;  // P, row-major n x n
+  TridiagEig te;
+  bool ok = true;
+  void solve(const double* a, int n);  // a: row-major n x n, symmetric
+  double min_eig() const;
+  void quad(int b, double beta, double e0, double* f) const;  // f: b x b row-major
 };
 
 // Eigendecomposition of a small symmetric matrix (cyclic Jacobi, n <= 16):

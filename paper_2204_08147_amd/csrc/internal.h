@@ -111,6 +111,33 @@ struct Seg {
   double tau;
 };
 
+// Block Lanczos (Algorithm 1) on the d_s start columns of every bath vector:
+// groups g = 0..G-1 of DS consecutive columns.  Per-group d_s x d_s matrices
+// in mats[(BM_x * G + g) * DS * DS + a * DS + b] (row a, column b), FP64.
+enum {
+  BM_BPREV = 0,  // B_{j-1} (zero at j = 1 and after breakdown)
+  BM_A,          // A_j
+  BM_RINV,       // inverse Cholesky factor of the current QR pass
+  BM_R1,         // Cholesky factor of the first QR pass
+  BM_SCALE,      // [0]: running max |entry| of the A_i, B_i (breakdown scale), [1]: frozen
+  BM_COUNT
+};
+enum { BLK_A = 0, BLK_G = 1, BLK_G2 = 2 };  // reduction phases
+struct BSeg {
+  void* Q;            // three ring slots of dim x cpad (panel layout): slot(j) = (j-1) % 3
+  void* R;            // dim x cpad: H q_j, then Z
+  double* part;       // [n_rt][G][DS*DS] per-row-tile partial sums
+  double* mats;       // [BM_COUNT][G][DS*DS]
+  double* a_hist;     // [k][G][DS*DS]  A_j
+  double* b_hist;     // [k][G][DS*DS]  B_j (Q_{j+1} B_j = Z)
+  int32_t* kc;        // [G] blocks before breakdown
+  uint64_t blk;       // dim * cpad
+  int32_t nbits, cpad, C, G, k;
+  int32_t rpl;        // rows per lane: a row tile is kBlock * rpl rows
+  int32_t n_rt, n_cb; // row tiles, column blocks of max(DS, panel width) columns
+  double tau;
+};
+
 // Work item of the apply / norm kernels, derived from blockIdx.x: segment s
 // owns workgroups [tile_base, tile_base + n_row_tiles * P/S), slab-major.
 struct Tile {
@@ -154,6 +181,13 @@ template <typename T>
 hipError_t launch_gram(const GSeg* gs, const GTile* tiles, int ntiles, int ds, int nb_chunk,
                        int beta0, int k, hipStream_t st);
 hipError_t launch_colsum(const double* part, int nrows, int width, double* out, hipStream_t st);
+// block Lanczos: one launch of the update kernel for step j (phase BLK_A:
+// Z = H q_j - q_{j-1} B^T and A partials; BLK_G: Z -= q_j A and Gram partials;
+// BLK_G2: q_{j+1} = Z R^-1 and Gram partials; 3: q_{j+1} = q_{j+1} R^-1), and
+// the per-group reduction + small-matrix step of a phase
+template <typename T>
+hipError_t launch_block_update(const BSeg* bs, int ds, int phase, int j, int n_rt, int n_cb, hipStream_t st);
+hipError_t launch_block_reduce(const BSeg* bs, int ds, int G, int phase, int j, hipStream_t st);
 template <typename T>
 hipError_t launch_start_block(int ns_log, int nb, int C, uint64_t seed, int kind, T* out,
                               int nbits, int cpad, hipStream_t st);

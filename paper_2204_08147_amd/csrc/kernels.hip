@@ -792,6 +792,260 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
 }
 
 // ---------------------------------------------------------------------------
+// Block Lanczos (Algorithm 1) on the DS start columns of each bath vector.
+// A lane owns one row of CB = max(DS, W) consecutive columns (NG = CB / DS
+// groups); every update mixes only the columns of one group.  Per-group
+// partial sums of d_s x d_s products go to part[rt][g][DS*DS] (FP64, fixed
+// order), reduced per group by k_block_reduce.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ typename PanelT<T>::V* blk_slot(const CONST_AS BSeg& bs, int j) {
+  return (typename PanelT<T>::V*)bs.Q + (uint64_t)((j - 1) % 3) * (bs.blk / PanelT<T>::W);
+}
+
+template <typename T, int DS>
+__global__ __launch_bounds__(kBlock) void k_block_update(const BSeg* __restrict__ bsp, int phase, int j) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  constexpr int CB = DS > W ? DS : W;
+  constexpr int NP = CB / W;
+  constexpr int NG = CB / DS;
+  constexpr int NE = DS * DS;
+  __shared__ double lds[4 * NG * NE];
+  const CONST_AS BSeg& bs = *(const CONST_AS BSeg*)bsp;
+  const int rt = (int)blockIdx.x % bs.n_rt, cb = (int)blockIdx.x / bs.n_rt;
+  const uint32_t dim = 1u << bs.nbits;
+  const uint64_t ps = dim;
+  const int p0 = cb * NP;
+  const int g0 = cb * NG;
+  const int G = bs.G;
+  const CONST_AS double* mats = (const CONST_AS double*)bs.mats;
+  auto mat = [&](int which, int i, int a, int b) -> T {
+    return (T)mats[((uint64_t)which * G + g0 + i) * NE + a * DS + b];
+  };
+  V* qj = blk_slot<T>(bs, j) + (uint64_t)p0 * ps;
+  V* qn = blk_slot<T>(bs, j + 1) + (uint64_t)p0 * ps;
+  const V* qp = j > 1 ? (const V*)blk_slot<T>(bs, j - 1) + (uint64_t)p0 * ps : nullptr;
+  V* rb = (V*)bs.R + (uint64_t)p0 * ps;
+  double dq[NG * NE];
+#pragma unroll
+  for (int i = 0; i < NG * NE; ++i) dq[i] = 0.0;
+
+  for (int rr = 0; rr < bs.rpl; ++rr) {
+    const uint32_t row = ((uint32_t)rt * bs.rpl + rr) * kBlock + threadIdx.x;
+    if (row >= dim) break;
+    T x[CB], y[CB], out[CB];
+    auto load = [&](const V* base, T (&dst)[CB]) {
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) {
+        const V v = ldg(base + pp * ps, row);
+#pragma unroll
+        for (int e = 0; e < W; ++e) dst[pp * W + e] = v[e];
+      }
+    };
+    auto store = [&](V* base, const T (&src)[CB]) {
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) {
+        V v;
+#pragma unroll
+        for (int e = 0; e < W; ++e) v[e] = src[pp * W + e];
+        stg(base + pp * ps, row, v);
+      }
+    };
+    if (phase == BLK_A) {
+      // Z = H q_j - q_{j-1} B_{j-1}^T ; A partials q_j^T Z
+      load(rb, x);
+      load(qj, y);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) out[c] = x[c];
+      if (qp) {
+        T w[CB];
+        load(qp, w);
+#pragma unroll
+        for (int i = 0; i < NG; ++i)
+#pragma unroll
+          for (int a = 0; a < DS; ++a)
+#pragma unroll
+            for (int b = 0; b < DS; ++b) out[i * DS + a] = fma_s(-w[i * DS + b], mat(BM_BPREV, i, a, b), out[i * DS + a]);
+      }
+      store(rb, out);
+#pragma unroll
+      for (int i = 0; i < NG; ++i)
+#pragma unroll
+        for (int a = 0; a < DS; ++a)
+#pragma unroll
+          for (int b = 0; b < DS; ++b)
+            dq[i * NE + a * DS + b] += (double)y[i * DS + a] * (double)out[i * DS + b];
+    } else if (phase == BLK_G) {
+      // Z <- Z - q_j A_j ; Gram partials Z^T Z
+      load(rb, x);
+      load(qj, y);
+#pragma unroll
+      for (int i = 0; i < NG; ++i)
+#pragma unroll
+        for (int a = 0; a < DS; ++a) {
+          T z = x[i * DS + a];
+#pragma unroll
+          for (int b = 0; b < DS; ++b) z = fma_s(-y[i * DS + b], mat(BM_A, i, b, a), z);
+          out[i * DS + a] = z;
+        }
+      store(rb, out);
+#pragma unroll
+      for (int i = 0; i < NG; ++i)
+#pragma unroll
+        for (int a = 0; a < DS; ++a)
+#pragma unroll
+          for (int b = 0; b < DS; ++b)
+            dq[i * NE + a * DS + b] += (double)out[i * DS + a] * (double)out[i * DS + b];
+    } else {
+      // phase 2: q_{j+1} = Z R^-1 (Gram partials for the second pass);
+      // phase 3: q_{j+1} <- q_{j+1} R^-1
+      load(phase == BLK_G2 ? (const V*)rb : (const V*)qn, x);
+#pragma unroll
+      for (int i = 0; i < NG; ++i)
+#pragma unroll
+        for (int a = 0; a < DS; ++a) {
+          T z = T(0);
+#pragma unroll
+          for (int b = 0; b <= a; ++b) z = fma_s(x[i * DS + b], mat(BM_RINV, i, b, a), z);
+          out[i * DS + a] = z;
+        }
+      store(qn, out);
+      if (phase == BLK_G2) {
+#pragma unroll
+        for (int i = 0; i < NG; ++i)
+#pragma unroll
+          for (int a = 0; a < DS; ++a)
+#pragma unroll
+            for (int b = 0; b < DS; ++b)
+              dq[i * NE + a * DS + b] += (double)out[i * DS + a] * (double)out[i * DS + b];
+      }
+    }
+  }
+  if (phase > BLK_G2) return;
+  double tot;
+  block_sum<NG * NE>(dq, lds, &tot);
+  if (threadIdx.x < NG * NE) bs.part[((uint64_t)rt * G + g0) * NE + threadIdx.x] = tot;
+}
+
+// Cholesky G = R^T R (R upper triangular, row-major DS x DS); returns the
+// smallest pivot R[i][i] (<= 0 or NaN when G is not positive definite).
+template <int DS>
+__device__ double small_chol(const double* g, double* r) {
+  double mn = INFINITY;
+  for (int i = 0; i < DS * DS; ++i) r[i] = 0.0;
+  for (int i = 0; i < DS; ++i) {
+    double d = g[i * DS + i];
+    for (int k = 0; k < i; ++k) d -= r[k * DS + i] * r[k * DS + i];
+    if (!(d > 0.0)) return d > 0.0 ? mn : (d == d ? 0.0 : d);
+    const double rii = sqrt(d);
+    r[i * DS + i] = rii;
+    mn = fmin(mn, rii);
+    for (int jj = i + 1; jj < DS; ++jj) {
+      double v = g[i * DS + jj];
+      for (int k = 0; k < i; ++k) v -= r[k * DS + i] * r[k * DS + jj];
+      r[i * DS + jj] = v / rii;
+    }
+  }
+  return mn;
+}
+// inverse of an upper-triangular R with positive diagonal
+template <int DS>
+__device__ void small_triinv(const double* r, double* ri) {
+  for (int i = 0; i < DS * DS; ++i) ri[i] = 0.0;
+  for (int c = 0; c < DS; ++c) {
+    ri[c * DS + c] = 1.0 / r[c * DS + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int k = i + 1; k <= c; ++k) v += r[i * DS + k] * ri[k * DS + c];
+      ri[i * DS + c] = -v / r[i * DS + i];
+    }
+  }
+}
+
+// one workgroup per group: sum the row-tile partials (fixed order), then the
+// small-matrix step of the phase
+template <int DS>
+__global__ __launch_bounds__(kBlock) void k_block_reduce(const BSeg* __restrict__ bsp, int phase, int j) {
+  constexpr int NE = DS * DS;
+  const BSeg& bs = *bsp;
+  const int g = blockIdx.x, G = bs.G;
+  __shared__ double red[kBlock];
+  __shared__ double tot[NE];
+  for (int e = 0; e < NE; ++e) {
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < bs.n_rt; t += kBlock) acc += bs.part[((uint64_t)t * G + g) * NE + e];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[e] = red[0];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  auto M = [&](int which) { return bs.mats + ((uint64_t)which * G + g) * NE; };
+  double* sc = M(BM_SCALE);
+  const bool frozen = sc[1] != 0.0;
+  if (phase == BLK_A) {
+    double* a = M(BM_A);
+    double mx = sc[0];
+    for (int p = 0; p < DS; ++p)
+      for (int q = 0; q < DS; ++q) {
+        const double v = frozen ? 0.0 : 0.5 * (tot[p * DS + q] + tot[q * DS + p]);
+        a[p * DS + q] = v;
+        bs.a_hist[((uint64_t)(j - 1) * G + g) * NE + p * DS + q] = v;
+        mx = fmax(mx, fabs(v));
+      }
+    sc[0] = mx;
+    return;
+  }
+  double r[NE], ri[NE];
+  if (phase == BLK_G) {
+    const double mn = frozen ? 0.0 : small_chol<DS>(tot, r);
+    if (frozen || !(mn > bs.tau * sc[0])) {
+      // breakdown: the block Krylov space closed (to the threshold) after j blocks
+      if (!frozen) bs.kc[g] = j;
+      sc[1] = 1.0;
+      for (int i = 0; i < NE; ++i) M(BM_RINV)[i] = M(BM_R1)[i] = M(BM_BPREV)[i] = 0.0;
+      return;
+    }
+    small_triinv<DS>(r, ri);
+    for (int i = 0; i < NE; ++i) {
+      M(BM_R1)[i] = r[i];
+      M(BM_RINV)[i] = ri[i];
+    }
+    return;
+  }
+  // BLK_G2: second Cholesky pass; B_j = R2 R1
+  if (frozen) {
+    for (int i = 0; i < NE; ++i) M(BM_RINV)[i] = M(BM_BPREV)[i] = 0.0;
+    return;
+  }
+  const double mn = small_chol<DS>(tot, r);
+  if (!(mn > 0.0)) {
+    bs.kc[g] = j;
+    sc[1] = 1.0;
+    for (int i = 0; i < NE; ++i) M(BM_RINV)[i] = M(BM_BPREV)[i] = 0.0;
+    return;
+  }
+  small_triinv<DS>(r, ri);
+  const double* r1 = M(BM_R1);
+  double mx = sc[0];
+  for (int p = 0; p < DS; ++p)
+    for (int q = 0; q < DS; ++q) {
+      double v = 0.0;
+      for (int t = 0; t < DS; ++t) v += r[p * DS + t] * r1[t * DS + q];
+      M(BM_BPREV)[p * DS + q] = v;
+      bs.b_hist[((uint64_t)(j - 1) * G + g) * NE + p * DS + q] = v;
+      mx = fmax(mx, fabs(v));
+    }
+  sc[0] = mx;
+  for (int i = 0; i < NE; ++i) M(BM_RINV)[i] = ri[i];
+}
+
+// ---------------------------------------------------------------------------
 // reductions of the per-tile partial sums: one workgroup per (segment,
 // column); lane i sums tiles i, i+256, ... and a fixed binary tree in LDS
 // combines the lanes, so the order never depends on scheduling.
@@ -1066,6 +1320,26 @@ hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipSt
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_block_update(const BSeg* bs, int ds, int phase, int j, int n_rt, int n_cb, hipStream_t st) {
+  const dim3 grid(n_rt * n_cb), blk(kBlock);
+  switch (ds) {
+    case 2: hipLaunchKernelGGL((k_block_update<T, 2>), grid, blk, 0, st, bs, phase, j); break;
+    case 4: hipLaunchKernelGGL((k_block_update<T, 4>), grid, blk, 0, st, bs, phase, j); break;
+    default: hipLaunchKernelGGL((k_block_update<T, 8>), grid, blk, 0, st, bs, phase, j); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_reduce(const BSeg* bs, int ds, int G, int phase, int j, hipStream_t st) {
+  switch (ds) {
+    case 2: hipLaunchKernelGGL((k_block_reduce<2>), dim3(G), dim3(kBlock), 0, st, bs, phase, j); break;
+    case 4: hipLaunchKernelGGL((k_block_reduce<4>), dim3(G), dim3(kBlock), 0, st, bs, phase, j); break;
+    default: hipLaunchKernelGGL((k_block_reduce<8>), dim3(G), dim3(kBlock), 0, st, bs, phase, j); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st) {
   if (nseg <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_red_beta, dim3(nseg, cmax), dim3(kBlock), 0, st, segs);
@@ -1132,6 +1406,8 @@ template hipError_t launch_norm<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t);
+template hipError_t launch_block_update<float>(const BSeg*, int, int, int, int, int, hipStream_t);
+template hipError_t launch_block_update<double>(const BSeg*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);

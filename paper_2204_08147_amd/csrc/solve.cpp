@@ -278,6 +278,24 @@ bool all_finite(const std::vector<double>& v) {
 // ---------------------------------------------------------------------------
 // phases shared by single solves, batches and the serving engine
 // ---------------------------------------------------------------------------
+// exported helpers (solve.h) for the block-Lanczos driver
+Seg make_plain_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int start_kind, int ns_log,
+                   int nb, uint64_t seed, double tau) {
+  return make_seg(g, op, base, mode, start_kind, ns_log, nb, seed, tau);
+}
+rdm_status fetch_history(const SegPlan& g, char* base, std::vector<double>& a, std::vector<double>& b,
+                         std::vector<double>& s, std::vector<int32_t>& kc, hipStream_t st) {
+  HostHist hh;
+  rdm_status r = fetch_hist(g, base, hh, st);
+  a.swap(hh.a);
+  b.swap(hh.b);
+  s.swap(hh.s);
+  kc.swap(hh.kc);
+  return r;
+}
+void parallel_jobs(int n, const std::function<void(int)>& fn) { parallel_for(n, fn); }
+size_t align_up(size_t x) { return al(x); }
+
 rdm_status bind_ops(InstRun& r, hipStream_t st) {
   const InstPlan& p = *r.plan;
   rdm_status s = get_device_op(p.h, 0, p.prec, st, &r.op_t);

@@ -1,6 +1,7 @@
 // Planning and execution of (batched) solves.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "host.h"
@@ -115,6 +116,31 @@ int tuned_slab(int prec, std::vector<Seg>& segs);
 rdm_status host_phase(InstRun& r, hipStream_t st);   // synchronous
 rdm_status gram_phase(InstRun& r, hipStream_t st, Timers* tg);  // synchronous
 rdm_status finalize(const InstRun& r, rdm_result* out);
+
+// helpers shared with the block-Lanczos driver
+Seg make_plain_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int start_kind, int ns_log,
+                   int nb, uint64_t seed, double tau);
+// alpha, beta, s histories ([k][cpad]) and Krylov sizes ([cpad]) of a segment
+// (asynchronous: synchronise the stream before reading)
+rdm_status fetch_history(const SegPlan& g, char* base, std::vector<double>& a, std::vector<double>& b,
+                         std::vector<double>& s, std::vector<int32_t>& kc, hipStream_t st);
+void parallel_jobs(int n, const std::function<void(int)>& fn);
+size_t align_up(size_t x);
+
+// Block Lanczos (Algorithm 1) with block Gauss quadrature: one solve.
+struct BlockPlan {
+  const rdm_hamiltonian* h = nullptr;
+  int prec = RDM_FP64, n_beta = 0, n_v = 0, k = 0, kb = 0;
+  int ds = 2, ds_log = 1, C = 0, cpad = 0, G = 0, CB = 0, n_cb = 0, rpl = 1, n_rt = 0;
+  uint64_t dim = 0, blk = 0;
+  SegPlan apply, bath;
+  size_t o_Q = 0, o_R = 0, o_part = 0, o_mats = 0, o_ah = 0, o_bh = 0, o_kc = 0;
+  size_t header = 0, bytes = 0;
+};
+rdm_status block_plan(BlockPlan& bp, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
+                      uint64_t budget);
+rdm_status block_solve(const BlockPlan& bp, const double* betas, uint64_t seed, double tau, char* ws,
+                       hipStream_t st, bool profile, rdm_result* out);
 
 // Lanczos coefficients only (rdm_lanczos).
 rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uint64_t seed, int prec,

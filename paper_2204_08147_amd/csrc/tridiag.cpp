@@ -96,6 +96,99 @@ void TridiagEig::apply_fn(const double* g, double* y) const {
   }
 }
 
+void TridiagEig::apply_fn_vec(const double* g, const double* x, double* y) const {
+  // S^T x = G_M^T (... (G_1^T x)): the rotations in recorded order, transposed
+  for (int i = 0; i < n; ++i) y[i] = x[i];
+  for (size_t t = 0; t < rot_i.size(); ++t) {
+    const int i = rot_i[t];
+    const double c = rot_c[t], s = rot_s[t];
+    const double w0 = y[i], w1 = y[i + 1];
+    y[i] = c * w0 - s * w1;
+    y[i + 1] = s * w0 + c * w1;
+  }
+  for (int i = 0; i < n; ++i) y[i] *= g[i];
+  for (size_t t = rot_i.size(); t-- > 0;) {
+    const int i = rot_i[t];
+    const double c = rot_c[t], s = rot_s[t];
+    const double w0 = y[i], w1 = y[i + 1];
+    y[i] = c * w0 + s * w1;
+    y[i + 1] = -s * w0 + c * w1;
+  }
+}
+
+// Householder tridiagonalisation (Golub & Van Loan, symmetric Householder
+// reduction): for k = 0..n-3 the reflector H = I - tau v v^T on rows/columns
+// k+1.. maps column k below the diagonal onto a multiple of e_1; the trailing
+// block B becomes H B H = B - v w^T - w v^T with p = tau B v and
+// w = p - (tau/2)(v^T p) v.  P accumulates H_0 H_1 ..., so A = P T P^T.
+void DenseSymEig::solve(const double* a_in, int nn) {
+  n = nn;
+  std::vector<double> a(a_in, a_in + (size_t)n * n);
+  p.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) p[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), pv(n), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double xn = 0.0;
+    for (int i = 0; i < m; ++i) xn += a[(size_t)(k + 1 + i) * n + k] * a[(size_t)(k + 1 + i) * n + k];
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const double x0 = a[(size_t)(k + 1) * n + k];
+    const double alpha = x0 >= 0.0 ? -xn : xn;
+    for (int i = 0; i < m; ++i) v[i] = a[(size_t)(k + 1 + i) * n + k];
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (int i = 0; i < m; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double tau = 2.0 / vv;
+    double vp = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int jj = 0; jj < m; ++jj) acc += a[(size_t)(k + 1 + i) * n + (k + 1 + jj)] * v[jj];
+      pv[i] = tau * acc;
+      vp += v[i] * pv[i];
+    }
+    for (int i = 0; i < m; ++i) w[i] = pv[i] - 0.5 * tau * vp * v[i];
+    for (int i = 0; i < m; ++i)
+      for (int jj = 0; jj < m; ++jj)
+        a[(size_t)(k + 1 + i) * n + (k + 1 + jj)] -= v[i] * w[jj] + w[i] * v[jj];
+    a[(size_t)(k + 1) * n + k] = a[(size_t)k * n + (k + 1)] = alpha;
+    for (int i = 1; i < m; ++i) a[(size_t)(k + 1 + i) * n + k] = a[(size_t)k * n + (k + 1 + i)] = 0.0;
+    // P <- P H on columns k+1..
+    for (int r = 0; r < n; ++r) {
+      double acc = 0.0;
+      for (int i = 0; i < m; ++i) acc += p[(size_t)r * n + (k + 1 + i)] * v[i];
+      acc *= tau;
+      for (int i = 0; i < m; ++i) p[(size_t)r * n + (k + 1 + i)] -= acc * v[i];
+    }
+  }
+  std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
+  for (int i = 0; i < n; ++i) d[i] = a[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = a[(size_t)(i + 1) * n + i];
+  te.solve(d.data(), e.data(), n);
+  ok = te.ok;
+}
+
+double DenseSymEig::min_eig() const {
+  double m = INFINITY;
+  for (double t : te.theta) m = std::min(m, t);
+  return m;
+}
+
+void DenseSymEig::quad(int b, double beta, double e0, double* f) const {
+  std::vector<double> g(n), x(n), y(n);
+  for (int i = 0; i < n; ++i) g[i] = std::exp(-beta * (te.theta[i] - e0));
+  for (int m = 0; m < b; ++m) {
+    for (int i = 0; i < n; ++i) x[i] = p[(size_t)m * n + i];  // P^T e_m
+    te.apply_fn_vec(g.data(), x.data(), y.data());
+    for (int r = 0; r < b; ++r) {
+      double acc = 0.0;
+      for (int i = 0; i < n; ++i) acc += p[(size_t)r * n + i] * y[i];
+      f[r * b + m] = acc;
+    }
+  }
+}
+
 void sym_eig_small(int n, const double* a_in, double* w, double* v) {
   double a[16 * 16];
   for (int i = 0; i < n * n; ++i) a[i] = a_in[i];
@@ -175,5 +268,22 @@ extern "C" rdm_status rdm_tridiag_fa(int32_t kk, const double* alpha, const doub
       quad[b] = q;
     }
   }
+  return RDM_OK;
+}
+
+extern "C" rdm_status rdm_block_quadrature(int32_t n, int32_t b, const double* t, int32_t n_beta,
+                                           const double* betas, double e0, double* min_eig, double* f) {
+  if (n < 1 || b < 1 || b > n || !t || n_beta < 0 || (n_beta > 0 && (!betas || !f))) {
+    set_error("rdm_block_quadrature: bad arguments");
+    return RDM_E_INVALID;
+  }
+  DenseSymEig de;
+  de.solve(t, n);
+  if (!de.ok) {
+    set_error("rdm_block_quadrature: QR iteration did not converge");
+    return RDM_E_NONFINITE;
+  }
+  if (min_eig) *min_eig = de.min_eig();
+  for (int q = 0; q < n_beta; ++q) de.quad(b, betas[q], e0, f + (size_t)q * b * b);
   return RDM_OK;
 }

@@ -116,3 +116,40 @@ def test_solve_rejects_bad_arguments_without_touching_device():
         with pytest.raises(rdm.RdmError) as e:
             rdm.solve(h, betas, n_v, k, 1, library_alloc=True)
         assert e.value.status == -1
+
+
+def test_block_quadrature_matches_oracle():
+    # E_1^T exp(-beta (T - e0)) E_1 of the block variant (eqn:fT), host routine,
+    # on random symmetric matrices and on a real block tridiagonal from O4
+    from oracle import block, spin
+    rng = np.random.default_rng(0)
+    cases = []
+    for n, b in [(1, 1), (4, 4), (12, 2), (40, 4), (96, 8)]:
+        a = rng.normal(size=(n, n))
+        cases.append(((a + a.T) / 2, b))
+    inst = cfg_small_chain()
+    op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    v = np.zeros((inst.dim, inst.d_s))
+    for m in range(inst.d_s):
+        v[m * inst.d_b:(m + 1) * inst.d_b, m] = 1.0 / np.sqrt(inst.d_b)
+    cases.append((block.block_lanczos(op.apply, v, 12), inst.d_s))
+    for t, b in cases:
+        e0 = float(np.linalg.eigvalsh(t)[0])
+        f, mn = rdm.block_quadrature(t, b, [0.3, 1.7], e0)
+        assert abs(mn - e0) < 1e-12 * max(1.0, abs(e0))
+        for q, bt in enumerate([0.3, 1.7]):
+            want = block.block_quadrature(t, b, bt, e0)
+            assert np.abs(f[q] - want).max() < 1e-12 * np.abs(want).max(), (t.shape, b, bt)
+
+
+def test_block_method_validation():
+    h = rdm.Hamiltonian.from_instance(cfg_small_chain())
+    with pytest.raises(rdm.RdmError) as e:
+        rdm.workspace_size(h, 1, 4, 30, precision="fp64", method=2, hbm_budget=1 << 40)
+    assert e.value.status == -1
+    # the block method plans a few vector blocks, no Lanczos basis (an explicit
+    # budget keeps the planner off the device)
+    wb = rdm.workspace_size(h, 1, 4, 30, precision="fp64", method="block", hbm_budget=1 << 40)
+    wc = rdm.workspace_size(h, 1, 4, 30, precision="fp64", mode="stored", hbm_budget=1 << 40)
+    assert 0 < wb < wc
+

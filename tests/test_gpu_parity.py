@@ -252,6 +252,45 @@ def test_solve_mixed_matches_oracle(name):
     check_result(got, want, 1e-5, name)
 
 
+# --------------------------------------------------------------------------
+# the paper's block variant (Algorithm 1 + block Gauss quadrature) against O4
+# --------------------------------------------------------------------------
+BLOCK_CASES = ["chain_1+9", "random_2+6", "random_3+5", "lr_2+9", "xz_2+14"]
+_ORACLE_BLOCK = {}
+
+
+def oracle_block(name):
+    if name not in _ORACLE_BLOCK:
+        from oracle import block
+        _ORACLE_BLOCK[name] = block.solve(SOLVE_CASES[name]())["results"]
+    return _ORACLE_BLOCK[name]
+
+
+@pytest.mark.parametrize("name", BLOCK_CASES)
+def test_block_fp64_matches_oracle(name):
+    inst = SOLVE_CASES[name]()
+    got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    check_result(got, oracle_block(name), 1e-10, "block " + name)
+
+
+@pytest.mark.parametrize("name", BLOCK_CASES)
+def test_block_mixed_matches_oracle(name):
+    inst = SOLVE_CASES[name]()
+    got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", method="block")
+    check_result(got, oracle_block(name), 1e-5, "block mixed " + name)
+
+
+def test_block_and_per_column_agree_at_convergence():
+    # both estimators converge to the same exact-typicality value (O2) for
+    # the same bath vectors
+    inst = SOLVE_CASES["chain_1+9"]()
+    ex = exact.exact_typicality(inst)
+    a = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    b = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    check_result(a, ex, 1e-9, "block vs exact typicality")
+    check_result(b, ex, 1e-9, "per-column vs exact typicality")
+
+
 def test_solve_outputs_are_density_matrices():
     inst = SOLVE_CASES["lr_2+9"]()
     for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):
