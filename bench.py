@@ -43,10 +43,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-block", action="store_true", help="skip the block-Lanczos comparison")
-    ap.add_argument("--workload", default="lr", choices=["lr", "batch", "large", "serve"],
+    ap.add_argument("--workload", default="lr", choices=["lr", "batch", "large", "serve", "scan"],
                     help="lr: the metric's workload (default); batch: 64 heterogeneous sparse XXZ "
                          "instances in one batched solve; large: 3+23 spins (dim 2^26) two-pass; "
-                         "serve: Poisson arrivals of transverse-field requests")
+                         "serve: Poisson arrivals of transverse-field requests; scan: the paper's "
+                         "entropy / internal-energy scans")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests at the offered rate")
     ap.add_argument("--steady-requests", type=int, default=300,
                     help="serve: requests at 0.7x the measured capacity")
@@ -336,6 +337,49 @@ def bench_serve(args):
             "peak_device_bytes": stats["peak_bytes"]}
 
 
+def bench_scan(args):
+    """The paper's long-range experiments on 2 + 14 spins (isotropic XY,
+    J_ij = |i-j|^-alpha, z-field h), mixed precision, one batched solve per
+    scan: entropy over (field, temperature) at alpha = 1 with n_v = 400;
+    internal-energy deviation over alpha at h = 0 and over the coupling scale
+    eps at alpha = 1, n_v = 100; k = 60."""
+    import paper_2204_08147_amd  # noqa: F401
+    from paper_2204_08147_amd import scans
+    from workloads import xy_power_law
+    temps = np.array([0.1, 0.2, 0.3, 0.5, 0.7, 1.0, 1.5, 2.0])
+    betas = tuple(1.0 / temps)
+    fields = np.linspace(0.0, 2.2, 12)
+    alphas = [0.0, 0.1, 0.3, 0.5, 1.0, 2.0, float("inf")]
+    epss = np.linspace(0.0, 1.0, 11)
+    out = {"metric": "scan solves/s (paper's long-range experiments)", "unit": "solves/s",
+           "dtype": "f32 vectors + f64 reductions",
+           "config": {"workload": "isotropic XY 2+14 spins, J_ij=|i-j|^-alpha, z-field h; entropy grid "
+                                  "alpha=1, 12 fields in [0,2.2] x 8 temperatures, n_v=400; deviation over "
+                                  "alpha (h=0) and eps (alpha=1, h=0), n_v=100; k=60"}}
+    t0 = time.perf_counter()
+    grid = scans.entropy_grid(lambda h: xy_power_law(2, 14, 1.0, h, 6100, betas=betas, n_v=400, k=60),
+                              fields, precision="mixed")
+    t_grid = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dev_a = scans.deviation_scan(lambda a: xy_power_law(2, 14, a, 0.0, 6200, betas=betas, n_v=100, k=60),
+                                 alphas, precision="mixed")
+    t_a = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dev_e = scans.deviation_scan(lambda e: xy_power_law(2, 14, 1.0, 0.0, 6300, eps=e, betas=betas, n_v=100,
+                                                        k=60), epss, precision="mixed")
+    t_e = time.perf_counter() - t0
+    n = len(fields) + len(alphas) + len(epss)
+    out.update({"value": round(n / (t_grid + t_a + t_e), 3),
+                "entropy_grid_s": round(t_grid, 3), "alpha_scan_s": round(t_a, 3), "eps_scan_s": round(t_e, 3),
+                "temperatures": temps.tolist(), "fields": fields.round(3).tolist(),
+                "entropy": grid.round(4).tolist(),
+                "alphas": ["inf" if np.isinf(a) else a for a in alphas],
+                "deviation_vs_alpha": dev_a.round(5).tolist(),
+                "eps": epss.round(2).tolist(), "deviation_vs_eps": dev_e.round(5).tolist(),
+                "max_abs_deviation_at_eps0": float(np.abs(dev_e[0]).max())})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -349,7 +393,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload != "lr":
-        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve}[args.workload]
+        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve, "scan": bench_scan}[args.workload]
         out = fn(args)
         out.update({"n_gpus": 1, "data": "synthetic", "scaling": "weak"})
         print(json.dumps(out))
@@ -501,6 +545,10 @@ def main():
         "norm_kernel_ms": round(float(np.mean(no_m)), 4),
         "transform_pass0_ms": round(float(np.mean(x0_m)), 4),
         "gram_kernel_ms": round(float(np.mean(gr_m)), 4),
+        # recombination + Gram: one read of the k stored FP32 vectors per solve
+        # (all four temperatures in one pass)
+        "gram_gbs_algorithmic": round(inst0.k * inst0.dim * inst0.n_cols * 4 / (float(np.mean(gr_m)) * 1e-3) / 1e9,
+                                      1),
         "fp64": None if fp64 is None else {k2: round(v, 4) for k2, v in fp64.items()},
         "mixed_over_fp64": None if fp64 is None else round(value / fp64["solves_per_s"], 3),
         "block_method": block,

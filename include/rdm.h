@@ -139,6 +139,13 @@ rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm_coupling* 
                                   rdm_hamiltonian** out);
 void rdm_hamiltonian_destroy(rdm_hamiltonian* h);
 
+/* H_s, the system part of the split H_t = H_s (x) I + I (x) H_b + H_sb
+ * (Section "Spin systems"): the couplings and fields of system sites only,
+ * as a dense d_s x d_s matrix (out: host, row-major, d_s = 2^n_s; system
+ * state m has site s < n_s at bit n_s-1-s).  Used by observables such as the
+ * internal-energy deviation tr(H* rho*) - tr(H_s rho_s). */
+rdm_status rdm_system_hamiltonian(const rdm_hamiltonian* h, double* out);
+
 /* Table sizes of a built Hamiltonian: out[0]=N, [1]=n_s, [2]=n_b,
  * [3]=uniform-coefficient hops, [4]=parity-dependent hops, [5]=diagonal terms,
  * [6..8] the same three counts for H_b, [9] / [10] partner-tile groups the

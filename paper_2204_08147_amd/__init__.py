@@ -108,6 +108,13 @@ class Hamiltonian:
                 "bath_tile_groups", "direct_hops", "bath_direct_hops", "transform", "bath_transform"]
         return dict(zip(keys, list(out)))
 
+    def system_matrix(self) -> np.ndarray:
+        """H_s (d_s x d_s): the couplings and fields of the system sites."""
+        d = 1 << self.n_s
+        out = np.zeros((d, d))
+        _check(LIB.rdm_system_hamiltonian(self.handle, _dptr(out)), "rdm_system_hamiltonian")
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             LIB.rdm_hamiltonian_destroy(self.handle)

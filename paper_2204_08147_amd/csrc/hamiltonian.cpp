@@ -281,3 +281,33 @@ extern "C" rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* ou
 }
 
 extern "C" const char* rdm_last_error(void) { return last_error(); }
+
+extern "C" rdm_status rdm_system_hamiltonian(const rdm_hamiltonian* h, double* out) {
+  if (!h || !out) {
+    set_error("rdm_system_hamiltonian: NULL argument");
+    return RDM_E_INVALID;
+  }
+  // H_s on the 2^n_s system states: the couplings and fields of system sites
+  // only (site s < n_s is bit n_s-1-s of the system index)
+  const int ns = h->n_s, ds = 1 << ns;
+  for (int i = 0; i < ds * ds; ++i) out[i] = 0.0;
+  auto bit = [&](int site) { return 1u << (ns - 1 - site); };
+  for (const auto& c : h->couplings) {
+    if (c.i >= ns || c.j >= ns) continue;
+    const uint32_t f = bit(c.i) | bit(c.j);
+    for (uint32_t r = 0; r < (uint32_t)ds; ++r) {
+      const bool differ = (__builtin_popcount(r & f) & 1u) != 0;
+      out[r * ds + r] += differ ? -c.jz : c.jz;
+      // sx sx + sy sy: jx - jy when the two bits agree, jx + jy when they differ
+      out[r * ds + (r ^ f)] += differ ? c.jx + c.jy : c.jx - c.jy;
+    }
+  }
+  for (int s = 0; s < ns; ++s) {
+    const uint32_t b = bit(s);
+    for (uint32_t r = 0; r < (uint32_t)ds; ++r) {
+      out[r * ds + r] += (r & b) ? -h->hz[s] : h->hz[s];
+      out[r * ds + (r ^ b)] += h->hx[s];
+    }
+  }
+  return RDM_OK;
+}

@@ -153,3 +153,13 @@ def test_block_method_validation():
     wc = rdm.workspace_size(h, 1, 4, 30, precision="fp64", mode="stored", hbm_budget=1 << 40)
     assert 0 < wb < wc
 
+
+def test_system_hamiltonian_matches_oracle_split():
+    # H_s of the split H_t = H_s (x) I + I (x) H_b + H_sb (Section "Spin systems")
+    from oracle import spin
+    for args in [(1, 4, 11), (2, 5, 12), (3, 4, 13)]:
+        inst = random_dense_terms(*args)
+        h = rdm.Hamiltonian.from_instance(inst)
+        hs, _, _ = spin.split_dense(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+        assert np.abs(h.system_matrix() - hs).max() < 1e-14
+

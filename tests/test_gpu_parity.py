@@ -291,6 +291,41 @@ def test_block_and_per_column_agree_at_convergence():
     check_result(b, ex, 1e-9, "per-column vs exact typicality")
 
 
+# --------------------------------------------------------------------------
+# scans and observables (the paper's long-range experiments)
+# --------------------------------------------------------------------------
+def test_entropy_grid_matches_oracle():
+    from paper_2204_08147_amd import scans
+    from workloads import xy_power_law
+    make = lambda h: xy_power_law(1, 7, 1.0, h, 81, betas=(0.5, 2.0), n_v=6, k=30)  # noqa: E731
+    fields = [0.3, 1.4]
+    grid = scans.entropy_grid(make, fields, precision="fp64")
+    for a, f in enumerate(fields):
+        want = olz.solve(make(f))["results"]
+        for b in range(2):
+            assert abs(grid[a, b] - want[b]["entropy"]) < 1e-10
+
+
+def test_energy_deviation_zero_without_coupling_and_matches_oracle():
+    from oracle import spin
+    from paper_2204_08147_amd import scans
+    from workloads import xy_power_law
+    betas = (0.5, 2.0, 8.0)
+    make = lambda e: xy_power_law(2, 6, 1.0, 0.4, 82, eps=e, betas=betas, n_v=5, k=40)  # noqa: E731
+    dev = scans.deviation_scan(make, [0.0, 0.5], precision="fp64")
+    # eps = 0: H* = H_s exactly, so the deviation vanishes
+    assert np.abs(dev[0]).max() < 1e-10
+    inst = make(0.5)
+    want = olz.solve(inst)["results"]
+    hs, _, _ = spin.split_dense(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+    for b, beta in enumerate(betas):
+        w, v = np.linalg.eigh(hs)
+        p = np.exp(-beta * (w - w.min()))
+        rho_s = (v * (p / p.sum())) @ v.T
+        ref = np.trace(want[b]["h_star"] @ want[b]["rho"]) - np.trace(hs @ rho_s)
+        assert abs(dev[1, b] - ref) < 1e-9
+
+
 def test_solve_outputs_are_density_matrices():
     inst = SOLVE_CASES["lr_2+9"]()
     for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):

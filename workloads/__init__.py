@@ -186,6 +186,29 @@ def tfim_request(r: int, *, n_range=(14, 24), n_v: int = 8, k: int = 60) -> Inst
                     f"tfim_{n_s}+{n - n_s}", {"h": h})
 
 
+def xy_power_law(n_s: int, n_b: int, alpha: float, h: float, seed: int, *, J: float = 1.0,
+                 eps: float = 1.0, betas: Sequence[float] = (1.0,), n_v: int = 100,
+                 k: int = 60) -> Instance:
+    """The family of the paper's long-range experiments: isotropic XY chain
+    with J^x = J^y = J |i-j|^-alpha (alpha = inf: nearest neighbours only),
+    J^z = 0, z-field h (coefficient h/2 on every site); the system-bath pairs
+    are scaled by eps (H_s + H_b + eps H_sb)."""
+    n = n_s + n_b
+    cps = []
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = j - i
+            c = J * (1.0 if d == 1 else 0.0) if np.isinf(alpha) else J * float(d) ** (-alpha)
+            if c == 0.0:
+                continue
+            if (i < n_s) != (j < n_s):
+                c *= eps
+            cps.append((i, j, c, c, 0.0))
+    hz = np.full(n, h / 2.0)
+    return Instance(n_s, n_b, cps, _zeros(n), hz, np.asarray(betas, float), n_v, k, seed,
+                    f"xy_a{alpha}_h{h}_e{eps}_{n_s}+{n_b}", {"alpha": alpha, "h": h, "eps": eps})
+
+
 def poisson_arrivals(n: int, rate: float, seed: int = 5999) -> np.ndarray:
     """Arrival times (s) of a Poisson process of the given rate."""
     rng = np.random.default_rng(seed)
