@@ -265,6 +265,28 @@ rdm_status rdm_tridiag_fa(int32_t kk, const double* alpha, const double* beta, i
 rdm_status rdm_block_quadrature(int32_t n, int32_t b, const double* t, int32_t n_beta,
                                 const double* betas, double e0, double* min_eig, double* f);
 
+/* Low-temperature limit (Section "High and low temperature limits"):
+ * rho*(inf) = (1/r) sum_i tr_b |psi_i><psi_i| over the r ground states of H_t,
+ * and the ground energies E_t, E_b of H_t and H_b, so that
+ * H*(inf) = (E_t - E_b) I.  n_v (1..8) Lanczos runs of k steps on seeded
+ * full-space Rademacher vectors (vector c is the bath-vector rule of the hot
+ * path with n_b replaced by N); the columns whose lowest Ritz value reached
+ * the smallest one span the ground space (r = the eigenvalues of their Ritz
+ * vectors' Gram matrix above 1e-6 (FP64) / 1e-3 (mixed) of the largest;
+ * r <= 4).  Outputs (host, any may be NULL): rho d_s x d_s row-major,
+ * e_total, e_bath, entropy -tr rho ln rho, degeneracy r.  opt: precision,
+ * hbm_budget, tau and eager are used (NULL = FP64).  Blocking; the library
+ * allocates its workspace. */
+typedef struct {
+  double* rho;
+  double* e_total;
+  double* e_bath;
+  double* entropy;
+  int32_t* degeneracy;
+} rdm_ground_result;
+rdm_status rdm_ground_state(const rdm_hamiltonian* h, int32_t n_v, int32_t k, uint64_t seed,
+                            const rdm_options* opt, void* hip_stream, rdm_ground_result* out);
+
 /* ---- Serving: continuous batching over one device stream ---- */
 
 typedef struct rdm_server rdm_server;

@@ -27,4 +27,6 @@ closed_form  O5: the solvable XX chain (paper appendix "Solution to the spin
              and a two-spin closed form derived directly.
 variance     O6: exact per-entry variance of the Rademacher partial-trace
              estimator.
+ground       O8: the low-temperature limit (ground-space partial trace and
+             ground energies), dense and step by step.
 """

@@ -252,6 +252,21 @@ def lanczos(h: Hamiltonian, *, which: int, n_v: int, k: int, seed: int, stream=N
     return a, b, kc
 
 
+def ground_state(h: Hamiltonian, n_v: int, k: int, seed: int, *, stream=None, **opts) -> dict:
+    """Low-temperature limit: rho*(inf) over the ground space, E_t, E_b,
+    H*(inf) = (E_t - E_b) I, the T = 0 entropy and the ground-space dimension."""
+    o = make_options(**opts)
+    d = 1 << h.n_s
+    rho = np.zeros((d, d))
+    et, eb, ent = C.c_double(), C.c_double(), C.c_double()
+    r = C.c_int32()
+    res = _lib.GroundResult(_dptr(rho), C.pointer(et), C.pointer(eb), C.pointer(ent), C.pointer(r))
+    _check(LIB.rdm_ground_state(h.handle, n_v, k, seed, C.byref(o), _stream_handle(stream), C.byref(res)),
+           "rdm_ground_state")
+    return {"rho": rho, "e_total": et.value, "e_bath": eb.value, "entropy": ent.value,
+            "degeneracy": int(r.value), "h_star": (et.value - eb.value) * np.eye(d)}
+
+
 def block_quadrature(t, b: int, betas, e0: float):
     """Host routine: E_1^T exp(-beta (T - e0)) E_1 (b x b) for a symmetric T and
     each beta, and the smallest eigenvalue of T."""

@@ -38,6 +38,12 @@ class Result(C.Structure):
                 ("diag", C.POINTER(C.c_double))]
 
 
+class GroundResult(C.Structure):
+    _fields_ = [("rho", C.POINTER(C.c_double)), ("e_total", C.POINTER(C.c_double)),
+                ("e_bath", C.POINTER(C.c_double)), ("entropy", C.POINTER(C.c_double)),
+                ("degeneracy", C.POINTER(C.c_int32))]
+
+
 class BatchItem(C.Structure):
     _fields_ = [("h", C.c_void_p), ("beta", C.POINTER(C.c_double)), ("n_beta", C.c_int32),
                 ("n_v", C.c_int32), ("k", C.c_int32), ("seed", C.c_uint64), ("out", Result),
@@ -79,6 +85,8 @@ SIGNATURES = [
     ("rdm_block_quadrature", C.c_int32,
      [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double), C.c_double,
       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("rdm_ground_state", C.c_int32,
+     [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(Options), C.c_void_p, C.POINTER(GroundResult)]),
     ("rdm_server_create", C.c_int32, [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
     ("rdm_server_submit", C.c_int32,
      [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,

@@ -93,6 +93,8 @@ struct TridiagEig {
   void apply_fn(const double* g, double* y) const;
   // y = S diag(g) S^T x for any x (n).
   void apply_fn_vec(const double* g, const double* x, double* y) const;
+  // eigenvector i (column i of S), n entries
+  void eigvec(int i, double* y) const;
 };
 
 // Eigensystem of a dense symmetric matrix through Householder reduction to

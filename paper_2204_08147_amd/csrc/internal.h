@@ -138,6 +138,18 @@ struct BSeg {
   double tau;
 };
 
+// Partial trace over the bath of the ground-space projector: for each bath
+// index b the lane forms phi_i[m] = sum_j sum_c w[j][i][c] u_j[(m << nb) + b][c]
+// for the R orthonormalised Ritz vectors phi_i and accumulates
+// sum_i phi_i[m] phi_i[n] (FP64) into part[tile][DS*DS].
+struct GPSeg {
+  const void* Q;      // k stored Lanczos blocks of dim x cpad (panel layout)
+  const void* w;      // [k][R][cpad] weights, in T
+  double* part;       // [n_tiles][DS*DS]
+  uint64_t blk;       // dim * cpad
+  int32_t nbits, nb, cpad, k, R, rpl, n_tiles, pad;
+};
+
 // Work item of the apply / norm kernels, derived from blockIdx.x: segment s
 // owns workgroups [tile_base, tile_base + n_row_tiles * P/S), slab-major.
 struct Tile {
@@ -188,6 +200,8 @@ hipError_t launch_colsum(const double* part, int nrows, int width, double* out, 
 template <typename T>
 hipError_t launch_block_update(const BSeg* bs, int ds, int phase, int j, int n_rt, int n_cb, hipStream_t st);
 hipError_t launch_block_reduce(const BSeg* bs, int ds, int G, int phase, int j, hipStream_t st);
+template <typename T>
+hipError_t launch_ground_ptrace(const GPSeg* gp, int ds, int n_tiles, hipStream_t st);
 template <typename T>
 hipError_t launch_start_block(int ns_log, int nb, int C, uint64_t seed, int kind, T* out,
                               int nbits, int cpad, hipStream_t st);

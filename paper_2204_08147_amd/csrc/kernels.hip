@@ -1046,6 +1046,60 @@ __global__ __launch_bounds__(kBlock) void k_block_reduce(const BSeg* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// ground-space partial trace (low-temperature limit): one lane per bath index
+// b, the DS system states m in registers, one pass over the stored blocks
+// ---------------------------------------------------------------------------
+template <typename T, int DS>
+__global__ __launch_bounds__(kBlock) void k_ground_ptrace(const GPSeg* __restrict__ gpp) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  constexpr int RMAX = 4;
+  constexpr int NE = DS * DS;
+  __shared__ double lds[4 * NE];
+  const CONST_AS GPSeg& gp = *(const CONST_AS GPSeg*)gpp;
+  const uint32_t db = 1u << gp.nb;
+  const uint64_t dim = 1ull << gp.nbits;
+  const int P = gp.cpad / W;
+  const CONST_AS T* w = (const CONST_AS T*)gp.w;
+  double acc[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) acc[i] = 0.0;
+  for (int rr = 0; rr < gp.rpl; ++rr) {
+    const uint32_t b = ((uint32_t)blockIdx.x * gp.rpl + rr) * kBlock + threadIdx.x;
+    if (b >= db) break;
+    T phi[RMAX][DS];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+#pragma unroll
+      for (int m = 0; m < DS; ++m) phi[i][m] = T(0);
+    for (int j = 0; j < gp.k; ++j) {
+      const V* qj = (const V*)gp.Q + (uint64_t)j * (gp.blk / W);
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int m = 0; m < DS; ++m) {
+          const V v = ldg(qj + (uint64_t)p * dim, ((uint32_t)m << gp.nb) | b);
+#pragma unroll
+          for (int e = 0; e < W; ++e)
+#pragma unroll
+            for (int i = 0; i < RMAX; ++i)
+              if (i < gp.R) phi[i][m] = fma_s(w[((uint64_t)j * gp.R + i) * gp.cpad + p * W + e], v[e], phi[i][m]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < gp.R)
+#pragma unroll
+        for (int m = 0; m < DS; ++m)
+#pragma unroll
+          for (int n = 0; n < DS; ++n) acc[m * DS + n] += (double)phi[i][m] * (double)phi[i][n];
+  }
+  double tot;
+  block_sum<NE>(acc, lds, &tot);
+  if (threadIdx.x < NE) gp.part[(uint64_t)blockIdx.x * NE + threadIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
 // reductions of the per-tile partial sums: one workgroup per (segment,
 // column); lane i sums tiles i, i+256, ... and a fixed binary tree in LDS
 // combines the lanes, so the order never depends on scheduling.
@@ -1340,6 +1394,16 @@ hipError_t launch_block_reduce(const BSeg* bs, int ds, int G, int phase, int j, 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_ground_ptrace(const GPSeg* gp, int ds, int n_tiles, hipStream_t st) {
+  switch (ds) {
+    case 2: hipLaunchKernelGGL((k_ground_ptrace<T, 2>), dim3(n_tiles), dim3(kBlock), 0, st, gp); break;
+    case 4: hipLaunchKernelGGL((k_ground_ptrace<T, 4>), dim3(n_tiles), dim3(kBlock), 0, st, gp); break;
+    default: hipLaunchKernelGGL((k_ground_ptrace<T, 8>), dim3(n_tiles), dim3(kBlock), 0, st, gp); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st) {
   if (nseg <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_red_beta, dim3(nseg, cmax), dim3(kBlock), 0, st, segs);
@@ -1407,6 +1471,8 @@ template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t);
 template hipError_t launch_block_update<float>(const BSeg*, int, int, int, int, int, hipStream_t);
+template hipError_t launch_ground_ptrace<float>(const GPSeg*, int, int, hipStream_t);
+template hipError_t launch_ground_ptrace<double>(const GPSeg*, int, int, hipStream_t);
 template hipError_t launch_block_update<double>(const BSeg*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);

@@ -116,6 +116,17 @@ void TridiagEig::apply_fn_vec(const double* g, const double* x, double* y) const
   }
 }
 
+void TridiagEig::eigvec(int i0, double* y) const {
+  for (int i = 0; i < n; ++i) y[i] = i == i0 ? 1.0 : 0.0;
+  for (size_t t = rot_i.size(); t-- > 0;) {
+    const int i = rot_i[t];
+    const double c = rot_c[t], s = rot_s[t];
+    const double w0 = y[i], w1 = y[i + 1];
+    y[i] = c * w0 + s * w1;
+    y[i + 1] = -s * w0 + c * w1;
+  }
+}
+
 // Householder tridiagonalisation (Golub & Van Loan, symmetric Householder
 // reduction): for k = 0..n-3 the reflector H = I - tau v v^T on rows/columns
 // k+1.. maps column k below the diagonal onto a multiple of e_1; the trailing
