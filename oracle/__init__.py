@@ -29,4 +29,7 @@ variance     O6: exact per-entry variance of the Rademacher partial-trace
              estimator.
 ground       O8: the low-temperature limit (ground-space partial trace and
              ground energies), dense and step by step.
+high_temperature
+             O9: the estimator's high-temperature offset C (the beta -> 0
+             limit of the estimated H* minus H_s), from its definition.
 """
