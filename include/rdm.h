@@ -287,6 +287,29 @@ typedef struct {
 rdm_status rdm_ground_state(const rdm_hamiltonian* h, int32_t n_v, int32_t k, uint64_t seed,
                             const rdm_options* opt, void* hip_stream, rdm_ground_result* out);
 
+/* High-temperature offset of the estimator (Section "A note on high
+ * temperatures"; the appendix deriving the high-temperature limit).  As
+ * beta -> 0 the exact H*(beta) tends to H_s, while the estimate built from
+ * the bath vectors v_0 .. v_{n_v-1} of a solve with this seed tends to
+ * H_s + C,
+ *     C = (1/n_v) sum_j (I_s (x) <v_j|) H_sb (I_s (x) |v_j>).
+ * C has zero mean over the random vectors: its size indicates the sampling
+ * error of that solve, and subtracting it from the estimated H*(beta)
+ * removes the estimator's offset at high temperature.
+ *   c_out   host, d_s x d_s row-major (system state m has site s < n_s at
+ *           bit n_s-1-s): C.
+ *   sx_out  host, n_b doubles, or NULL: (1/n_v) sum_j <v_j| sx_c |v_j> for
+ *           bath site c = n_s .. N-1 (the only bath expectations C needs:
+ *           the sy ones vanish for real vectors, the sz ones because all
+ *           entries of a bath vector have the same magnitude).
+ * The device computes the bath sign correlations as exact integer sums on
+ * hip_stream (NULL: the null stream); the call allocates and frees a small
+ * device buffer and returns after the stream has finished it.
+ * Errors: RDM_E_INVALID for a NULL h or c_out or n_v outside 1..65535;
+ * RDM_E_DEVICE for a failed HIP call. */
+rdm_status rdm_high_temperature_term(const rdm_hamiltonian* h, int32_t n_v, uint64_t seed, void* hip_stream,
+                                     double* c_out, double* sx_out);
+
 /* ---- Serving: continuous batching over one device stream ---- */
 
 typedef struct rdm_server rdm_server;

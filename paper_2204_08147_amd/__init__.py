@@ -267,6 +267,19 @@ def ground_state(h: Hamiltonian, n_v: int, k: int, seed: int, *, stream=None, **
             "degeneracy": int(r.value), "h_star": (et.value - eb.value) * np.eye(d)}
 
 
+def high_temperature_term(h: Hamiltonian, n_v: int, seed: int, *, stream=None) -> dict:
+    """The estimator's high-temperature offset C (d_s x d_s) for the bath
+    vectors of a solve with this n_v and seed: the estimated H* tends to
+    H_s + C as beta -> 0, the exact one to H_s.  Also returns the averaged
+    bath expectations <v|sx_c|v> per bath site and the spectral norm of C."""
+    d = 1 << h.n_s
+    c = np.zeros((d, d))
+    sx = np.zeros(h.n_b)
+    _check(LIB.rdm_high_temperature_term(h.handle, n_v, seed, _stream_handle(stream), _dptr(c), _dptr(sx)),
+           "rdm_high_temperature_term")
+    return {"c": c, "sx": sx, "norm": float(np.abs(np.linalg.eigvalsh(c)).max())}
+
+
 def block_quadrature(t, b: int, betas, e0: float):
     """Host routine: E_1^T exp(-beta (T - e0)) E_1 (b x b) for a symmetric T and
     each beta, and the smallest eigenvalue of T."""

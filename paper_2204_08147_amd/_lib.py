@@ -87,6 +87,8 @@ SIGNATURES = [
       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("rdm_ground_state", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(Options), C.c_void_p, C.POINTER(GroundResult)]),
+    ("rdm_high_temperature_term", C.c_int32,
+     [C.c_void_p, C.c_int32, C.c_uint64, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("rdm_server_create", C.c_int32, [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
     ("rdm_server_submit", C.c_int32,
      [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,

@@ -206,4 +206,11 @@ template <typename T>
 hipError_t launch_start_block(int ns_log, int nb, int C, uint64_t seed, int kind, T* out,
                               int nbits, int cpad, hipStream_t st);
 
+// Bath-site sign correlations of the random bath vectors: for bath vectors
+// j < nv and bath bits p < nb, the integer sum over b of s_b s_(b xor 2^p)
+// (s_b = +-1 the signs of v_j), as per-block partials
+// part[(j * nblk + blk) * nb + p], nblk = bath_sx_blocks(nb).
+int bath_sx_blocks(int nb);
+hipError_t launch_bath_sx(uint64_t seed, int nb, int nv, long long* part, hipStream_t st);
+
 }  // namespace rdm

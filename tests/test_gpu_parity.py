@@ -525,3 +525,53 @@ def test_serving_alone_equals_in_mix():
         assert b["status"] == 0
         for key in ("rho", "h_star", "log_z", "entropy"):
             assert np.array_equal(a[key], b[key]), key
+
+
+# --- high-temperature offset (Section "A note on high temperatures") -------
+# n_b below 6 (one partial sign word), exactly 6, above 6 (partner words),
+# and the long-range workload at full size; n_v 1..16.
+HT_CASES = {
+    "dense_1+3": (lambda: random_dense_terms(1, 3, 5, density=1.0), 3),
+    "dense_2+5": (lambda: random_dense_terms(2, 5, 17), 1),
+    "dense_2+6": (lambda: random_dense_terms(2, 6, 29), 16),
+    "dense_1+9": (lambda: random_dense_terms(1, 9, 41), 5),
+    "lr_2+18": (lambda: cfg_long_range(1), 1),
+}
+
+
+@pytest.mark.parametrize("name", list(HT_CASES))
+def test_high_temperature_term_matches_oracle(name):
+    from oracle import high_temperature as ht
+    make, n_v = HT_CASES[name]
+    inst = make()
+    got = rdm.high_temperature_term(H(inst), n_v, inst.seed)
+    # <v|sx|v>: the library sums the integer sign correlations exactly; the
+    # oracle multiplies entries +-2^(-n_b/2), whose square rounds for odd n_b
+    assert np.allclose(got["sx"], ht.bath_sx(inst, n_v, inst.seed), rtol=1e-14, atol=1e-16)
+    want = ht.offset(inst, n_v, inst.seed)
+    scale = max(1.0, sum(abs(c[2]) for c in inst.couplings))
+    assert np.abs(got["c"] - want).max() < 1e-14 * scale
+    assert np.abs(got["c"] - got["c"].T).max() == 0.0
+
+
+def test_high_temperature_bath_sx_full_size():
+    # the largest workload's bath (23 sites): the sign correlations only
+    from oracle import high_temperature as ht
+    from workloads import cfg_large
+    inst = cfg_large()
+    got = rdm.high_temperature_term(H(inst), 1, 77)
+    assert np.allclose(got["sx"], ht.bath_sx(inst, 1, 77), rtol=1e-14, atol=1e-16)
+
+
+def test_high_temperature_correction_removes_the_offset():
+    # at small beta the estimate misses the exact H* by about C; subtracting
+    # C leaves an O(beta) remainder
+    inst = random_dense_terms(2, 7, 13, n_v=2, k=30)
+    h = H(inst)
+    c = rdm.high_temperature_term(h, inst.n_v, inst.seed)["c"]
+    for beta in (1e-3, 1e-2):
+        est = rdm.solve(h, [beta], inst.n_v, inst.k, inst.seed, precision="fp64")["h_star"][0]
+        ex = exact.exact_rdm(inst, beta)["h_star"]
+        raw, corr = np.abs(est - ex).max(), np.abs(est - c - ex).max()
+        assert raw > 0.5 * np.abs(c).max() > 1e-3
+        assert corr < 0.2 * raw, (beta, raw, corr)
