@@ -32,4 +32,6 @@ ground       O8: the low-temperature limit (ground-space partial trace and
 high_temperature
              O9: the estimator's high-temperature offset C (the beta -> 0
              limit of the estimated H* minus H_s), from its definition.
+product      O10: the product-state (rank-one) trace estimator of Z_t and
+             ln Z*, dense and step by step.
 """
