@@ -230,8 +230,10 @@ rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t precision,
                      const void* x, void* y, const rdm_options* opt, void* hip_stream);
 
 /* The start block of a solve: column c = j*d_s + m is |m> (x) |v_j> (which = 0,
- * 2^N rows, d_s*n_v columns) or v_j itself (which = 1, 2^n_b rows, n_v
- * columns), in the panel layout.  out: device.  Asynchronous. */
+ * 2^N rows, d_s*n_v columns), v_j itself (which = 1, 2^n_b rows, n_v
+ * columns), or the product vector |v_s^(j)> (x) |v_j> of rdm_product_trace
+ * (which = 2, 2^N rows, n_v columns), in the panel layout.  out: device.
+ * Asynchronous. */
 rdm_status rdm_start_block(const rdm_hamiltonian* h, int32_t which, int32_t precision, int32_t n_v,
                            uint64_t seed, void* out, void* hip_stream);
 
@@ -286,6 +288,38 @@ typedef struct {
 } rdm_ground_result;
 rdm_status rdm_ground_state(const rdm_hamiltonian* h, int32_t n_v, int32_t k, uint64_t seed,
                             const rdm_options* opt, void* hip_stream, rdm_ground_result* out);
+
+/* Outputs of rdm_product_trace, per inverse temperature (caller-owned host
+ * arrays; any may be NULL). */
+typedef struct {
+  double* log_z;    /* n_beta: ln Z* = ln Z_t - ln Z_b                        */
+  double* log_z_t;  /* n_beta: ln Z_t from the product samples                */
+  double* log_z_b;  /* n_beta: ln Z_b from the bath vectors                   */
+  double* samples;  /* n_beta x n_v: per-sample ln(2^N <x_j|exp(-beta H_t)|x_j>) */
+} rdm_product_result;
+
+/* Product-state (rank-one) estimator of Z_t (appendix "A consistent partial
+ * trace estimator").  Sample j is the unit product vector
+ * x_j = |v_s^(j)> (x) |v_j>, where v_j is bath vector j of rdm_solve with the
+ * same seed and v_s^(j) is the same sign rule over the n_s system bits with
+ * the seed XOR 0x9E3779B97F4A7C15.  2^N <x_j|exp(-beta H_t)|x_j> is unbiased
+ * for Z_t; its means over the bath factor (system factor) are the quadratic
+ * forms of tr_b exp(-beta H_t) (tr_s exp(-beta H_t)), so the trace estimate
+ * is consistent with the partial-trace estimates, and with the same bath
+ * vector it equals <v_s|M_j|v_s> for the partial-trace sample M_j of
+ * rdm_solve.  One Lanczos column per sample (k steps, the hot-path kernels),
+ * Gauss quadrature from each T (eqn:fT with block size one), Z_b from the
+ * bath vectors as in rdm_solve.  ln Z_t = ln mean_j(2^N e_1^T exp(-beta
+ * (T_j - E0)) e_1) - beta E0 with E0 the smallest Ritz value over the
+ * columns.  betas: host, n_beta values >= 0.  Options as for rdm_solve
+ * (precision, tau, hbm_budget, eager; the rest ignored).  Allocates its
+ * device workspace, runs on hip_stream and returns when done.
+ * Errors: RDM_E_INVALID for NULL arguments, n_v or k outside 1..4096 or a
+ * negative or non-finite beta; RDM_E_NOMEM beyond the budget; RDM_E_DEVICE;
+ * RDM_E_NONFINITE for a failed quadrature. */
+rdm_status rdm_product_trace(const rdm_hamiltonian* h, const double* betas, int32_t n_beta, int32_t n_v,
+                             int32_t k, uint64_t seed, const rdm_options* opt, void* hip_stream,
+                             rdm_product_result* out);
 
 /* High-temperature offset of the estimator (Section "A note on high
  * temperatures"; the appendix deriving the high-temperature limit).  As

@@ -267,6 +267,21 @@ def ground_state(h: Hamiltonian, n_v: int, k: int, seed: int, *, stream=None, **
             "degeneracy": int(r.value), "h_star": (et.value - eb.value) * np.eye(d)}
 
 
+def product_trace(h: Hamiltonian, betas, n_v: int, k: int, seed: int, *, stream=None, **opts) -> dict:
+    """Product-state estimator: ln Z*, ln Z_t, ln Z_b per beta and the
+    per-sample ln Z_t estimates ([n_beta, n_v]) from n_v columns
+    |v_s^(j)> (x) |v_j>."""
+    o = make_options(**opts)
+    bt = np.ascontiguousarray(np.atleast_1d(betas), dtype=np.float64)
+    nb = len(bt)
+    lz, lzt, lzb = np.zeros(nb), np.zeros(nb), np.zeros(nb)
+    smp = np.zeros((nb, n_v))
+    res = _lib.ProductResult(_dptr(lz), _dptr(lzt), _dptr(lzb), _dptr(smp))
+    _check(LIB.rdm_product_trace(h.handle, _dptr(bt), nb, n_v, k, seed, C.byref(o), _stream_handle(stream),
+                                 C.byref(res)), "rdm_product_trace")
+    return {"log_z": lz, "log_z_t": lzt, "log_z_b": lzb, "samples": smp}
+
+
 def high_temperature_term(h: Hamiltonian, n_v: int, seed: int, *, stream=None) -> dict:
     """The estimator's high-temperature offset C (d_s x d_s) for the bath
     vectors of a solve with this n_v and seed: the estimated H* tends to

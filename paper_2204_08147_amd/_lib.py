@@ -44,6 +44,11 @@ class GroundResult(C.Structure):
                 ("degeneracy", C.POINTER(C.c_int32))]
 
 
+class ProductResult(C.Structure):
+    _fields_ = [("log_z", C.POINTER(C.c_double)), ("log_z_t", C.POINTER(C.c_double)),
+                ("log_z_b", C.POINTER(C.c_double)), ("samples", C.POINTER(C.c_double))]
+
+
 class BatchItem(C.Structure):
     _fields_ = [("h", C.c_void_p), ("beta", C.POINTER(C.c_double)), ("n_beta", C.c_int32),
                 ("n_v", C.c_int32), ("k", C.c_int32), ("seed", C.c_uint64), ("out", Result),
@@ -87,6 +92,9 @@ SIGNATURES = [
       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("rdm_ground_state", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(Options), C.c_void_p, C.POINTER(GroundResult)]),
+    ("rdm_product_trace", C.c_int32,
+     [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(Options),
+      C.c_void_p, C.POINTER(ProductResult)]),
     ("rdm_high_temperature_term", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_uint64, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("rdm_server_create", C.c_int32, [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),

@@ -393,17 +393,16 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
 
 extern "C" rdm_status rdm_start_block(const rdm_hamiltonian* h, int32_t which, int32_t precision,
                                       int32_t n_v, uint64_t seed, void* out, void* hip_stream) {
-  if (!h || (which != 0 && which != 1) || (precision != RDM_FP64 && precision != RDM_MIXED) || n_v < 1 ||
-      !out) {
+  if (!h || which < 0 || which > 2 || (precision != RDM_FP64 && precision != RDM_MIXED) || n_v < 1 || !out) {
     set_error("rdm_start_block: bad arguments");
     return RDM_E_INVALID;
   }
   hipStream_t st = (hipStream_t)hip_stream;
-  const int nbits = which == 0 ? h->n : h->n_b;
+  const int nbits = which == 1 ? h->n_b : h->n;
   const int C = which == 0 ? (1 << h->n_s) * n_v : n_v;
   const int W = precision == RDM_FP64 ? 2 : 4;
   const int cpad = (C + W - 1) / W * W;
-  const int kind = which == 0 ? START_SYSBATH : START_BATH;
+  const int kind = which == 0 ? START_SYSBATH : which == 1 ? START_BATH : START_PRODUCT;
   if (precision == RDM_FP64)
     RDM_HIP(launch_start_block<double>(h->n_s, h->n_b, C, seed, kind, (double*)out, nbits, cpad, st));
   else

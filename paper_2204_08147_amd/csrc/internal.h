@@ -26,7 +26,7 @@ enum {
 };
 
 enum { MODE_LANCZOS = 0, MODE_REGEN = 1, MODE_PLAIN = 2 };
-enum { START_SYSBATH = 0, START_BATH = 1 };
+enum { START_SYSBATH = 0, START_BATH = 1, START_PRODUCT = 2 };
 
 constexpr int kTileBits = 8;       // the apply stages 2^8 = kBlock-row partner tiles in LDS
 constexpr int kXzTileBits = 12;    // transform apply: 4096-element tiles ...

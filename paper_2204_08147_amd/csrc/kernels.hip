@@ -47,7 +47,13 @@ template <typename T> __device__ __forceinline__ T amp_of(int nb);
 template <> __device__ __forceinline__ double amp_of<double>(int nb) { return sqrt(ldexp(1.0, -nb)); }
 template <> __device__ __forceinline__ float amp_of<float>(int nb) { return sqrtf(ldexpf(1.0f, -nb)); }
 
-// Start-block entry (row, column c): |m> (x) |v_j> with c = j*d_s + m, or v_c.
+// The system factor of product start vector j follows the bath-vector rule
+// with this seed offset, over the n_s system bits.
+constexpr uint64_t kSysSeedXor = 0x9E3779B97F4A7C15ull;
+
+// Start-block entry (row, column c): |m> (x) |v_j> with c = j*d_s + m
+// (START_SYSBATH), the product |v_s^(c)> (x) |v_c> (START_PRODUCT), or v_c.
+// amp = 2^(-nb/2).
 template <typename T>
 __device__ __forceinline__ T start_value(int kind, int ns_log, int nb, uint64_t seed, uint32_t row,
                                          int c, int C, T amp) {
@@ -58,6 +64,11 @@ __device__ __forceinline__ T start_value(int kind, int ns_log, int nb, uint64_t 
     j = (uint32_t)(c >> ns_log);
     if ((int)(row >> nb) != m) return T(0);
     b = row & ((1u << nb) - 1u);
+  } else if (kind == START_PRODUCT) {
+    const uint32_t m = row >> nb;
+    b = row & ((1u << nb) - 1u);
+    const T a = amp * amp_of<T>(ns_log);
+    return (bath_bit(seed, (uint32_t)c, b) ^ bath_bit(seed ^ kSysSeedXor, (uint32_t)c, m)) ? -a : a;
   } else {
     j = (uint32_t)c;
     b = row;
@@ -78,6 +89,20 @@ __device__ __forceinline__ V ldg(const V* base, uint32_t row) {
 template <typename V>
 __device__ __forceinline__ void stg(V* base, uint32_t row, V v) {
   *(GLOBAL_AS V*)((GLOBAL_AS char*)base + (uint32_t)(row << 4)) = v;
+}
+// Streaming forms for the transform passes: each pass reads every vector
+// once and its working set is several times the last-level cache, so loads
+// carry the nontemporal hint; stores take it where it measured faster (passes
+// 1 and 2; pass 0 keeps ordinary stores).
+template <typename V>
+__device__ __forceinline__ V ldg_nt(const V* base, uint32_t row) {
+  return __builtin_nontemporal_load((const GLOBAL_AS V*)((const GLOBAL_AS char*)base + (uint32_t)(row << 4)));
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void stg_stream(V* base, uint32_t row, V v) {
+  GLOBAL_AS V* p = (GLOBAL_AS V*)((GLOBAL_AS char*)base + (uint32_t)(row << 4));
+  if (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 template <typename T>
 __device__ __forceinline__ T ldg_s(const T* base, uint32_t row) {
@@ -654,8 +679,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
       V up[kXzRegs];
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q) {
-        v[q] = ldg((const V*)rb, t.row0 + xz_tau(0, l, q));
-        up[q] = ldg(uprev, t.row0 + xz_tau(0, l, q));
+        v[q] = ldg_nt((const V*)rb, t.row0 + xz_tau(0, l, q));
+        up[q] = ldg_nt(uprev, t.row0 + xz_tau(0, l, q));
       }
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q)
@@ -664,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     }
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) {
-      stg(ucur, t.row0 + xz_tau(0, l, q), v[q]);
+      stg_stream<PHASE != 0>(ucur, t.row0 + xz_tau(0, l, q), v[q]);
 #pragma unroll
       for (int e = 0; e < W; ++e) dsum[e] += (double)v[q][e] * (double)v[q][e];
     }
@@ -702,12 +727,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     xz_bfly(v, 0xF);                 // bits 4..7
     xz_rearrange(v, lds, 2, 0);
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) stg(rb, t.row0 + xz_tau(0, l, q), v[q]);
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<PHASE != 0>(rb, t.row0 + xz_tau(0, l, q), v[q]);
   } else if (PHASE == 0 || PHASE == 2) {
     // contiguous tile: row = row0 + tau; arrangement 0 loads and stores coalesced
     const V* src = PHASE == 0 ? ub : (const V*)rb;
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg(src, t.row0 + xz_tau(0, l, q));
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(src, t.row0 + xz_tau(0, l, q));
     // pass C: the epilogue's operands are loaded while the tile is transformed
     V u[PHASE == 2 ? kXzRegs : 1];
     T d[PHASE == 2 ? kXzRegs : 1];
@@ -715,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
       const T* dg = (const T*)sg.diag;
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q) {
-        u[q] = ldg(ub, t.row0 + xz_tau(0, l, q));
+        u[q] = ldg_nt(ub, t.row0 + xz_tau(0, l, q));
         d[q] = ldg_s(dg, t.row0 + xz_tau(0, l, q));
       }
     }
@@ -727,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     xz_rearrange(v, lds, 2, 0);
     if (PHASE == 0) {
 #pragma unroll
-      for (int q = 0; q < kXzRegs; ++q) stg(rb, t.row0 + xz_tau(0, l, q), v[q]);
+      for (int q = 0; q < kXzRegs; ++q) stg_stream<PHASE != 0>(rb, t.row0 + xz_tau(0, l, q), v[q]);
       return;
     }
     const int cp = sg.cpad;
@@ -748,11 +773,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
       const uint32_t row = t.row0 + xz_tau(0, l, q);
       V r = sc * (d[q] * u[q] + v[q]);
       if (uprev) {
-        const V up = ldg(uprev, row);
+        const V up = ldg_nt(uprev, row);
 #pragma unroll
         for (int e = 0; e < W; ++e) r[e] = fma_s(-bp[e], up[e], r[e]);
       }
-      stg(rb, row, r);
+      stg_stream<PHASE != 0>(rb, row, r);
       if (dots) {
 #pragma unroll
         for (int e = 0; e < W; ++e) dq[e] += (double)u[q][e] * (double)r[e];
@@ -774,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
       return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
     };
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg((const V*)rb, row_of(xz_tau(0, l, q)));
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt((const V*)rb, row_of(xz_tau(0, l, q)));
     // tau bits lrb..11 are the row's high bits: 8..11 in arrangement 0, the
     // part of 4..7 at or above lrb in arrangement 2
     const int m2 = 0xF & ~((1 << (lrb > 4 ? lrb - 4 : 0)) - 1);
@@ -787,7 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     xz_rearrange(v, lds, 2, 0);
     xz_bfly(v, 0xF);
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) stg(rb, row_of(xz_tau(0, l, q)), v[q]);
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<PHASE != 0>(rb, row_of(xz_tau(0, l, q)), v[q]);
   }
 }
 

@@ -575,3 +575,66 @@ def test_high_temperature_correction_removes_the_offset():
         raw, corr = np.abs(est - ex).max(), np.abs(est - c - ex).max()
         assert raw > 0.5 * np.abs(c).max() > 1e-3
         assert corr < 0.2 * raw, (beta, raw, corr)
+
+
+# --- product-state estimator (appendix "A consistent partial trace estimator")
+@pytest.mark.parametrize("n_s,n_b,n_v,seed", [(1, 3, 3, 7), (2, 9, 5, 8), (3, 12, 2, 9)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_product_start_block(n_s, n_b, n_v, seed, prec):
+    from oracle import product
+    inst = Instance(n_s, n_b, [], np.zeros(n_s + n_b), np.zeros(n_s + n_b), np.array([1.0]), n_v, 1, seed)
+    h = H(inst)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    w = rdm.panel_width(prec)
+    cp = (n_v + w - 1) // w * w
+    out = torch.full((inst.dim * cp,), float("nan"), dtype=dt, device="cuda")
+    rdm.start_block(h, out, which=2, precision=prec, n_v=n_v, seed=seed)
+    torch.cuda.synchronize()
+    got = rdm.from_panels(out, inst.dim, n_v, prec).cpu().numpy()
+    want = np.stack([product.product_vector(seed, j, n_s, n_b) for j in range(n_v)], axis=1)
+    if prec == "fp64":
+        assert np.array_equal(got, want)          # same products of the same two roundings
+    else:
+        # FP32 product of two FP32 square roots: within one rounding of the FP64 value
+        assert np.array_equal(np.sign(got), np.sign(want))
+        assert np.abs(got / want - 1).max() < 2.5e-7
+
+
+PRODUCT_CASES = {
+    "dense_2+5": (lambda: random_dense_terms(2, 5, 17), [0.3, 1.0, 2.5], 3, 40),
+    "dense_1+8": (lambda: random_dense_terms(1, 8, 4), [0.5, 2.0], 16, 50),
+    "xz_2+14": (lambda: long_range_xx_zz(2, 14, 1.0, 2002), [0.5, 1.0, 2.0, 4.0], 2, 60),
+    "xxz_3+10": (lambda: long_range_xxz(3, 10, 55), [1.0], 1, 60),
+}
+
+
+@pytest.mark.parametrize("name", list(PRODUCT_CASES))
+def test_product_trace_matches_oracle(name):
+    from oracle import product
+    make, betas, n_v, k = PRODUCT_CASES[name]
+    inst = make()
+    want = product.lanczos_estimate(inst, betas, n_v, k, 31)
+    got = rdm.product_trace(H(inst), betas, n_v, k, 31, precision="fp64")
+    for key in ("log_z", "log_z_t", "log_z_b"):
+        assert np.abs(got[key] - want[key]).max() < 1e-10 * max(1.0, np.abs(want[key]).max()), key
+    assert np.abs(got["samples"] - want["log_z_t_samples"]).max() < 1e-10 * max(1.0, np.abs(want["log_z_t"]).max())
+    mixed = rdm.product_trace(H(inst), betas, n_v, k, 31, precision="mixed")
+    assert np.abs(mixed["log_z"] - want["log_z"]).max() < 1e-5 * max(1.0, np.abs(want["log_z"]).max())
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 2e-5)])
+def test_product_sample_is_the_partial_trace_sample_full_size(prec, tol):
+    # with the same bath vector, <v_s (x) v_0| A |v_s (x) v_0> = v_s^T M_0 v_s, so
+    # ln Z_t(product, n_v = 1) = ln Z_t(partial trace, n_v = 1) + ln(d_s v_s^T rho* v_s)
+    # on the metric's 2 + 18 instance (any size: both converge at k = 60)
+    from oracle import product
+    inst = cfg_long_range(0)
+    h = H(inst)
+    seed = 12345
+    pr = rdm.product_trace(h, inst.betas, 1, inst.k, seed, precision=prec)
+    sv = rdm.solve(h, inst.betas, 1, inst.k, seed, precision=prec)
+    vs = product.system_vector(seed, 0, inst.n_s)
+    for i in range(len(inst.betas)):
+        want = sv["log_z_t"][i] + np.log(inst.d_s * vs @ sv["rho"][i] @ vs)
+        assert abs(pr["log_z_t"][i] - want) < tol * abs(want), (i, pr["log_z_t"][i], want)
+        assert abs(pr["log_z_b"][i] - sv["log_z_b"][i]) < tol * abs(sv["log_z_b"][i])
