@@ -120,11 +120,11 @@ typedef struct {
                        [3] columns of H_b that hit breakdown, [4] 1 if the
                        two-pass plan was used, [5] device bytes of the plan,
                        [6] mu_min/mu_max of the last beta, [7] mean apply
-                       time per Lanczos step (ms; hop-table apply kernel,
-                       or transform passes 1-2), [8] mean norm kernel time
+                       time per Lanczos step (ms; hop-table apply kernel
+                       and transform pass 2), [8] mean norm kernel time
                        (ms; hop-table operators), [9] mean Gram kernel time
-                       (ms), [10] mean transform pass 0 time (ms; norm step
-                       and first transform) -- [7..10] only when
+                       (ms), [10] mean transform pass 1 time (ms; norm step
+                       and high-bit transform) -- [7..10] only when
                        rdm_options.profile = 1 (event timing), else 0 --
                        [11..15] zero; then per beta {ln Z_t, ln Z_b}.        */
 } rdm_result;

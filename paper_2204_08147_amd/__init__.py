@@ -144,7 +144,7 @@ class _ResultBuffers:
                 "entropy": self.entropy, "e0": d[0], "e0b": d[1],
                 "breakdown_total": int(d[2]), "breakdown_bath": int(d[3]),
                 "two_pass": bool(d[4]), "device_bytes": int(d[5]), "mu_ratio": d[6],
-                "t_apply_ms": d[7], "t_norm_ms": d[8], "t_gram_ms": d[9], "t_xz0_ms": d[10],
+                "t_apply_ms": d[7], "t_norm_ms": d[8], "t_gram_ms": d[9], "t_xz1_ms": d[10],
                 "log_z_t": d[DIAG_FIXED::2][:nb].copy(), "log_z_b": d[DIAG_FIXED + 1::2][:nb].copy()}
 
 

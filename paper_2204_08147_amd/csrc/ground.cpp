@@ -132,13 +132,15 @@ rdm_status ground_run(const GroundPlan& gp, const rdm_hamiltonian* h, uint64_t s
   }
   // columns whose lowest Ritz value reached the ground energy
   const double e_tol = (gp.prec == RDM_FP64 ? 1e-9 : 1e-4) * std::max(1.0, scale);
+  // Ritz vector weights (times L^-1/2 when the basis is kept as W_lo u)
+  const double bscale = op_t->xz ? kXzBasisScale : 1.0;
   std::vector<double> y((size_t)gp.k * cp, 0.0);
   std::vector<std::vector<double>> yc(n_v);
   for (int c = 0; c < n_v; ++c) {
     if (et[c].theta[i0[c]] > et_min + e_tol) continue;
     yc[c].resize(et[c].n);
     et[c].eigvec(i0[c], yc[c].data());
-    for (int j = 0; j < et[c].n; ++j) y[(size_t)j * cp + c] = yc[c][j] * tsc[(size_t)j * cp + c];
+    for (int j = 0; j < et[c].n; ++j) y[(size_t)j * cp + c] = bscale * yc[c][j] * tsc[(size_t)j * cp + c];
   }
   // Gram of the Ritz vectors (hot-path Gram kernel, one group of dsg columns)
   std::vector<T> yt(y.size());

@@ -182,10 +182,20 @@ template <typename T>
 hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 template <typename T>
 hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
-// pass 0, 1 or 2 of the transform apply over the segments with xz = 1 (pass 0
-// also does the norm step outside MODE_PLAIN)
+// pass 0, 1 or 2 of the plain transform apply Y = H X (MODE_PLAIN segments
+// with xz = 1)
 template <typename T>
 hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st);
+// Lanczos step over the segments with xz = 1, basis kept in the low-bit
+// Hadamard basis: pass 0 = start block (once per run), 1 = norm step + high
+// transform, 2 = low transforms + recurrence.  Pass 1 runs on the
+// MODE_REGEN segments if regen, else on the others.  boff: first transform
+// tile.
+template <typename T>
+hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff,
+                             hipStream_t st);
+// Recombination weights of a segment whose basis is kept as W_lo u: L^-1/2
+constexpr double kXzBasisScale = 1.0 / (1 << (kXzTileBits / 2));
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st);

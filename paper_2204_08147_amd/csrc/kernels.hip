@@ -92,8 +92,9 @@ __device__ __forceinline__ void stg(V* base, uint32_t row, V v) {
 }
 // Streaming forms for the transform passes: each pass reads every vector
 // once and its working set is several times the last-level cache, so loads
-// carry the nontemporal hint; stores take it where it measured faster (passes
-// 1 and 2; pass 0 keeps ordinary stores).
+// carry the nontemporal hint.  Stores of the block R take it too; the basis
+// vector written in the norm step (read again within the step) and the
+// plain apply's first pass keep ordinary stores, which measured faster.
 template <typename V>
 __device__ __forceinline__ V ldg_nt(const V* base, uint32_t row) {
   return __builtin_nontemporal_load((const GLOBAL_AS V*)((const GLOBAL_AS char*)base + (uint32_t)(row << 4)));
@@ -618,9 +619,8 @@ __device__ __forceinline__ void xz_rearrange(V (&v)[kXzRegs], V* lds, int from, 
   __syncthreads();
 }
 
-__device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg) {
+__device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg, int b) {
   const CONST_AS Seg* cs = (const CONST_AS Seg*)segs;
-  const int b = (int)blockIdx.x;
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -633,107 +633,37 @@ __device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg) {
   return Tile{lo, (uint32_t)rt << kXzTileBits, sl, rt};
 }
 
-// Pass A (phase 0), B (phase 1) or C (phase 2) of the transform apply.
+template <typename V>
+__device__ __forceinline__ void xz_low_transform(V (&v)[kXzRegs], V* lds) {
+  xz_bfly(v, 0xF);                 // bits 8..11
+  xz_rearrange(v, lds, 0, 1);
+  xz_bfly(v, 0xF);                 // bits 0..3
+  xz_rearrange(v, lds, 1, 2);
+  xz_bfly(v, 0xF);                 // bits 4..7
+  xz_rearrange(v, lds, 2, 0);
+}
+
+// Plain transform apply Y = H X (MODE_PLAIN segments), H = D_Z + W D_X W:
+// phase 0: R = W_lo X (contiguous tiles); phase 1: R = W_hi D_X W_hi R
+// (strided tiles); phase 2: R = D_Z X + W_lo R (contiguous tiles).
 template <typename T, int PHASE>
 __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ segs, int nseg) {
   using V = typename PanelT<T>::V;
-  constexpr int W = PanelT<T>::W;
   __shared__ V lds[1 << kXzTileBits];
-  __shared__ double red[4 * W];
-  const Tile t = xz_tile_of(segs, nseg);
+  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
-  const bool plain = sg.mode == MODE_PLAIN;
-  int j = 1;
-  if (!plain) {
-    j = sg.stepc[0];
-    if (j > sg.k) return;
-  }
-  const uint32_t dim = 1u << sg.nbits;
-  const uint64_t pstride = (uint64_t)dim;
-  const V* ub = (plain ? (const V*)sg.Q : (const V*)slot_ptr<T>(sg, j)) + (uint64_t)t.panel0 * pstride;
+  const uint64_t pstride = (uint64_t)1 << sg.nbits;
+  const V* ub = (const V*)sg.Q + (uint64_t)t.panel0 * pstride;
   V* rb = (V*)sg.R + (uint64_t)t.panel0 * pstride;
   const uint32_t l = threadIdx.x;
   V v[kXzRegs];
 
-  if (PHASE == 0 && !plain) {
-    // u_j from r and u_{j-1} (norm step), kept in registers for the transform
-    const int cp = sg.cpad;
-    const CONST_AS double* st = (const CONST_AS double*)sg.st;
-    V* ucur = (V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
-    const V* uprev = j > 1 ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride : nullptr;
-    V acur;
-#pragma unroll
-    for (int e = 0; e < W; ++e) acur[e] = (T)st[ST_ACUR * cp + t.panel0 * W + e];
-    const T amp = amp_of<T>(sg.nb);
-    double dsum[W];
-#pragma unroll
-    for (int e = 0; e < W; ++e) dsum[e] = 0.0;
-    if (j == 1) {
-#pragma unroll
-      for (int q = 0; q < kXzRegs; ++q)
-#pragma unroll
-        for (int e = 0; e < W; ++e)
-          v[q][e] = start_value<T>(sg.start_kind, sg.ns_log, sg.nb, sg.seed, t.row0 + xz_tau(0, l, q),
-                                   t.panel0 * W + e, sg.C, amp);
-    } else {
-      V up[kXzRegs];
-#pragma unroll
-      for (int q = 0; q < kXzRegs; ++q) {
-        v[q] = ldg_nt((const V*)rb, t.row0 + xz_tau(0, l, q));
-        up[q] = ldg_nt(uprev, t.row0 + xz_tau(0, l, q));
-      }
-#pragma unroll
-      for (int q = 0; q < kXzRegs; ++q)
-#pragma unroll
-        for (int e = 0; e < W; ++e) v[q][e] = fma_s(-acur[e], up[q][e], v[q][e]);
-    }
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) {
-      stg_stream<PHASE != 0>(ucur, t.row0 + xz_tau(0, l, q), v[q]);
-#pragma unroll
-      for (int e = 0; e < W; ++e) dsum[e] += (double)v[q][e] * (double)v[q][e];
-    }
-    if (sg.mode == MODE_REGEN) {
-      const CONST_AS T* yt = (const CONST_AS T*)sg.ytab;
-      for (int b = 0; b < sg.n_beta; ++b) {
-        V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + (uint64_t)t.panel0 * pstride;
-        V y;
-#pragma unroll
-        for (int e = 0; e < W; ++e) y[e] = yt[((uint64_t)b * sg.k + (j - 1)) * cp + t.panel0 * W + e];
-#pragma unroll
-        for (int q = 0; q < kXzRegs; ++q) {
-          const uint32_t row = t.row0 + xz_tau(0, l, q);
-          V old;
-          if (j == 1) {
-#pragma unroll
-            for (int e = 0; e < W; ++e) old[e] = T(0);
-          } else {
-            old = ldg((const V*)pb, row);
-          }
-          V nw;
-#pragma unroll
-          for (int e = 0; e < W; ++e) nw[e] = fma_s(y[e], v[q][e], old[e]);
-          stg(pb, row, nw);
-        }
-      }
-    }
-    double tot;
-    block_sum<W>(dsum, red, &tot);
-    if (threadIdx.x < W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
-    xz_bfly(v, 0xF);                 // bits 8..11
-    xz_rearrange(v, lds, 0, 1);
-    xz_bfly(v, 0xF);                 // bits 0..3
-    xz_rearrange(v, lds, 1, 2);
-    xz_bfly(v, 0xF);                 // bits 4..7
-    xz_rearrange(v, lds, 2, 0);
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) stg_stream<PHASE != 0>(rb, t.row0 + xz_tau(0, l, q), v[q]);
-  } else if (PHASE == 0 || PHASE == 2) {
+  if (PHASE == 0 || PHASE == 2) {
     // contiguous tile: row = row0 + tau; arrangement 0 loads and stores coalesced
     const V* src = PHASE == 0 ? ub : (const V*)rb;
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(src, t.row0 + xz_tau(0, l, q));
-    // pass C: the epilogue's operands are loaded while the tile is transformed
+    // phase 2: the diagonal term's operands are loaded while the tile is transformed
     V u[PHASE == 2 ? kXzRegs : 1];
     T d[PHASE == 2 ? kXzRegs : 1];
     if (PHASE == 2) {
@@ -744,49 +674,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
         d[q] = ldg_s(dg, t.row0 + xz_tau(0, l, q));
       }
     }
-    xz_bfly(v, 0xF);                 // bits 8..11
-    xz_rearrange(v, lds, 0, 1);
-    xz_bfly(v, 0xF);                 // bits 0..3
-    xz_rearrange(v, lds, 1, 2);
-    xz_bfly(v, 0xF);                 // bits 4..7
-    xz_rearrange(v, lds, 2, 0);
-    if (PHASE == 0) {
+    xz_low_transform(v, lds);
 #pragma unroll
-      for (int q = 0; q < kXzRegs; ++q) stg_stream<PHASE != 0>(rb, t.row0 + xz_tau(0, l, q), v[q]);
-      return;
-    }
-    const int cp = sg.cpad;
-    const bool dots = sg.mode == MODE_LANCZOS;
-    const CONST_AS double* st = (const CONST_AS double*)sg.st;
-    const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride
-                                       : nullptr;
-    const V sc = scur_of<T, 1>(st, cp, t.panel0, 0, plain);
-    V bp;
-#pragma unroll
-    for (int e = 0; e < W; ++e) bp[e] = T(0);
-    if (uprev) bp = bps_of<T, 1>(st, cp, t.panel0, 0);
-    double dq[W];
-#pragma unroll
-    for (int e = 0; e < W; ++e) dq[e] = 0.0;
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) {
-      const uint32_t row = t.row0 + xz_tau(0, l, q);
-      V r = sc * (d[q] * u[q] + v[q]);
-      if (uprev) {
-        const V up = ldg_nt(uprev, row);
-#pragma unroll
-        for (int e = 0; e < W; ++e) r[e] = fma_s(-bp[e], up[e], r[e]);
-      }
-      stg_stream<PHASE != 0>(rb, row, r);
-      if (dots) {
-#pragma unroll
-        for (int e = 0; e < W; ++e) dq[e] += (double)u[q][e] * (double)r[e];
-      }
-    }
-    if (!dots) return;
-    double tot;
-    block_sum<W>(dq, red, &tot);
-    if (threadIdx.x < W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
+    for (int q = 0; q < kXzRegs; ++q)
+      stg_stream<PHASE != 0>(rb, t.row0 + xz_tau(0, l, q), PHASE == 0 ? v[q] : d[q] * u[q] + v[q]);
   } else {
     // strided tile: tau = hi * Lr + lr  ->  row = hi * 4096 + rt * Lr + lr,
     // hb = N - 12 high bits (4 <= hb <= 8), Lr = 2^(12 - hb) >= 16
@@ -812,8 +703,203 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     xz_rearrange(v, lds, 2, 0);
     xz_bfly(v, 0xF);
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) stg_stream<PHASE != 0>(rb, row_of(xz_tau(0, l, q)), v[q]);
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(rb, row_of(xz_tau(0, l, q)), v[q]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos step of the transform apply with the basis kept as u~ = W_lo u
+// (W_lo: Hadamard transform over the 12 low row bits, W_lo W_lo = L I,
+// L = 4096).  With W = W_hi W_lo and H = D_Z + W D_X W (D_X holding 2^-N):
+//   W_lo (H u) = W_lo (D_Z u) + L W_hi D_X W_hi u~,
+// so a step is one strided pass (high-bit transform, norm step fused) and one
+// contiguous pass (low-bit transforms, recurrence): 8 vector streams instead
+// of 10.  W_lo acts on bath bits only, so Gram matrices and bath partial
+// traces of the basis are those of u times L; the recombination weights
+// carry L^-1/2.
+//   PASS 0 (once per run, contiguous tiles): R = W_lo x_1
+//   PASS 1 (strided tiles): u~_j = R - (alpha s)_{j-1} u~_{j-1} -> slot j,
+//     partial |u~_j|^2 / L, psi~_b += y_{b,j} u~_j (regeneration pass);
+//     R = W_hi D_X W_hi u~_j
+//   PASS 2 (contiguous tiles): w = s L R - (beta s)_{j-1} u~_{j-1};
+//     u = W_lo u~_j / L; R = s W_lo (D_Z u) + w  (= W_lo r_j);
+//     partial <u_j, r_j> = s sum d u^2 + <u~_j, w> / L
+// boff offsets blockIdx.x in the segments' transform tile numbering.
+// ---------------------------------------------------------------------------
+template <typename T, int PASS, bool REGEN>
+__global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ segs, int nseg, int boff) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  __shared__ V lds[1 << kXzTileBits];
+  __shared__ double red[4 * W];
+  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x + boff);
+  const CONST_AS CSeg& sg = cseg(segs, t.seg);
+  // pass 1 comes in two variants (the regeneration pass needs more
+  // registers); each leaves the other mode's tiles alone
+  if (PASS == 1 && (sg.mode == MODE_REGEN) != REGEN) return;
+  const int j = PASS == 0 ? 1 : sg.stepc[0];
+  if (j > sg.k) return;
+  const int cp = sg.cpad;
+  const uint64_t pstride = (uint64_t)1 << sg.nbits;
+  const uint32_t l = threadIdx.x;
+  const CONST_AS double* st = (const CONST_AS double*)sg.st;
+  V* rb = (V*)sg.R + (uint64_t)t.panel0 * pstride;
+  const V* uprev = j > 1 ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel0 * pstride : nullptr;
+  const T inv_l = T(1) / T(1 << kXzTileBits);
+  V v[kXzRegs];
+
+  if (PASS == 0) {
+    const T amp = amp_of<T>(sg.nb);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q)
+#pragma unroll
+      for (int e = 0; e < W; ++e)
+        v[q][e] = start_value<T>(sg.start_kind, sg.ns_log, sg.nb, sg.seed, t.row0 + xz_tau(0, l, q),
+                                 t.panel0 * W + e, sg.C, amp);
+    xz_low_transform(v, lds);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(rb, t.row0 + xz_tau(0, l, q), v[q]);
+    return;
+  }
+
+  if (PASS == 1) {
+    // strided tile: tau = hi * Lr + lr  ->  row = hi * 4096 + rt * Lr + lr,
+    // hb = N - 12 high bits (4 <= hb <= 8), Lr = 2^(12 - hb) >= 16
+    const int hb = sg.nbits - kXzTileBits;
+    const int lrb = kXzTileBits - hb;
+    const uint32_t lrm = (1u << lrb) - 1u;
+    const uint32_t base = (uint32_t)t.rtile << lrb;
+    auto row_of = [&](uint32_t tau) -> uint32_t {
+      return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
+    };
+    V* ucur = (V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
+    V acur;
+#pragma unroll
+    for (int e = 0; e < W; ++e) acur[e] = (T)st[ST_ACUR * cp + t.panel0 * W + e];
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt((const V*)rb, row_of(xz_tau(0, l, q)));
+    if (uprev) {
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q) {
+        const V up = ldg_nt(uprev, row_of(xz_tau(0, l, q)));
+#pragma unroll
+        for (int e = 0; e < W; ++e) v[q][e] = fma_s(-acur[e], up[e], v[q][e]);
+      }
+    }
+    double dsum[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) dsum[e] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      stg(ucur, row_of(xz_tau(0, l, q)), v[q]);
+#pragma unroll
+      for (int e = 0; e < W; ++e) dsum[e] += (double)v[q][e] * (double)v[q][e];
+    }
+    if (REGEN) {
+      const CONST_AS T* yt = (const CONST_AS T*)sg.ytab;
+      for (int b = 0; b < sg.n_beta; ++b) {
+        V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + (uint64_t)t.panel0 * pstride;
+        V y;
+#pragma unroll
+        for (int e = 0; e < W; ++e) y[e] = yt[((uint64_t)b * sg.k + (j - 1)) * cp + t.panel0 * W + e];
+#pragma unroll
+        for (int q = 0; q < kXzRegs; ++q) {
+          const uint32_t row = row_of(xz_tau(0, l, q));
+          V old;
+          if (j == 1) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) old[e] = T(0);
+          } else {
+            old = ldg((const V*)pb, row);
+          }
+          V nw;
+#pragma unroll
+          for (int e = 0; e < W; ++e) nw[e] = fma_s(y[e], v[q][e], old[e]);
+          stg(pb, row, nw);
+        }
+      }
+    }
+    double tot;
+    block_sum<W>(dsum, red, &tot);
+    if (threadIdx.x < W)
+      sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot * (double)inv_l;
+    // tau bits lrb..11 are the row's high bits: 8..11 in arrangement 0, the
+    // part of 4..7 at or above lrb in arrangement 2
+    const T* dx = (const T*)sg.dx;
+    const int m2 = 0xF & ~((1 << (lrb > 4 ? lrb - 4 : 0)) - 1);
+    xz_bfly(v, 0xF);
+    xz_rearrange(v, lds, 0, 2);
+    xz_bfly(v, m2);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dx, row_of(xz_tau(2, l, q))) * v[q];
+    xz_bfly(v, m2);
+    xz_rearrange(v, lds, 2, 0);
+    xz_bfly(v, 0xF);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(rb, row_of(xz_tau(0, l, q)), v[q]);
+    return;
+  }
+
+  // PASS 2: contiguous tile, row = row0 + tau
+  const V* ub = (const V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
+  const T* dg = (const T*)sg.diag;
+  V w[kXzRegs];
+  T d[kXzRegs];
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) {
+    const uint32_t row = t.row0 + xz_tau(0, l, q);
+    v[q] = ldg_nt(ub, row);
+    w[q] = ldg_nt((const V*)rb, row);
+    d[q] = ldg_s(dg, row);
+  }
+  const V sc = scur_of<T, 1>(st, cp, t.panel0, 0, false);
+  const V scl = sc * T(1 << kXzTileBits);
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) w[q] = scl * w[q];
+  if (uprev) {
+    const V bp = bps_of<T, 1>(st, cp, t.panel0, 0);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const V up = ldg_nt(uprev, t.row0 + xz_tau(0, l, q));
+#pragma unroll
+      for (int e = 0; e < W; ++e) w[q][e] = fma_s(-bp[e], up[e], w[q][e]);
+    }
+  }
+  const bool dots = sg.mode == MODE_LANCZOS;
+  double d1[W], d2[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) d1[e] = d2[e] = 0.0;
+  if (dots) {
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q)
+#pragma unroll
+      for (int e = 0; e < W; ++e) d1[e] += (double)v[q][e] * (double)w[q][e];
+  }
+  xz_low_transform(v, lds);        // L u
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) {
+    const V u = v[q] * inv_l;
+    v[q] = d[q] * u;               // D_Z u
+    if (dots) {
+#pragma unroll
+      for (int e = 0; e < W; ++e) d2[e] += (double)u[e] * (double)v[q][e];
+    }
+  }
+  xz_low_transform(v, lds);        // W_lo D_Z u
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) {
+    V r;
+#pragma unroll
+    for (int e = 0; e < W; ++e) r[e] = fma_s(sc[e], v[q][e], w[q][e]);
+    stg_stream<true>(rb, t.row0 + xz_tau(0, l, q), r);
+  }
+  if (!dots) return;
+  double dq[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) dq[e] = (double)sc[e] * d2[e] + d1[e] * (double)inv_l;
+  double tot;
+  block_sum<W>(dq, red, &tot);
+  if (threadIdx.x < W) sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -1400,6 +1486,17 @@ hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipSt
 }
 
 template <typename T>
+hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 g(ntiles), b(kBlock);
+  if (pass == 0) hipLaunchKernelGGL((k_xz_lanczos<T, 0, false>), g, b, 0, st, segs, nseg, boff);
+  else if (pass == 1 && regen) hipLaunchKernelGGL((k_xz_lanczos<T, 1, true>), g, b, 0, st, segs, nseg, boff);
+  else if (pass == 1) hipLaunchKernelGGL((k_xz_lanczos<T, 1, false>), g, b, 0, st, segs, nseg, boff);
+  else hipLaunchKernelGGL((k_xz_lanczos<T, 2, false>), g, b, 0, st, segs, nseg, boff);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_block_update(const BSeg* bs, int ds, int phase, int j, int n_rt, int n_cb, hipStream_t st) {
   const dim3 grid(n_rt * n_cb), blk(kBlock);
   switch (ds) {
@@ -1500,6 +1597,8 @@ template hipError_t launch_ground_ptrace<float>(const GPSeg*, int, int, hipStrea
 template hipError_t launch_ground_ptrace<double>(const GPSeg*, int, int, hipStream_t);
 template hipError_t launch_block_update<double>(const BSeg*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t);
+template hipError_t launch_xz_lanczos<float>(int, bool, const Seg*, int, int, int, hipStream_t);
+template hipError_t launch_xz_lanczos<double>(int, bool, const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);

@@ -204,9 +204,11 @@ void rdm_server::run() {
     if (s == RDM_OK && hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg),
                                       hipMemcpyHostToDevice, stream) != hipSuccess)
       s = RDM_E_DEVICE;
-    for (auto& ir : init_ranges)
-      if (s == RDM_OK && launch_init_state(dsegs + ir.first, 1, cmax, ir.second, stream) != hipSuccess)
-        s = RDM_E_DEVICE;
+    for (auto& ir : init_ranges) {
+      const Seg& sg = segs[ir.first];
+      if (s == RDM_OK)
+        s = init_run(prec, dsegs + ir.first, 1, cmax, ir.second, sg.xz ? sg.x_tiles * sg.P : 0, sg.x_base, stream);
+    }
     if (s == RDM_OK) s = launch_step(prec, dsegs, (int)segs.size(), ntiles, slab, cmax, stream, nullptr);
     // the host tables must stay valid until the copies above completed
     if (s == RDM_OK && hipStreamSynchronize(stream) != hipSuccess) s = RDM_E_DEVICE;

@@ -343,8 +343,8 @@ void bind_apply(Seg& s, const OpDevice* op) {
 }
 
 Launch assign_tiles(std::vector<Seg>& segs) {
-  // the norm and apply launches cover the hop-table segments, the three
-  // transform passes the others (pass 0 doing their norm step).  Segments of
+  // the norm and apply launches cover the hop-table segments, the transform
+  // passes the others (pass 1 doing their norm step).  Segments of
   // the other kind get no workgroups (their base is the running count, which
   // the kernels' binary search never resolves to them).
   Launch L;
@@ -354,9 +354,20 @@ Launch assign_tiles(std::vector<Seg>& segs) {
     sg.ap_base = L.apply;
     if (!sg.xz) L.apply += sg.n_row_tiles * (sg.P / sg.S);
     sg.x_base = L.xz;
-    if (sg.xz) L.xz += sg.x_tiles * sg.P;
+    if (sg.xz) {
+      L.xz += sg.x_tiles * sg.P;
+      (sg.mode == MODE_REGEN ? L.xz_regen : L.xz_lanczos) = true;
+    }
   }
   return L;
+}
+
+rdm_status init_run(int prec, const Seg* dsegs, int nseg, int cmax, int phase, int xz_tiles, int xz_boff,
+                    hipStream_t st) {
+  RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
+  RDM_HIP(prec == RDM_FP64 ? launch_xz_lanczos<double>(0, false, dsegs, nseg, xz_tiles, xz_boff, st)
+                           : launch_xz_lanczos<float>(0, false, dsegs, nseg, xz_tiles, xz_boff, st));
+  return RDM_OK;
 }
 
 rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, hipStream_t st,
@@ -365,16 +376,19 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
   if (tm) RDM_HIP(tm->norm.mark(st));
   RDM_HIP(d ? launch_norm<double>(dsegs, nseg, L.norm, slab, st) : launch_norm<float>(dsegs, nseg, L.norm, slab, st));
   if (tm) RDM_HIP(tm->norm.mark(st));
-  if (tm) RDM_HIP(tm->xz0.mark(st));
-  RDM_HIP(d ? launch_xz_pass<double>(0, dsegs, nseg, L.xz, st) : launch_xz_pass<float>(0, dsegs, nseg, L.xz, st));
-  if (tm) RDM_HIP(tm->xz0.mark(st));
+  if (tm) RDM_HIP(tm->xz1.mark(st));
+  for (int regen = 0; regen < 2; ++regen) {
+    if (!(regen ? L.xz_regen : L.xz_lanczos)) continue;
+    RDM_HIP(d ? launch_xz_lanczos<double>(1, regen, dsegs, nseg, L.xz, 0, st)
+              : launch_xz_lanczos<float>(1, regen, dsegs, nseg, L.xz, 0, st));
+  }
+  if (tm) RDM_HIP(tm->xz1.mark(st));
   RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(d ? launch_apply<double>(dsegs, nseg, L.apply, slab, st)
             : launch_apply<float>(dsegs, nseg, L.apply, slab, st));
-  for (int pass = 1; pass <= 2; ++pass)
-    RDM_HIP(d ? launch_xz_pass<double>(pass, dsegs, nseg, L.xz, st)
-              : launch_xz_pass<float>(pass, dsegs, nseg, L.xz, st));
+  RDM_HIP(d ? launch_xz_lanczos<double>(2, false, dsegs, nseg, L.xz, 0, st)
+            : launch_xz_lanczos<float>(2, false, dsegs, nseg, L.xz, 0, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(launch_red_alpha(dsegs, nseg, cmax, st));
   return RDM_OK;
@@ -426,6 +440,8 @@ rdm_status host_phase_t(InstRun& r, hipStream_t st) {
   for (int c = 0; c < p.tot.C; ++c) r.n_break_t += ht.kc[c] < p.tot.k;
   for (int c = 0; c < p.bath.C; ++c) r.n_break_b += hb.kc[c] < p.bath.k;
   // weights y'_{b,j,c} = y_b[j] s_j / s_1: psi = |x| Q y and q_j = s_j u_j, |x| = 1/s_1
+  // (times L^-1/2 when the basis is kept as W_lo u)
+  const double bscale = r.op_t->xz ? kXzBasisScale : 1.0;
   std::vector<T> yt((size_t)p.n_beta * p.k * p.tot.cpad, T(0));
   parallel_for(p.tot.C, [&](int c) {
     const TridiagEig& e = et[c];
@@ -435,7 +451,7 @@ rdm_status host_phase_t(InstRun& r, hipStream_t st) {
       for (int q = 0; q < e.n; ++q) g[q] = std::exp(-0.5 * r.betas[b] * (e.theta[q] - e0));
       e.apply_fn(g.data(), y.data());
       for (int j = 0; j < e.n; ++j)
-        yt[((size_t)b * p.k + j) * p.tot.cpad + c] = (T)(y[j] * ht.s[(size_t)j * p.tot.cpad + c] / s1);
+        yt[((size_t)b * p.k + j) * p.tot.cpad + c] = (T)(bscale * y[j] * ht.s[(size_t)j * p.tot.cpad + c] / s1);
     }
   });
   // bath: Gauss quadrature e_1^T exp(-b (T_b - E0b)) e_1 scaled by |v|^2 = 1/s_1^2
@@ -662,7 +678,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
       for (auto& e : ev) RDM_HIP(hipEventCreate(&e));
       rdm_status s = RDM_OK;
       RDM_HIP(hipMemcpyAsync(dsegs, tabs[0].data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
-      RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
+      if ((s = init_run(prec, dsegs, nseg, cmax, phase, nt[0].xz, 0, st)) != RDM_OK) return s;
       s = launch_step(prec, dsegs, nseg, nt[0], cands[0], cmax, st, tm);
       ++j;
       for (size_t c = 0; c < cands.size() && s == RDM_OK; ++c) {
@@ -694,7 +710,10 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
   set_slab(hsegs, slab);
   const Launch ntiles = assign_tiles(hsegs);
   RDM_HIP(hipMemcpyAsync(dsegs, hsegs.data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, st));
-  if (j == 1) RDM_HIP(launch_init_state(dsegs, nseg, cmax, phase, st));
+  if (j == 1) {
+    rdm_status s = init_run(prec, dsegs, nseg, cmax, phase, ntiles.xz, 0, st);
+    if (s != RDM_OK) return s;
+  }
   if (graph && !tm && kmax - j + 1 >= 2) {
     rdm_status s = graph_steps(prec, dsegs, nseg, ntiles, slab, cmax, kmax - j + 1, st);
     if (s != RDM_OK) return s;
@@ -726,7 +745,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     if (s != RDM_OK) return s;
   }
   StepTimers tm;
-  tm.apply.on = tm.norm.on = tm.xz0.on = profile;
+  tm.apply.on = tm.norm.on = tm.xz1.on = profile;
   // pass 1: every total and bath segment in the same launches
   std::vector<Seg> segs;
   for (auto& r : runs) {
@@ -751,7 +770,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     for (auto& r : runs) {
       r.t_apply_ms = tm.apply.avg_ms();
       r.t_norm_ms = tm.norm.avg_ms();
-      r.t_xz0_ms = tm.xz0.avg_ms();
+      r.t_xz1_ms = tm.xz1.avg_ms();
       r.t_gram_ms = tg.avg_ms();
     }
   return RDM_OK;
@@ -830,7 +849,7 @@ rdm_status finalize(const InstRun& r, rdm_result* out) {
     d[7] = r.t_apply_ms;
     d[8] = r.t_norm_ms;
     d[9] = r.t_gram_ms;
-    d[10] = r.t_xz0_ms;
+    d[10] = r.t_xz1_ms;
     for (int t = 11; t < kDiagFixed; ++t) d[t] = 0.0;
   }
   return RDM_OK;

@@ -61,10 +61,10 @@ struct Timers {
     return n ? tot / n : 0.0;
   }
 };
-// apply: hop-table apply and transform passes 1-2; norm: the norm kernel;
-// xz0: transform pass 0 (norm step + first transform)
+// apply: hop-table apply and transform pass 2; norm: the norm kernel;
+// xz1: transform pass 1 (norm step + high-bit transform)
 struct StepTimers {
-  Timers apply, norm, xz0;
+  Timers apply, norm, xz1;
 };
 
 struct InstRun {
@@ -78,7 +78,7 @@ struct InstRun {
   double e0 = 0, e0b = 0;
   int n_break_t = 0, n_break_b = 0;
   std::vector<double> mb, gsum;
-  double t_apply_ms = 0, t_norm_ms = 0, t_gram_ms = 0, t_xz0_ms = 0;
+  double t_apply_ms = 0, t_norm_ms = 0, t_gram_ms = 0, t_xz1_ms = 0;
 };
 
 void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
@@ -100,6 +100,7 @@ void bind_apply(Seg& s, const OpDevice* op);
 // workgroups of the norm launch and of the two kinds of apply launch
 struct Launch {
   int norm = 0, apply = 0, xz = 0;
+  bool xz_lanczos = false, xz_regen = false;  // transform segments in each mode
 };
 // sets every segment's tile_base / ap_base / x_base
 Launch assign_tiles(std::vector<Seg>& segs);
@@ -108,6 +109,11 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
 // Runs every step of a phase.  tune: choose the panels per lane by timing the
 // first steps (cached per shape); otherwise the segments' own value is used.
 // graph: the steps after tuning run as one captured hipGraph (not with tm).
+// State initialisation of a run (phase 0) or regeneration pass (phase 1):
+// per-column state, and the start block of the transform segments in the
+// low-bit Hadamard basis (xz_tiles tiles from tile xz_boff).
+rdm_status init_run(int prec, const Seg* dsegs, int nseg, int cmax, int phase, int xz_tiles, int xz_boff,
+                    hipStream_t st);
 rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
                      StepTimers* tm, bool tune, bool graph);
 // Panels per lane for a launch over these segments: the cached measurement
