@@ -127,15 +127,16 @@ def operator_work(nbits, cols, nnz, transform, s, k):
     2*nnz flops per element.
     Transform (D_Z + W D_X W, basis kept in the low-bit Hadamard basis):
     pass 1 reads R and u~_(j-1), writes u~_j and R and reads D_X; pass 2
-    reads u~_j, R, u~_(j-1) and D_Z and writes R: (6 + 2p) vectors + 2
-    diagonals per panel; 2*nbits + 8 flops per element."""
+    reads u~_j, R, u~_(j-1) and D_Z and writes R: (6 + 2p) vectors + the two
+    diagonals (once: every panel reads the same ones); 2*nbits + 8 flops per
+    element."""
     dim = 1 << nbits
     w = 16 // s
     cp = (cols + w - 1) // w * w
     vec = dim * cp * s
     p = (k - 1) / k
     if transform:
-        return vec * (6 + 2 * p) + 2 * (cp // w) * dim * s, (2.0 * nbits + 8) * dim * cp
+        return vec * (6 + 2 * p) + 2 * dim * s, (2.0 * nbits + 8) * dim * cp
     return vec * (3 + 3 * p) + dim * s, 2.0 * nnz * dim * cols
 
 
@@ -497,21 +498,9 @@ def main():
     value = n_solves / wall_m
     ms_per_step = 1e3 * wall_m / args.steps
 
-    # measured stream-copy ceiling: 2 GiB -> 2 GiB device copies, best of
-    # three timed batches of five
-    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    copy_gbs = 0.0
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        copy_gbs = max(copy_gbs, 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
-    del src, dst
+    # measured streaming reference points (library probe: nontemporal loads and
+    # stores, one 4 KiB chunk per workgroup and array, 2 GiB arrays, best of 10)
+    probe = {p: rdm.stream_probe(p, 1 << 31, 10) for p in ("read", "copy", "r3w1", "r2w2")}
     torch.cuda.empty_cache()
 
     # roofline of the dominant kernel: the apply launch (H_t and H_b segments)
@@ -520,6 +509,7 @@ def main():
     bytes_alg, flops = step_work([inst0], 4)
     t_step = float(np.mean(ap_m) + np.mean(no_m) + np.mean(x0_m)) * 1e-3
     achieved_gbs = bytes_alg / t_step / 1e9
+    mix_gbs = 2.0 / (1.0 / probe["r2w2"] + 1.0 / probe["r3w1"])
     traffic = read_traffic("lanczos_step_lr_xxzz_2+18_mixed_counters.txt")
     roof = roofline(bytes_alg, flops, t_step, traffic)
 
@@ -553,7 +543,10 @@ def main():
         "mixed_over_fp64": None if fp64 is None else round(value / fp64["solves_per_s"], 3),
         "block_method": block,
         "roofline": roof,
-        "copy_ceiling": {"gbs": round(copy_gbs, 1), "step_frac_of_copy": round(achieved_gbs / copy_gbs, 4)},
+        # a transform step is half two-read-two-write (pass 1), half
+        # three-read-one-write (pass 2): the probe's matching mix
+        "stream_probe": {**{k: round(v, 1) for k, v in probe.items()},
+                         "step_mix_gbs": round(mix_gbs, 1), "step_frac_of_mix": round(achieved_gbs / mix_gbs, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -344,6 +344,18 @@ rdm_status rdm_product_trace(const rdm_hamiltonian* h, const double* betas, int3
 rdm_status rdm_high_temperature_term(const rdm_hamiltonian* h, int32_t n_v, uint64_t seed, void* hip_stream,
                                      double* c_out, double* sx_out);
 
+/* Device memory bandwidth probe (a measurement utility, not part of the
+ * method): the reference points for the streaming kernels.  pattern 0 reads
+ * one array, 1 copies one array into another, 2 reads three arrays and
+ * writes a fourth, 3 reads two and writes two; every array holds `bytes`
+ * (a positive multiple of 4096), each workgroup moves one 4 KiB chunk per
+ * array with nontemporal loads and stores, as the transform passes do.
+ * gbs (host): bytes moved per second / 1e9, best of reps timed launches
+ * after one warm-up.  Allocates and frees its arrays; runs on hip_stream and
+ * returns when done.  Errors: RDM_E_INVALID (pattern, reps < 1, bytes),
+ * RDM_E_NOMEM, RDM_E_DEVICE. */
+rdm_status rdm_stream_probe(int32_t pattern, uint64_t bytes, int32_t reps, void* hip_stream, double* gbs);
+
 /* ---- Serving: continuous batching over one device stream ---- */
 
 typedef struct rdm_server rdm_server;

@@ -282,6 +282,18 @@ def product_trace(h: Hamiltonian, betas, n_v: int, k: int, seed: int, *, stream=
     return {"log_z": lz, "log_z_t": lzt, "log_z_b": lzb, "samples": smp}
 
 
+STREAM_PATTERNS = {"read": 0, "copy": 1, "r3w1": 2, "r2w2": 3}
+
+
+def stream_probe(pattern: str, nbytes: int = 2 << 30, reps: int = 10, *, stream=None) -> float:
+    """Device bandwidth (GB/s of bytes moved) of a nontemporal streaming
+    kernel: 'read', 'copy', 'r3w1' (three reads, one write) or 'r2w2'."""
+    g = C.c_double(0.0)
+    _check(LIB.rdm_stream_probe(STREAM_PATTERNS[pattern], nbytes, reps, _stream_handle(stream), C.byref(g)),
+           "rdm_stream_probe")
+    return g.value
+
+
 def high_temperature_term(h: Hamiltonian, n_v: int, seed: int, *, stream=None) -> dict:
     """The estimator's high-temperature offset C (d_s x d_s) for the bath
     vectors of a solve with this n_v and seed: the estimated H* tends to

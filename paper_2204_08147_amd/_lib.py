@@ -95,6 +95,7 @@ SIGNATURES = [
     ("rdm_product_trace", C.c_int32,
      [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(Options),
       C.c_void_p, C.POINTER(ProductResult)]),
+    ("rdm_stream_probe", C.c_int32, [C.c_int32, C.c_uint64, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     ("rdm_high_temperature_term", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_uint64, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("rdm_server_create", C.c_int32, [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),

@@ -90,11 +90,13 @@ template <typename V>
 __device__ __forceinline__ void stg(V* base, uint32_t row, V v) {
   *(GLOBAL_AS V*)((GLOBAL_AS char*)base + (uint32_t)(row << 4)) = v;
 }
-// Streaming forms for the transform passes: each pass reads every vector
-// once and its working set is several times the last-level cache, so loads
-// carry the nontemporal hint.  Stores of the block R take it too; the basis
-// vector written in the norm step (read again within the step) and the
-// plain apply's first pass keep ordinary stores, which measured faster.
+// Streaming forms: a transform pass reads every vector once and its working
+// set is several times the last-level cache, so loads carry the nontemporal
+// hint.  Stores of the block R take it too; the basis vector written in the
+// norm step (read again within the step) and the plain apply's first pass
+// keep ordinary stores, which measured faster.  The hop-table kernels use
+// the same forms for their pure streams (r and u_{j-1}), not for the partner
+// tiles that neighbouring workgroups share.
 template <typename V>
 __device__ __forceinline__ V ldg_nt(const V* base, uint32_t row) {
   return __builtin_nontemporal_load((const GLOBAL_AS V*)((const GLOBAL_AS char*)base + (uint32_t)(row << 4)));
@@ -268,8 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_norm(const Seg* __restrict__ segs, i
       V r[S], up[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        r[s] = ldg(rv + s * pstride, row);
-        up[s] = ldg(uprev + s * pstride, row);
+        r[s] = ldg_nt(rv + s * pstride, row);
+        up[s] = ldg_nt(uprev + s * pstride, row);
       }
 #pragma unroll
       for (int s = 0; s < S; ++s)
@@ -540,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
     V up[S];
     if (uprev) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) up[s] = ldg(uprev + s * pstride, row);
+      for (int s = 0; s < S; ++s) up[s] = ldg_nt(uprev + s * pstride, row);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -550,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
 #pragma unroll
         for (int e = 0; e < W; ++e) r[e] = fma_s(-bp[e], up[s][e], r[e]);
       }
-      stg(out + s * pstride, row, r);
+      stg_stream<true>(out + s * pstride, row, r);
       if (dots) {
 #pragma unroll
         for (int e = 0; e < W; ++e) dq[s * W + e] = (double)xc[s][e] * (double)r[e];
@@ -568,15 +570,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
 // (XX couplings and x-fields, no YY): in the Hadamard basis such a term is
 // diagonal, so H = D_Z + W D_X W with W the unnormalised Walsh-Hadamard
 // transform on all N bits and D_X (with the 2^-N of W^2 folded in) the X-term
-// energies.  The product runs as three streaming passes over the panel, each
-// workgroup transforming a 4096-row tile in registers and LDS:
-//   A: t = W_lo u            (bits 0..11, contiguous tiles)
-//   B: t = W_hi D_X W_hi t   (bits 12..N-1, tiles of 2^(24-N)-row runs)
-//   C: r = s_j (D_Z u + W_lo t) - beta s u_{j-1}, partial <u_j, r>
-// t lives in the output block R (each workgroup rewrites only its own rows).
-// In a Lanczos step pass A also does the norm kernel's work for its tile: it
-// forms u_j = r - (alpha s) u_{j-1} (or the start block), stores it, adds the
-// partial |u_j|^2 (and psi in the regeneration pass), then transforms it.
+// energies.  Each workgroup transforms a 4096-row tile in registers and LDS,
+// over the low 12 row bits (W_lo, contiguous tiles) or the high N - 12 bits
+// (W_hi, tiles of 2^(24-N)-row runs at every high-bit value); W = W_hi W_lo.
+// The plain product Y = H X takes three such passes (k_apply_xz); a Lanczos
+// step keeps its basis in the low-bit Hadamard basis and takes two
+// (k_xz_lanczos).  Intermediate results live in the output block R, which
+// each workgroup rewrites only at its own rows.
 //
 // A tile is 4096 elements indexed by a 12-bit coordinate tau; lane l holds 16
 // of them in registers q.  Three arrangements: 0: tau = q*256 + l (q = bits
