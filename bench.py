@@ -393,12 +393,6 @@ def main():
     from workloads import LR_FIELDS, cfg_long_range
 
     torch.cuda.set_device(0)
-    if args.workload != "lr":
-        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve, "scan": bench_scan}[args.workload]
-        out = fn(args)
-        out.update({"n_gpus": 1, "data": "synthetic", "scaling": "weak"})
-        print(json.dumps(out))
-        return
     if args.copy_calibration:
         # a plain copy of known size: reads 1 GiB, writes 1 GiB
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -406,6 +400,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload != "lr":
+        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve, "scan": bench_scan}[args.workload]
+        out = fn(args)
+        out.update({"n_gpus": 1, "data": "synthetic", "scaling": "weak"})
+        print(json.dumps(out))
+        return
     insts = [cfg_long_range(i, n_b=args.n_b) for i in range(len(LR_FIELDS))]
     hs = [rdm.Hamiltonian.from_instance(i) for i in insts]
     inst0 = insts[0]

@@ -91,6 +91,8 @@ struct TridiagEig {
   void solve(const double* alpha, const double* beta, int n);
   // y = S diag(g) S^T e_1 for g_i given.
   void apply_fn(const double* g, double* y) const;
+  // apply_fn for nf weight vectors g (nf x n, row-major) -> y (nf x n)
+  void apply_fn_multi(int nf, const double* g, double* y) const;
   // y = S diag(g) S^T x for any x (n).
   void apply_fn_vec(const double* g, const double* x, double* y) const;
   // eigenvector i (column i of S), n entries

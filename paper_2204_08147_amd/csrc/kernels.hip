@@ -1348,7 +1348,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
           if (b < nb) {
             const V* pb = (const V*)g.Q + (uint64_t)(beta0 + b) * (g.blk / W) +
                           (uint64_t)(t.cblock * NPAN + q) * pstride;
-            psi[b][q] = ldg(pb, row);
+            psi[b][q] = ldg_nt(pb, row);
           } else {
 #pragma unroll
             for (int e = 0; e < W; ++e) psi[b][q][e] = T(0);
@@ -1365,7 +1365,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
         const V* sb = (const V*)g.Q + (uint64_t)jj * (g.blk / W);
         V qv[NPAN];
 #pragma unroll
-        for (int q = 0; q < NPAN; ++q) qv[q] = ldg(sb + (uint64_t)(t.cblock * NPAN + q) * pstride, row);
+        for (int q = 0; q < NPAN; ++q) qv[q] = ldg_nt(sb + (uint64_t)(t.cblock * NPAN + q) * pstride, row);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll

@@ -445,14 +445,15 @@ rdm_status host_phase_t(InstRun& r, hipStream_t st) {
   std::vector<T> yt((size_t)p.n_beta * p.k * p.tot.cpad, T(0));
   parallel_for(p.tot.C, [&](int c) {
     const TridiagEig& e = et[c];
-    std::vector<double> g(e.n), y(e.n);
+    std::vector<double> g((size_t)p.n_beta * e.n), y((size_t)p.n_beta * e.n);
     const double s1 = ht.s[c];
-    for (int b = 0; b < p.n_beta; ++b) {
-      for (int q = 0; q < e.n; ++q) g[q] = std::exp(-0.5 * r.betas[b] * (e.theta[q] - e0));
-      e.apply_fn(g.data(), y.data());
+    for (int b = 0; b < p.n_beta; ++b)
+      for (int q = 0; q < e.n; ++q) g[(size_t)b * e.n + q] = std::exp(-0.5 * r.betas[b] * (e.theta[q] - e0));
+    e.apply_fn_multi(p.n_beta, g.data(), y.data());
+    for (int b = 0; b < p.n_beta; ++b)
       for (int j = 0; j < e.n; ++j)
-        yt[((size_t)b * p.k + j) * p.tot.cpad + c] = (T)(bscale * y[j] * ht.s[(size_t)j * p.tot.cpad + c] / s1);
-    }
+        yt[((size_t)b * p.k + j) * p.tot.cpad + c] =
+            (T)(bscale * y[(size_t)b * e.n + j] * ht.s[(size_t)j * p.tot.cpad + c] / s1);
   });
   // bath: Gauss quadrature e_1^T exp(-b (T_b - E0b)) e_1 scaled by |v|^2 = 1/s_1^2
   r.mb.assign(p.n_beta, 0.0);

@@ -9,6 +9,18 @@
 
 namespace rdm {
 
+namespace {
+
+// sqrt(x^2 + z^2): the plain form (the entries are bounded by the norm of H),
+// library hypot only where the squares would overflow or lose precision
+inline double norm2(double x, double z) {
+  const double q = x * x + z * z;
+  if (q > 1e-280 && q < 1e280) return std::sqrt(q);
+  return std::hypot(x, z);
+}
+
+}  // namespace
+
 // Implicit symmetric QR on a tridiagonal matrix with Wilkinson shifts
 // (Golub & Van Loan, "Matrix Computations", the implicit symmetric QR step).
 // Each step chases a bulge with Givens rotations G acting on rows/columns
@@ -25,6 +37,10 @@ void TridiagEig::solve(const double* alpha, const double* beta, int nn) {
   rot_i.clear();
   rot_c.clear();
   rot_s.clear();
+  const size_t guess = (size_t)3 * n * n + 16;
+  rot_i.reserve(guess);
+  rot_c.reserve(guess);
+  rot_s.reserve(guess);
   ok = true;
   const double eps = 2.220446049250313e-16;
   int hi = n - 1;
@@ -49,14 +65,14 @@ void TridiagEig::solve(const double* alpha, const double* beta, int nn) {
     // Wilkinson shift from the trailing 2x2 of the block
     const double d = 0.5 * (theta[hi - 1] - theta[hi]);
     const double b2 = e[hi - 1] * e[hi - 1];
-    const double den = d + (d >= 0.0 ? 1.0 : -1.0) * std::hypot(d, e[hi - 1]);
+    const double den = d + (d >= 0.0 ? 1.0 : -1.0) * norm2(d, e[hi - 1]);
     const double mu = theta[hi] - b2 / den;
     double x = theta[lo] - mu;
     double z = e[lo];
     double bulge = 0.0;
     for (int i = lo; i < hi; ++i) {
       // rotation zeroing z against x: c x - s z = r, s x + c z = 0
-      const double r = std::hypot(x, z);
+      const double r = norm2(x, z);
       double c = 1.0, s = 0.0;
       if (r != 0.0) {
         c = x / r;
@@ -94,6 +110,26 @@ void TridiagEig::apply_fn(const double* g, double* y) const {
     y[i] = c * w0 + s * w1;
     y[i + 1] = -s * w0 + c * w1;
   }
+}
+
+void TridiagEig::apply_fn_multi(int nf, const double* g, double* y) const {
+  // the same replay as apply_fn for nf vectors at once, interleaved so that
+  // the updates of one rotation are independent of each other
+  std::vector<double> w((size_t)n * nf);
+  for (int i = 0; i < n; ++i)
+    for (int f = 0; f < nf; ++f) w[(size_t)i * nf + f] = g[(size_t)f * n + i] * zrow[i];
+  for (size_t t = rot_i.size(); t-- > 0;) {
+    double* w0 = w.data() + (size_t)rot_i[t] * nf;
+    double* w1 = w0 + nf;
+    const double c = rot_c[t], s = rot_s[t];
+    for (int f = 0; f < nf; ++f) {
+      const double a0 = w0[f], a1 = w1[f];
+      w0[f] = c * a0 + s * a1;
+      w1[f] = -s * a0 + c * a1;
+    }
+  }
+  for (int f = 0; f < nf; ++f)
+    for (int i = 0; i < n; ++i) y[(size_t)f * n + i] = w[(size_t)i * nf + f];
 }
 
 void TridiagEig::apply_fn_vec(const double* g, const double* x, double* y) const {
@@ -269,16 +305,17 @@ extern "C" rdm_status rdm_tridiag_fa(int32_t kk, const double* alpha, const doub
   }
   if (theta)
     for (int i = 0; i < kk; ++i) theta[i] = te.theta[i];
-  std::vector<double> g(kk);
+  std::vector<double> g((size_t)n_beta * kk);
   for (int b = 0; b < n_beta; ++b) {
-    for (int i = 0; i < kk; ++i) g[i] = std::exp(-0.5 * betas[b] * (te.theta[i] - e0));
-    if (y) te.apply_fn(g.data(), y + (size_t)b * kk);
+    double* gb = g.data() + (size_t)b * kk;
+    for (int i = 0; i < kk; ++i) gb[i] = std::exp(-0.5 * betas[b] * (te.theta[i] - e0));
     if (quad) {
       double q = 0.0;
-      for (int i = 0; i < kk; ++i) q += te.zrow[i] * te.zrow[i] * g[i] * g[i];
+      for (int i = 0; i < kk; ++i) q += te.zrow[i] * te.zrow[i] * gb[i] * gb[i];
       quad[b] = q;
     }
   }
+  if (y && n_beta > 0) te.apply_fn_multi(n_beta, g.data(), y);
   return RDM_OK;
 }
 
