@@ -163,3 +163,29 @@ def test_system_hamiltonian_matches_oracle_split():
         hs, _, _ = spin.split_dense(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
         assert np.abs(h.system_matrix() - hs).max() < 1e-14
 
+
+
+def test_new_entry_points_validate_before_touching_the_device():
+    # argument checks come first, so these run without a GPU
+    h = rdm.Hamiltonian.from_instance(cfg_small_chain())
+    for kw in (dict(n_v=0, k=10), dict(n_v=4, k=0), dict(n_v=5000, k=10)):
+        with pytest.raises(rdm.RdmError) as e:
+            rdm.product_trace(h, [1.0], kw["n_v"], kw["k"], 1)
+        assert e.value.status == -1, kw
+    with pytest.raises(rdm.RdmError) as e:
+        rdm.product_trace(h, [-1.0], 2, 10, 1)
+    assert e.value.status == -1
+    with pytest.raises(rdm.RdmError) as e:
+        rdm.product_trace(h, [float("nan")], 2, 10, 1)
+    assert e.value.status == -1
+    with pytest.raises(rdm.RdmError) as e:
+        rdm.high_temperature_term(h, 0, 1)
+    assert e.value.status == -1
+    import ctypes as C
+    g = C.c_double(0.0)
+    assert rdm.LIB.rdm_stream_probe(7, 1 << 20, 1, None, C.byref(g)) == -1     # pattern
+    assert rdm.LIB.rdm_stream_probe(1, 1000, 1, None, C.byref(g)) == -1        # not a multiple of 4096
+    assert rdm.LIB.rdm_stream_probe(1, 1 << 20, 0, None, C.byref(g)) == -1     # reps
+    assert rdm.LIB.rdm_stream_probe(1, 1 << 20, 1, None, None) == -1           # output
+    # start block: which = 2 (product vectors) accepted, 3 rejected
+    assert rdm.LIB.rdm_start_block(h.handle, 3, 0, 1, 1, C.c_void_p(1), None) == -1

@@ -638,3 +638,13 @@ def test_product_sample_is_the_partial_trace_sample_full_size(prec, tol):
         want = sv["log_z_t"][i] + np.log(inst.d_s * vs @ sv["rho"][i] @ vs)
         assert abs(pr["log_z_t"][i] - want) < tol * abs(want), (i, pr["log_z_t"][i], want)
         assert abs(pr["log_z_b"][i] - sv["log_z_b"][i]) < tol * abs(sv["log_z_b"][i])
+
+
+def test_stream_probe_reports_plausible_bandwidth():
+    # bytes moved per second of the measurement utility (1 GiB arrays, four
+    # times the last-level cache): positive, below the 8 TB/s HBM peak, and a
+    # read-only stream no slower than a copy beyond noise
+    g = {p: rdm.stream_probe(p, 1 << 30, 3) for p in ("read", "copy", "r3w1", "r2w2")}
+    for p, v in g.items():
+        assert 500.0 < v < 9000.0, (p, v)
+    assert g["read"] > 0.8 * g["copy"]
