@@ -142,11 +142,18 @@ def test_transform_apply_bath_and_total():
             assert np.abs(got - want).max() < tol * np.abs(want).max() * 10, (which, prec)
 
 
-@pytest.mark.parametrize("make,cols", [(lambda: cfg_long_range(2), 64), (lambda: tfim_request(3, n_range=(24, 24)), 32)])
+def _cfg_large():
+    from workloads import cfg_large
+    return cfg_large()
+
+
+@pytest.mark.parametrize("make,cols", [(lambda: cfg_long_range(2), 64), (lambda: tfim_request(3, n_range=(24, 24)), 32),
+                                       (_cfg_large, 32)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_apply_full_size_sampled_rows(make, cols, prec):
-    # full-size shapes (dim 2^20 and 2^24) in the bench's launch configuration,
-    # checked on 300 sampled rows computed one by one by the oracle
+    # full-size shapes (dim 2^20, 2^24 and the largest, 2^26 with all-pairs
+    # XXZ) in the bench's launch configuration, checked on 300 sampled rows
+    # computed one by one by the oracle
     inst = make()
     h = H(inst)
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
@@ -648,3 +655,45 @@ def test_stream_probe_reports_plausible_bandwidth():
     for p, v in g.items():
         assert 500.0 < v < 9000.0, (p, v)
     assert g["read"] > 0.8 * g["copy"]
+
+
+# --- degenerate Hamiltonians ------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_zero_hamiltonian(prec, tol):
+    # H = 0: every column breaks down at the first step; rho* = I/d_s, H* = 0,
+    # ln Z* = n_s ln 2 and S = n_s ln 2 exactly
+    n_s, n_b = 2, 6
+    inst = Instance(n_s, n_b, [], np.zeros(8), np.zeros(8), np.array([0.5, 2.0]), 3, 10, 4)
+    r = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision=prec)
+    assert r["breakdown_total"] == inst.n_cols and r["breakdown_bath"] == inst.n_v
+    for b in range(2):
+        assert np.abs(r["rho"][b] - np.eye(4) / 4).max() < tol
+        assert np.abs(r["h_star"][b]).max() < tol
+        assert abs(r["log_z"][b] - n_s * np.log(2)) < tol
+        assert abs(r["entropy"][b] - n_s * np.log(2)) < tol
+
+
+def _spin_state(hx, hz, beta):
+    e = np.hypot(hx, hz)
+    sx, sz = np.array([[0.0, 1.0], [1.0, 0.0]]), np.diag([1.0, -1.0])
+    return 0.5 * (np.eye(2) - np.tanh(beta * e) * (hx * sx + hz * sz) / e)
+
+
+@pytest.mark.parametrize("n_b", [6, 14])
+def test_fields_only_is_the_bare_product_state(n_b):
+    # no couplings: H_sb = 0, so rho* is the bare system's thermal state, a
+    # product of single-spin states, whatever the bath vectors (n_b = 14 runs
+    # on the transform apply)
+    n_s = 2
+    n = n_s + n_b
+    rng = np.random.default_rng(n_b)
+    hx, hz = rng.uniform(0.2, 0.8, n), rng.uniform(-0.5, 0.5, n)
+    inst = Instance(n_s, n_b, [], hx, hz, np.array([0.4, 1.5]), 2, 40, 9)
+    h = H(inst)
+    assert h.info()["transform"] == (n >= 16)
+    r = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    for b, beta in enumerate(inst.betas):
+        want = np.kron(_spin_state(hx[0], hz[0], beta), _spin_state(hx[1], hz[1], beta))
+        assert np.abs(r["rho"][b] - want).max() < 1e-10
+        hs = rdm.Hamiltonian.from_instance(inst).system_matrix()
+        assert np.abs(r["h_star"][b] - hs).max() < 1e-8
