@@ -43,11 +43,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-block", action="store_true", help="skip the block-Lanczos comparison")
-    ap.add_argument("--workload", default="lr", choices=["lr", "batch", "large", "serve", "scan"],
+    ap.add_argument("--workload", default="lr", choices=["lr", "batch", "large", "serve", "scan", "estimators"],
                     help="lr: the metric's workload (default); batch: 64 heterogeneous sparse XXZ "
                          "instances in one batched solve; large: 3+23 spins (dim 2^26) two-pass; "
                          "serve: Poisson arrivals of transverse-field requests; scan: the paper's "
-                         "entropy / internal-energy scans")
+                         "entropy / internal-energy scans; estimators: product-state estimate, "
+                         "high-temperature offset and low-temperature limit on the 2+18 instance")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests at the offered rate")
     ap.add_argument("--steady-requests", type=int, default=300,
                     help="serve: requests at 0.7x the measured capacity")
@@ -381,6 +382,55 @@ def bench_scan(args):
     return out
 
 
+def bench_estimators(args):
+    """The estimator variants and limits on the long-range 2 + 18 workload
+    (h = 0.5, n_v = 16, k = 60, beta in {0.5, 1, 2, 4}), mixed precision:
+    the product-state estimate of ln Z* (n_v single columns), the
+    high-temperature offset, and the low-temperature limit (n_v = 4 full-space
+    Lanczos runs, k = 60).  Best of three timed calls after one warm-up, next
+    to the partial-trace solve of the same instance."""
+    import torch
+    import paper_2204_08147_amd as rdm
+    from workloads import cfg_long_range
+    inst = cfg_long_range(0, n_b=args.n_b)
+    h = rdm.Hamiltonian.from_instance(inst)
+
+    def best(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return min(t), out
+
+    t_solve, sv = best(lambda: rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed"))
+    t_prod, pr = best(lambda: rdm.product_trace(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed"))
+    t_prod64, pr64 = best(lambda: rdm.product_trace(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64"))
+    t_ht, ht = best(lambda: rdm.high_temperature_term(h, inst.n_v, inst.seed))
+    t_gs, gs = best(lambda: rdm.ground_state(h, 4, inst.k, inst.seed, precision="mixed"))
+    # algorithmic bytes of the product run's Lanczos steps: n_v columns on
+    # H_t and on H_b, k steps (the whole call's time, host work included)
+    info = h.info()
+    b_t, _ = operator_work(inst.n, inst.n_v, 0, info["transform"], 4, inst.k)
+    b_b, _ = operator_work(inst.n_b, inst.n_v, 0, info["bath_transform"], 4, inst.k)
+    return {"metric": "estimator variants: calls/s of the product-state estimate (n_v = 16)",
+            "value": round(1.0 / t_prod, 3), "unit": "calls/s", "dtype": "f32 vectors + f64 reductions",
+            "config": {"workload": "long-range XX+ZZ 2+18 spins, h=0.5, n_v=16, k=60, beta in {0.5,1,2,4}"},
+            "partial_trace_solve_ms": round(1e3 * t_solve, 2),
+            "product_trace_ms": round(1e3 * t_prod, 2), "product_trace_fp64_ms": round(1e3 * t_prod64, 2),
+            "product_whole_call_gbs_algorithmic": round(inst.k * (b_t + b_b) / t_prod / 1e9, 1),
+            "log_z_partial_trace": np.round(sv["log_z"], 6).tolist(),
+            "log_z_product": np.round(pr["log_z"], 6).tolist(),
+            "log_z_product_fp64": np.round(pr64["log_z"], 6).tolist(),
+            "high_temperature_term_ms": round(1e3 * t_ht, 3), "high_temperature_offset_norm": round(ht["norm"], 6),
+            "ground_state_ms": round(1e3 * t_gs, 2), "ground_energy": round(gs["e_total"], 6),
+            "ground_bath_energy": round(gs["e_bath"], 6), "ground_degeneracy": gs["degeneracy"],
+            "ground_entropy": round(gs["entropy"], 6)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -401,7 +451,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.workload != "lr":
-        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve, "scan": bench_scan}[args.workload]
+        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve, "scan": bench_scan,
+              "estimators": bench_estimators}[args.workload]
         out = fn(args)
         out.update({"n_gpus": 1, "data": "synthetic", "scaling": "weak"})
         print(json.dumps(out))
