@@ -68,10 +68,11 @@ def lanczos_estimate(inst, betas, n_v: int, k: int, seed: int, tau: float = TAU_
             for j in range(n_v)]
     e0 = min(min_ritz(a, b) for a, b, _, _ in tot)
     e0b = min(min_ritz(a, b) for a, b, _, _ in bath)
-    lw = np.array([[np.log(quad_weight(a, b, bt, e0)) - bt * e0 + inst.n * np.log(2.0) for a, b, _, _ in tot]
-                   for bt in betas])
-    lb = np.array([[np.log(quad_weight(a, b, bt, e0b)) - bt * e0b + inst.n_b * np.log(2.0) for a, b, _, _ in bath]
-                   for bt in betas])
+    # x^T f(H) x = |x|^2 e_1^T f(T) e_1 (Gauss quadrature from a start vector of norm |x|)
+    lw = np.array([[np.log(nx * nx * quad_weight(a, b, bt, e0)) - bt * e0 + inst.n * np.log(2.0)
+                    for a, b, _, nx in tot] for bt in betas])
+    lb = np.array([[np.log(nx * nx * quad_weight(a, b, bt, e0b)) - bt * e0b + inst.n_b * np.log(2.0)
+                    for a, b, _, nx in bath] for bt in betas])
     log_z_t, log_z_b = _logmeanexp_rows(lw), _logmeanexp_rows(lb)
     return {"log_z_t": log_z_t, "log_z_b": log_z_b, "log_z": log_z_t - log_z_b, "log_z_t_samples": lw,
             "e0": e0, "e0b": e0b}
