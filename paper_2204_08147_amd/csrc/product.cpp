@@ -105,8 +105,10 @@ rdm_status product_run(const ProductPlan& pp, const rdm_hamiltonian* h, const do
       double wt = 0.0, wb = 0.0;
       for (int q = 0; q < et[c].n; ++q) wt += et[c].zrow[q] * et[c].zrow[q] * std::exp(-beta * (et[c].theta[q] - e0));
       for (int q = 0; q < eb[c].n; ++q) wb += eb[c].zrow[q] * eb[c].zrow[q] * std::exp(-beta * (eb[c].theta[q] - e0b));
-      lt[c] = std::log(wt) - beta * e0 + h->n * ln2;
-      lb[c] = std::log(wb) - beta * e0b + h->n_b * ln2;
+      // x^T f(H) x = |x|^2 e_1^T f(T) e_1, |x| = 1 / s_1 (unit up to rounding)
+      const double st1 = tsc[c], sb1 = bsc[c];
+      lt[c] = std::log(wt / (st1 * st1)) - beta * e0 + h->n * ln2;
+      lb[c] = std::log(wb / (sb1 * sb1)) - beta * e0b + h->n_b * ln2;
       if (!std::isfinite(lt[c]) || !std::isfinite(lb[c])) {
         set_error("non-finite quadrature value");
         return RDM_E_NONFINITE;
