@@ -212,7 +212,7 @@ rdm_status block_solve(const BlockPlan& bp, const double* betas, uint64_t seed, 
           }
       }
     }
-    eig[g].solve(t.data(), n);
+    eig[g].solve(t.data(), n, std::min(ds, n));
   });
   InstPlan p;
   p.h = bp.h;
@@ -238,7 +238,7 @@ rdm_status block_solve(const BlockPlan& bp, const double* betas, uint64_t seed, 
   r.e0 = e0;
   r.gsum.assign((size_t)bp.n_beta * n_v * NE, 0.0);
   parallel_jobs(n_v, [&](int g) {
-    for (int b = 0; b < bp.n_beta; ++b) eig[g].quad(ds, betas[b], e0, r.gsum.data() + ((size_t)b * n_v + g) * NE);
+    for (int b = 0; b < bp.n_beta; ++b) eig[g].quad(betas[b], e0, r.gsum.data() + ((size_t)b * n_v + g) * NE);
   });
   r.n_break_t = 0;
   for (int g = 0; g < n_v; ++g) r.n_break_t += kc[g] < bp.k;

@@ -93,6 +93,8 @@ struct TridiagEig {
   void apply_fn(const double* g, double* y) const;
   // apply_fn for nf weight vectors g (nf x n, row-major) -> y (nf x n)
   void apply_fn_multi(int nf, const double* g, double* y) const;
+  // w <- S^T w for nf vectors stored interleaved (w[i * nf + f])
+  void apply_st_multi(int nf, double* w) const;
   // y = S diag(g) S^T x for any x (n).
   void apply_fn_vec(const double* g, const double* x, double* y) const;
   // eigenvector i (column i of S), n entries
@@ -100,16 +102,18 @@ struct TridiagEig {
 };
 
 // Eigensystem of a dense symmetric matrix through Householder reduction to
-// tridiagonal form (A = P T P^T) and TridiagEig on T.  quad() forms the
-// leading b x b block of f(A) for f(x) = exp(-beta (x - e0)).
+// tridiagonal form (A = P T P^T) and TridiagEig on T, kept in the form the
+// leading b x b block of f(A) needs: Z = S^T P_b^T (n x b; P_b the first b
+// rows of P, S the eigenvectors of T), so that quad() forms
+// E_b^T f(A) E_b = Z^T diag(f(theta)) Z for f(x) = exp(-beta (x - e0)).
 struct DenseSymEig {
-  int n = 0;
-  std::vector<double> p;  // P, row-major n x n
+  int n = 0, b = 0;
+  std::vector<double> z;  // Z, row-major n x b
   TridiagEig te;
   bool ok = true;
-  void solve(const double* a, int n);  // a: row-major n x n, symmetric
+  void solve(const double* a, int n, int b);  // a: row-major n x n, symmetric; 1 <= b <= n
   double min_eig() const;
-  void quad(int b, double beta, double e0, double* f) const;  // f: b x b row-major
+  void quad(double beta, double e0, double* f) const;  // f: b x b row-major
 };
 
 // Eigendecomposition of a small symmetric matrix (cyclic Jacobi, n <= 16):

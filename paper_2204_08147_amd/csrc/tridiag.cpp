@@ -132,6 +132,20 @@ void TridiagEig::apply_fn_multi(int nf, const double* g, double* y) const {
     for (int i = 0; i < n; ++i) y[(size_t)f * n + i] = w[(size_t)i * nf + f];
 }
 
+void TridiagEig::apply_st_multi(int nf, double* w) const {
+  // S^T = G_M^T ... G_1^T: the rotations in recorded order, transposed
+  for (size_t t = 0; t < rot_i.size(); ++t) {
+    double* w0 = w + (size_t)rot_i[t] * nf;
+    double* w1 = w0 + nf;
+    const double c = rot_c[t], s = rot_s[t];
+    for (int f = 0; f < nf; ++f) {
+      const double a0 = w0[f], a1 = w1[f];
+      w0[f] = c * a0 - s * a1;
+      w1[f] = s * a0 + c * a1;
+    }
+  }
+}
+
 void TridiagEig::apply_fn_vec(const double* g, const double* x, double* y) const {
   // S^T x = G_M^T (... (G_1^T x)): the rotations in recorded order, transposed
   for (int i = 0; i < n; ++i) y[i] = x[i];
@@ -168,11 +182,13 @@ void TridiagEig::eigvec(int i0, double* y) const {
 // k+1.. maps column k below the diagonal onto a multiple of e_1; the trailing
 // block B becomes H B H = B - v w^T - w v^T with p = tau B v and
 // w = p - (tau/2)(v^T p) v.  P accumulates H_0 H_1 ..., so A = P T P^T.
-void DenseSymEig::solve(const double* a_in, int nn) {
+void DenseSymEig::solve(const double* a_in, int nn, int bb) {
   n = nn;
+  b = bb;
   std::vector<double> a(a_in, a_in + (size_t)n * n);
-  p.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) p[(size_t)i * n + i] = 1.0;
+  // only the first b rows of P are needed (the leading block of f(A))
+  std::vector<double> p((size_t)b * n, 0.0);
+  for (int i = 0; i < b; ++i) p[(size_t)i * n + i] = 1.0;
   std::vector<double> v(n), pv(n), w(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
@@ -201,8 +217,8 @@ void DenseSymEig::solve(const double* a_in, int nn) {
         a[(size_t)(k + 1 + i) * n + (k + 1 + jj)] -= v[i] * w[jj] + w[i] * v[jj];
     a[(size_t)(k + 1) * n + k] = a[(size_t)k * n + (k + 1)] = alpha;
     for (int i = 1; i < m; ++i) a[(size_t)(k + 1 + i) * n + k] = a[(size_t)k * n + (k + 1 + i)] = 0.0;
-    // P <- P H on columns k+1..
-    for (int r = 0; r < n; ++r) {
+    // P <- P H on columns k+1.. (rows 0..b-1)
+    for (int r = 0; r < b; ++r) {
       double acc = 0.0;
       for (int i = 0; i < m; ++i) acc += p[(size_t)r * n + (k + 1 + i)] * v[i];
       acc *= tau;
@@ -214,6 +230,11 @@ void DenseSymEig::solve(const double* a_in, int nn) {
   for (int i = 0; i + 1 < n; ++i) e[i] = a[(size_t)(i + 1) * n + i];
   te.solve(d.data(), e.data(), n);
   ok = te.ok;
+  // Z = S^T P_b^T: one replay of the rotations over the b columns
+  z.assign((size_t)n * b, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int m = 0; m < b; ++m) z[(size_t)i * b + m] = p[(size_t)m * n + i];
+  if (ok) te.apply_st_multi(b, z.data());
 }
 
 double DenseSymEig::min_eig() const {
@@ -222,17 +243,13 @@ double DenseSymEig::min_eig() const {
   return m;
 }
 
-void DenseSymEig::quad(int b, double beta, double e0, double* f) const {
-  std::vector<double> g(n), x(n), y(n);
-  for (int i = 0; i < n; ++i) g[i] = std::exp(-beta * (te.theta[i] - e0));
-  for (int m = 0; m < b; ++m) {
-    for (int i = 0; i < n; ++i) x[i] = p[(size_t)m * n + i];  // P^T e_m
-    te.apply_fn_vec(g.data(), x.data(), y.data());
-    for (int r = 0; r < b; ++r) {
-      double acc = 0.0;
-      for (int i = 0; i < n; ++i) acc += p[(size_t)r * n + i] * y[i];
-      f[r * b + m] = acc;
-    }
+void DenseSymEig::quad(double beta, double e0, double* f) const {
+  for (int q = 0; q < b * b; ++q) f[q] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double g = std::exp(-beta * (te.theta[i] - e0));
+    const double* zi = z.data() + (size_t)i * b;
+    for (int r = 0; r < b; ++r)
+      for (int m = 0; m < b; ++m) f[r * b + m] += zi[r] * g * zi[m];
   }
 }
 
@@ -326,12 +343,12 @@ extern "C" rdm_status rdm_block_quadrature(int32_t n, int32_t b, const double* t
     return RDM_E_INVALID;
   }
   DenseSymEig de;
-  de.solve(t, n);
+  de.solve(t, n, b);
   if (!de.ok) {
     set_error("rdm_block_quadrature: QR iteration did not converge");
     return RDM_E_NONFINITE;
   }
   if (min_eig) *min_eig = de.min_eig();
-  for (int q = 0; q < n_beta; ++q) de.quad(b, betas[q], e0, f + (size_t)q * b * b);
+  for (int q = 0; q < n_beta; ++q) de.quad(betas[q], e0, f + (size_t)q * b * b);
   return RDM_OK;
 }
