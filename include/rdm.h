@@ -60,7 +60,7 @@ typedef enum {
 
 enum { RDM_FP64 = 0, RDM_MIXED = 1 };                 /* rdm_options.precision */
 enum { RDM_AUTO = 0, RDM_STORED_Q = 1, RDM_TWO_PASS = 2 };  /* rdm_options.mode */
-enum { RDM_PER_COLUMN = 0, RDM_BLOCK = 1 };           /* rdm_options.method */
+enum { RDM_PER_COLUMN = 0, RDM_BLOCK = 1, RDM_METHOD_AUTO = 2 };  /* rdm_options.method */
 
 /* One two-site term: jx sx_i sx_j + jy sy_i sy_j + jz sz_i sz_j (Pauli),
  * eqn:Ht.  0 <= i, j < N, i != j; (i, j) and (j, i) denote the same pair. */
@@ -105,7 +105,13 @@ typedef struct {
                            each bath vector's d_s start columns and the block
                            Gauss quadrature E_1^T exp(-beta T) E_1 (eqn:fT,
                            eqn:trB_est); single solves only (rdm_solve,
-                           rdm_solve_ws), no Lanczos basis is kept            */
+                           rdm_solve_ws), no Lanczos basis is kept.
+                           RDM_METHOD_AUTO (2): per-column when its plan
+                           keeps the Lanczos basis within the budget, block
+                           when the basis would not fit (with mode RDM_AUTO;
+                           otherwise per-column); rdm_workspace_size and
+                           rdm_solve_ws decide alike for the same budget;
+                           batches use per-column                             */
   int32_t reserved;     /* must be 0                                          */
 } rdm_options;
 

@@ -53,7 +53,7 @@ def _stream_handle(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
-METHODS = {"per_column": 0, "block": 1}
+METHODS = {"per_column": 0, "block": 1, "auto": 2}
 
 
 def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_lane=0, tau=0.0,

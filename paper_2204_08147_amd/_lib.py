@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "librdm.so")
 RDM_OK, RDM_E_INVALID, RDM_E_NOMEM, RDM_E_DEVICE, RDM_E_NONFINITE, RDM_E_BUSY = 0, -1, -2, -3, -4, -5
 RDM_FP64, RDM_MIXED = 0, 1
 RDM_AUTO, RDM_STORED_Q, RDM_TWO_PASS = 0, 1, 2
-RDM_PER_COLUMN, RDM_BLOCK = 0, 1
+RDM_PER_COLUMN, RDM_BLOCK, RDM_METHOD_AUTO = 0, 1, 2
 DIAG_FIXED = 16
 
 STATUS_NAMES = {0: "RDM_OK", -1: "RDM_E_INVALID", -2: "RDM_E_NOMEM", -3: "RDM_E_DEVICE",

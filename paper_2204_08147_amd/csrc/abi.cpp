@@ -51,8 +51,8 @@ rdm_status read_opts(const rdm_options* o, Opts& r) {
     set_error("options: tau must be finite and >= 0");
     return RDM_E_INVALID;
   }
-  if (r.method != RDM_PER_COLUMN && r.method != RDM_BLOCK) {
-    set_error("options: method must be RDM_PER_COLUMN or RDM_BLOCK");
+  if (r.method != RDM_PER_COLUMN && r.method != RDM_BLOCK && r.method != RDM_METHOD_AUTO) {
+    set_error("options: method must be RDM_PER_COLUMN, RDM_BLOCK or RDM_METHOD_AUTO");
     return RDM_E_INVALID;
   }
   if (r.tau == 0.0) r.tau = r.prec == RDM_FP64 ? 1e-12 : 1e-5;
@@ -92,6 +92,21 @@ rdm_status default_budget(uint64_t& budget) {
 
 }  // namespace
 
+// RDM_METHOD_AUTO: the per-column path when its plan keeps the Lanczos basis
+// within the budget, else the block variant, which keeps three blocks and
+// needs no regeneration pass (a mode other than RDM_AUTO keeps the per-column
+// path).  Call after the budget is known.
+static rdm_status resolve_method(Opts& o, const rdm_hamiltonian* h, int n_beta, int n_v, int k) {
+  if (o.method != RDM_METHOD_AUTO) return RDM_OK;
+  o.method = RDM_PER_COLUMN;
+  if (o.mode != RDM_AUTO) return RDM_OK;
+  std::vector<InstPlan> plans(1);
+  const rdm_status s = plan_instance(plans[0], h, n_beta, n_v, k, o.prec, o.mode, o.budget, o.slab, o.rpl);
+  if (s == RDM_E_NOMEM || (s == RDM_OK && plans[0].two_pass)) o.method = RDM_BLOCK;
+  else if (s != RDM_OK) return s;
+  return RDM_OK;
+}
+
 extern "C" rdm_status rdm_workspace_size(const rdm_hamiltonian* h, int32_t n_beta, int32_t n_v,
                                          int32_t k, const rdm_options* opt, uint64_t* bytes) {
   Opts o;
@@ -102,6 +117,7 @@ extern "C" rdm_status rdm_workspace_size(const rdm_hamiltonian* h, int32_t n_bet
     return RDM_E_INVALID;
   }
   if ((s = default_budget(o.budget)) != RDM_OK) return s;
+  if ((s = resolve_method(o, h, n_beta, n_v, k)) != RDM_OK) return s;
   if (o.method == RDM_BLOCK) {
     BlockPlan bp;
     if ((s = block_plan(bp, h, n_beta, n_v, k, o.prec, o.budget)) != RDM_OK) return s;
@@ -128,6 +144,7 @@ static rdm_status solve_impl(const rdm_hamiltonian* h, const double* beta, int32
   }
   if (dev_ws && !o.budget) o.budget = ws_bytes;
   if ((s = default_budget(o.budget)) != RDM_OK) return s;
+  if ((s = resolve_method(o, h, n_beta, n_v, k)) != RDM_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   if (o.method == RDM_BLOCK) {
     BlockPlan bp;
@@ -250,7 +267,7 @@ rdm_status batch_impl(int32_t n_items, rdm_batch_item* items, const rdm_options*
     set_error("rdm_solve_batch: bad item list");
     return RDM_E_INVALID;
   }
-  if (o.method != RDM_PER_COLUMN) {
+  if (o.method == RDM_BLOCK) {
     set_error("batched solves use the per-column method");
     return RDM_E_INVALID;
   }

@@ -145,7 +145,7 @@ def test_block_quadrature_matches_oracle():
 def test_block_method_validation():
     h = rdm.Hamiltonian.from_instance(cfg_small_chain())
     with pytest.raises(rdm.RdmError) as e:
-        rdm.workspace_size(h, 1, 4, 30, precision="fp64", method=2, hbm_budget=1 << 40)
+        rdm.workspace_size(h, 1, 4, 30, precision="fp64", method=3, hbm_budget=1 << 40)
     assert e.value.status == -1
     # the block method plans a few vector blocks, no Lanczos basis (an explicit
     # budget keeps the planner off the device)
@@ -189,3 +189,19 @@ def test_new_entry_points_validate_before_touching_the_device():
     assert rdm.LIB.rdm_stream_probe(1, 1 << 20, 1, None, None) == -1           # output
     # start block: which = 2 (product vectors) accepted, 3 rejected
     assert rdm.LIB.rdm_start_block(h.handle, 3, 0, 1, 1, C.c_void_p(1), None) == -1
+
+
+def test_auto_method_picks_block_when_the_basis_does_not_fit():
+    # per-column with a stored basis when it fits the budget, the block
+    # variant otherwise (explicit budgets keep the planner off the device)
+    h = rdm.Hamiltonian.from_instance(cfg_small_chain())
+    stored = rdm.workspace_size(h, 1, 4, 30, precision="fp64", mode="stored", hbm_budget=1 << 40)
+    block = rdm.workspace_size(h, 1, 4, 30, precision="fp64", method="block", hbm_budget=1 << 40)
+    assert rdm.workspace_size(h, 1, 4, 30, precision="fp64", method="auto", hbm_budget=1 << 40) == stored
+    assert block < stored
+    assert rdm.workspace_size(h, 1, 4, 30, precision="fp64", method="auto",
+                              hbm_budget=(block + stored) // 2) == block
+    # a forced mode keeps the per-column path
+    two = rdm.workspace_size(h, 1, 4, 30, precision="fp64", mode="two_pass", hbm_budget=1 << 40)
+    assert rdm.workspace_size(h, 1, 4, 30, precision="fp64", method="auto", mode="two_pass",
+                              hbm_budget=1 << 40) == two

@@ -697,3 +697,23 @@ def test_fields_only_is_the_bare_product_state(n_b):
         assert np.abs(r["rho"][b] - want).max() < 1e-10
         hs = rdm.Hamiltonian.from_instance(inst).system_matrix()
         assert np.abs(r["h_star"][b] - hs).max() < 1e-8
+
+
+def test_auto_method_equals_the_method_it_picks():
+    # within the budget the stored-basis per-column path, below it the block
+    # variant: bitwise the results of the explicit method
+    inst = SOLVE_CASES["lr_2+9"]()
+    h = H(inst)
+    args = (h, inst.betas, inst.n_v, inst.k, inst.seed)
+    stored = rdm.workspace_size(h, len(inst.betas), inst.n_v, inst.k, precision="fp64", mode="stored",
+                                hbm_budget=1 << 40)
+    block = rdm.workspace_size(h, len(inst.betas), inst.n_v, inst.k, precision="fp64", method="block",
+                               hbm_budget=1 << 40)
+    small = (stored + block) // 2
+    a = rdm.solve(*args, precision="fp64", method="auto", hbm_budget=1 << 40)
+    b = rdm.solve(*args, precision="fp64", mode="stored", hbm_budget=1 << 40)
+    c = rdm.solve(*args, precision="fp64", method="auto", hbm_budget=small)
+    d = rdm.solve(*args, precision="fp64", method="block", hbm_budget=small)
+    for key in ("rho", "h_star", "log_z", "entropy"):
+        assert np.array_equal(a[key], b[key]), key
+        assert np.array_equal(c[key], d[key]), key
