@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-block", action="store_true", help="skip the block-Lanczos comparison")
+    ap.add_argument("--no-truncation", action="store_true", help="skip the k against k + 20 check")
     ap.add_argument("--workload", default="lr", choices=["lr", "batch", "large", "serve", "scan", "estimators"],
                     help="lr: the metric's workload (default); batch: 64 heterogeneous sparse XXZ "
                          "instances in one batched solve; large: 3+23 spins (dim 2^26) two-pass; "
@@ -557,6 +558,23 @@ def main():
                 "p99_ms": 1e3 * float(np.percentile(lat_d, 99)),
                 "step_kernels_ms": float(np.mean(ap_d) + np.mean(no_d) + np.mean(x0_d))}
 
+    # Krylov truncation (Section "Error analysis"): the FP64 result at k
+    # against k + 20 steps with the same bath vectors, outside the timed region
+    trunc = None
+    if not args.no_truncation:
+        d_rho = d_h = d_lz = 0.0
+        for h, i in zip(hs, insts):
+            a = rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision="fp64", stream=stream)
+            b = rdm.solve(h, i.betas, i.n_v, i.k + 20, i.seed, precision="fp64", stream=stream)
+            for t in range(len(i.betas)):
+                d_rho = max(d_rho, float(np.linalg.norm(a["rho"][t] - b["rho"][t]) / np.linalg.norm(b["rho"][t])))
+                d_h = max(d_h, float(np.linalg.norm(a["h_star"][t] - b["h_star"][t]) /
+                                     np.linalg.norm(b["h_star"][t])))
+                d_lz = max(d_lz, abs(float(a["log_z"][t] - b["log_z"][t])))
+        torch.cuda.empty_cache()
+        trunc = {"k": inst0.k, "k_ref": inst0.k + 20, "precision": "fp64", "rho_rel_diff": d_rho,
+                 "h_star_rel_diff": d_h, "log_z_abs_diff": d_lz}
+
     n_solves = len(lat_m)
     value = n_solves / wall_m
     ms_per_step = 1e3 * wall_m / args.steps
@@ -605,6 +623,7 @@ def main():
         "fp64": None if fp64 is None else {k2: round(v, 4) for k2, v in fp64.items()},
         "mixed_over_fp64": None if fp64 is None else round(value / fp64["solves_per_s"], 3),
         "block_method": block,
+        "truncation_k_vs_k20": trunc,
         "roofline": roof,
         # a transform step is half two-read-two-write (pass 1), half
         # three-read-one-write (pass 2): the probe's matching mix

@@ -34,4 +34,7 @@ high_temperature
              limit of the estimated H* minus H_s), from its definition.
 product      O10: the product-state (rank-one) trace estimator of Z_t and
              ln Z*, dense and step by step.
+bounds       the paper's truncation bound of the Krylov quadratures (block
+             and per-column) through Chebyshev interpolation; a pin, not a
+             step of the path.
 """

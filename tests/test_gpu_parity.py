@@ -287,6 +287,33 @@ def test_block_mixed_matches_oracle(name):
     check_result(got, oracle_block(name), 1e-5, "block mixed " + name)
 
 
+@pytest.mark.parametrize("method", ["per_column", "block"])
+def test_truncation_sweep_within_polynomial_bound(method):
+    # k = 2 .. 29 on two dense-term instances: the library matches O3 / O4 at
+    # every k, and its M (rebuilt from rho*, ln Z_t and E0) stays within the
+    # truncation bound of Section "Error analysis" ("Block Gauss quadrature")
+    # of the exact-typicality value for the same bath vectors
+    from oracle import block, bounds
+    for n_s, n_b, seed, n_v in ((1, 7, 38, 3), (2, 6, 39, 2)):
+        inst = random_dense_terms(n_s, n_b, seed, betas=(0.5, 2.0), n_v=n_v, k=2)
+        ev = np.linalg.eigvalsh(spin.dense_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz))
+        lo, hi = ev[0], ev[-1]
+        m_ex = [r["m"] for r in exact.exact_typicality(inst)]
+        h = H(inst)
+        for k in range(2, 30, 3):
+            inst.k = k
+            got = rdm.solve(h, inst.betas, n_v, k, seed, precision="fp64", method=method)
+            want = (block.solve(inst) if method == "block" else olz.solve(inst))["results"]
+            check_result(got, want, 1e-10, f"{method} {n_s}+{n_b} k={k}")
+            for b, beta in enumerate(inst.betas):
+                m = got["rho"][b] * np.exp(got["log_z_t"][b] + beta * got["e0"] - n_b * np.log(2.0))
+                ref = m_ex[b] * np.exp(beta * (got["e0"] - lo))
+                err = np.linalg.norm(m - ref, 2)
+                bound = (bounds.block_quadrature_bound(beta, lo, hi, got["e0"], k) if method == "block"
+                         else bounds.per_column_gram_bound(beta, lo, hi, got["e0"], k, inst.d_s))
+                assert err <= bound + 1e-11 * np.linalg.norm(ref, 2), (method, k, beta, err, bound)
+
+
 def test_block_and_per_column_agree_at_convergence():
     # both estimators converge to the same exact-typicality value (O2) for
     # the same bath vectors

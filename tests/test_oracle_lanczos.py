@@ -119,3 +119,53 @@ def test_high_temperature_note():
     assert np.abs(r["h_star"] - (hs + corr)).max() < 1e-3
     assert np.abs(r["h_star"] - hs).max() > 10 * np.abs(r["h_star"] - (hs + corr)).max()
     assert np.abs(r["rho"] - np.eye(4) / 4).max() < 1e-3
+
+
+TRUNCATION_CASES = [lambda b: random_dense_terms(1, 7, 38, betas=(b,), n_v=3, k=2),
+                    lambda b: random_dense_terms(2, 6, 39, betas=(b,), n_v=2, k=2)]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("beta", [0.5, 2.0])
+def test_truncation_within_polynomial_bound(case, beta):
+    # Section "Error analysis", "Block Gauss quadrature": after k steps the
+    # block quadrature differs from the exact quadratic form by at most
+    # 2 E_{2k-1}(f) on the spectral interval; the per-column Gram by the
+    # bound derived from E_{k-1}(exp(-beta x / 2)).  Both are measured here
+    # against O2 (same bath vectors, no Krylov error) for k = 2 .. 29.
+    from oracle import bounds
+    inst = TRUNCATION_CASES[case](beta)
+    ev = np.linalg.eigvalsh(spin.dense_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz))
+    lo, hi = ev[0], ev[-1]
+    m_ex = exact.exact_typicality(inst)[0]["m"]          # shifted by lambda_min
+    tight = []
+    for k in range(2, 30, 3):
+        inst.k = k
+        o4 = block.solve(inst)
+        ref = m_ex * np.exp(beta * (o4["e0"] - lo))
+        err = np.linalg.norm(o4["results"][0]["m"] - ref, 2)
+        bound = bounds.block_quadrature_bound(beta, lo, hi, o4["e0"], k)
+        assert err <= bound + 1e-13 * np.linalg.norm(ref, 2), ("block", k, err, bound)
+        o3 = lanczos.solve(inst)
+        ref = m_ex * np.exp(beta * (o3["e0"] - lo))
+        err3 = np.linalg.norm(o3["results"][0]["m"] - ref, 2)
+        bound3 = bounds.per_column_gram_bound(beta, lo, hi, o3["e0"], k, inst.d_s)
+        assert err3 <= bound3 + 1e-13 * np.linalg.norm(ref, 2), ("per-column", k, err3, bound3)
+        tight.append(bound3 < 1e-3 * np.linalg.norm(ref, 2))
+    # the bound is not vacuous: it falls far below |M| within the sweep
+    assert any(tight)
+
+
+def test_chebyshev_interpolation_error_closed_form():
+    # for f = exp(-beta x) the interpolation error obeys the classical bound
+    # ((hi-lo)/2)^{n+1} max|f^{(n+1)}| / (2^n (n+1)!) and exceeds the best
+    # approximation error, which for degree 0 is (max f - min f)/2
+    from math import exp, factorial
+    from oracle import bounds
+    for beta, lo, hi, n in [(1.0, -3.0, 2.0, 5), (0.3, 0.0, 10.0, 9), (2.0, -1.0, 1.0, 12)]:
+        e = bounds.chebyshev_interpolation_error(beta, lo, hi, 0.0, n)
+        cap = ((hi - lo) / 2) ** (n + 1) * beta ** (n + 1) * exp(-beta * lo) / (2 ** n * factorial(n + 1))
+        assert e <= cap * (1 + 1e-12)
+        assert e > 0.05 * cap
+    e0 = bounds.chebyshev_interpolation_error(1.0, 0.0, 2.0, 0.0, 0)
+    assert e0 >= 0.5 * (1.0 - exp(-2.0)) * (1 - 1e-12)
