@@ -444,6 +444,12 @@ def bench_estimators(args):
             "ground_entropy": round(gs["entropy"], 6)}
 
 
+def stage(msg: str) -> None:
+    """Progress of a long run on stderr (the JSON line alone goes to stdout)."""
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -507,6 +513,7 @@ def main():
                 gram_ms.append(r["t_gram_ms"])
         return wall, lat, apply_ms, norm_ms, gram_ms, res, xz1_ms
 
+    stage("mixed-precision solves")
     ws_m = make_ws("mixed")
     wall_m, lat_m, ap_m, no_m, gr_m, res_m, x0_m = run("mixed", args.steps, args.warmup, ws_m, True)
     # the paper's block variant (Algorithm 1 + block Gauss quadrature) on the
@@ -514,6 +521,7 @@ def main():
     # per-column path (same bath vectors)
     block = None
     if not args.no_block:
+        stage("block variant")
         ws_b = [torch.empty(rdm.workspace_size(h, len(i.betas), i.n_v, i.k, precision="mixed", method="block"),
                             dtype=torch.uint8, device="cuda") for h, i in zip(hs, insts)]
         for h, i, w in zip(hs, insts, ws_b):
@@ -548,6 +556,7 @@ def main():
 
     fp64 = None
     if not args.no_fp64:
+        stage("FP64 solves")
         ws_d = make_ws("fp64")
         wall_d, lat_d, ap_d, no_d, gr_d, res_d, x0_d = run("fp64", max(1, args.steps // 2), args.warmup, ws_d,
                                                            True)
@@ -562,6 +571,7 @@ def main():
     # against k + 20 steps with the same bath vectors, outside the timed region
     trunc = None
     if not args.no_truncation:
+        stage("k against k + 20")
         d_rho = d_h = d_lz = 0.0
         for h, i in zip(hs, insts):
             a = rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision="fp64", stream=stream)
@@ -581,6 +591,7 @@ def main():
 
     # measured streaming reference points (library probe: nontemporal loads and
     # stores, one 4 KiB chunk per workgroup and array, 2 GiB arrays, best of 10)
+    stage("streaming probe")
     probe = {p: rdm.stream_probe(p, 1 << 31, 10) for p in ("read", "copy", "r3w1", "r2w2")}
     torch.cuda.empty_cache()
 
@@ -596,6 +607,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        stage("oracle on the host")
         cpu = cpu_baseline(inst0, 0, args.n_b)
 
     out = {

@@ -159,7 +159,7 @@ rdm_status rdm_system_hamiltonian(const rdm_hamiltonian* h, double* out);
  * above a 256-row tile; the own tile plus every tile read by at least three
  * hops), [11] / [12] hops it gathers directly from memory instead, [13] /
  * [14] 1 when H_t / H_b is applied as D_Z + W D_X W instead (every
- * off-diagonal term X-type, i.e. J^y = 0 on every pair, and 16..20 sites; W
+ * off-diagonal term X-type, i.e. J^y = 0 on every pair, and 16..22 sites; W
  * is the Walsh-Hadamard transform, in whose basis X-type terms are diagonal).
  * out: host array of 15 int64. */
 rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* out);

@@ -395,9 +395,10 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   rdm_status r = RDM_OK;
   auto run = [&]() -> rdm_status {
     RDM_HIP(hipMemcpyAsync(d, &sg, sizeof(Seg), hipMemcpyHostToDevice, st));
+    const bool deep = sg.nbits > kXzShallowMaxBits;
     for (int pass = 0; pass <= 2; ++pass)
-      RDM_HIP(precision == RDM_FP64 ? launch_xz_pass<double>(pass, (Seg*)d, 1, L.xz, st)
-                                    : launch_xz_pass<float>(pass, (Seg*)d, 1, L.xz, st));
+      RDM_HIP(precision == RDM_FP64 ? launch_xz_pass<double>(pass, (Seg*)d, 1, L.xz, st, deep)
+                                    : launch_xz_pass<float>(pass, (Seg*)d, 1, L.xz, st, deep));
     RDM_HIP(precision == RDM_FP64 ? launch_apply<double>((Seg*)d, 1, L.apply, g.S, st)
                                   : launch_apply<float>((Seg*)d, 1, L.apply, g.S, st));
     RDM_HIP(hipStreamSynchronize(st));

@@ -137,7 +137,8 @@ rdm_status run_block(const BlockPlan& bp, const OpDevice* op_t, char* ws, char* 
     const Seg* sj = dsegs + (j - 1) % 3;
     if (tm) RDM_HIP(tm->apply.mark(st));
     RDM_HIP(launch_apply<T>(sj, 1, L.apply, 1, st));
-    for (int pass = 0; pass <= 2; ++pass) RDM_HIP(launch_xz_pass<T>(pass, sj, 1, L.xz, st));
+    for (int pass = 0; pass <= 2; ++pass)
+      RDM_HIP(launch_xz_pass<T>(pass, sj, 1, L.xz, st, bp.h->n > kXzShallowMaxBits));
     if (tm) RDM_HIP(tm->apply.mark(st));
     if (tm) RDM_HIP(tm->norm.mark(st));
     RDM_HIP(launch_block_update<T>(dbs, bp.ds, BLK_A, j, bp.n_rt, bp.n_cb, st));

@@ -155,7 +155,9 @@ rdm_status upload(const OpTables& t, OpDevice& d, hipStream_t st) {
     RDM_HIP(hipMalloc(&d.dx, dim * sizeof(T)));
     RDM_HIP(hipMemcpyAsync(d.xterms, t.xterms.data(), t.xterms.size() * sizeof(DiagTerm),
                            hipMemcpyHostToDevice, st));
-    RDM_HIP(launch_diag<T>((const DiagTerm*)d.xterms, (int)t.xterms.size(), (T*)d.dx, t.nbits, st));
+    // D_X of deep operators in the order of the strided tiles that read it
+    RDM_HIP(launch_diag<T>((const DiagTerm*)d.xterms, (int)t.xterms.size(), (T*)d.dx, t.nbits, st,
+                           t.nbits > kXzShallowMaxBits));
   }
   RDM_HIP(hipStreamSynchronize(st));
   d.ngroups = (int)t.groups.size();

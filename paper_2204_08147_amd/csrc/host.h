@@ -56,7 +56,7 @@ struct OpDevice {
   void* dterms = nullptr;
   int ngroups = 0;
   bool xz = false;
-  void* dx = nullptr;      // D_X / 2^N per row (transform apply)
+  void* dx = nullptr;      // D_X / 2^N (transform apply); strided-tile order above 20 bits
   void* xterms = nullptr;
 };
 

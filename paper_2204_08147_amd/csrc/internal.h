@@ -31,8 +31,10 @@ enum { START_SYSBATH = 0, START_BATH = 1, START_PRODUCT = 2 };
 constexpr int kTileBits = 8;       // the apply stages 2^8 = kBlock-row partner tiles in LDS
 constexpr int kXzTileBits = 12;    // transform apply: 4096-element tiles ...
 constexpr int kXzRegs = 16;        // ... as kBlock lanes x 16 registers
-constexpr int kXzMinBits = 16;     // operators on 16..20 bits use the transform apply
-constexpr int kXzMaxBits = 20;
+constexpr int kXzMinBits = 16;     // operators on 16..22 bits use the transform apply; above
+constexpr int kXzMaxBits = 22;     // 22 bits a strided tile's row runs (16 or 32 bytes) make
+                                   // the hop tables faster
+constexpr int kXzShallowMaxBits = 20;  // up to 8 high bits: strided tiles of 16-row runs
 constexpr int kFatGroup = 3;       // partner tiles read by at least this many hops go through LDS
 
 // One off-diagonal term of H as the apply sees it: row idx couples to the
@@ -94,7 +96,7 @@ struct Seg {
   int32_t xz;          // 1: transform apply (D_Z + W D_X W), 0: hop tables
   int32_t x_tiles;     // transform apply: tiles of 2^kXzTileBits rows
   int32_t x_base;      // transform apply: first workgroup of this segment
-  const void* dx;      // transform apply: D_X / 2^N per row, in T
+  const void* dx;      // transform apply: D_X / 2^N in T (tile order above 20 bits)
   uint64_t seed;
   uint64_t blk;        // elements per vector block = dim * cpad
   void* Q;
@@ -177,23 +179,26 @@ struct GTile {
 
 // ---- kernel launchers (kernels.hip) ----
 template <typename T>
-hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st);
+hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st,
+                       bool xz_tiled = false);
 template <typename T>
 hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 template <typename T>
 hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 // pass 0, 1 or 2 of the plain transform apply Y = H X (MODE_PLAIN segments
-// with xz = 1)
+// with xz = 1); pass 1 on the segments of more than kXzShallowMaxBits bits
+// if deep, else on the others
 template <typename T>
-hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st);
+hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st, bool deep = false);
 // Lanczos step over the segments with xz = 1, basis kept in the low-bit
 // Hadamard basis: pass 0 = start block (once per run), 1 = norm step + high
 // transform, 2 = low transforms + recurrence.  Pass 1 runs on the
-// MODE_REGEN segments if regen, else on the others.  boff: first transform
-// tile.
+// MODE_REGEN segments if regen, else on the others, and on the segments of
+// more than kXzShallowMaxBits bits if deep, else on the others.  boff: first
+// transform tile.
 template <typename T>
 hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff,
-                             hipStream_t st);
+                             hipStream_t st, bool deep = false);
 // Recombination weights of a segment whose basis is kept as W_lo u: L^-1/2
 constexpr double kXzBasisScale = 1.0 / (1 << (kXzTileBits / 2));
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);

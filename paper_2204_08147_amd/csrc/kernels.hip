@@ -111,6 +111,21 @@ template <typename T>
 __device__ __forceinline__ T ldg_s(const T* base, uint32_t row) {
   return ((const GLOBAL_AS T*)base)[row];
 }
+// Strided transform tiles whose row runs are shorter than a cache line share
+// lines with their neighbours (which run on the same XCD): there the hint
+// would evict lines before the neighbours use them, so NT is false.  The
+// choice is a template parameter: a run-time select around every access
+// costs the common case about 8 %.
+template <bool NT, typename V>
+__device__ __forceinline__ V ldg_sel(const V* base, uint32_t row) {
+  if constexpr (NT) return ldg_nt(base, row);
+  else return ldg(base, row);
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void stg_sel(V* base, uint32_t row, V v) {
+  if constexpr (NT) stg_stream<true>(base, row, v);
+  else stg(base, row, v);
+}
 
 // Segment descriptors are read-only during a kernel: read them through the
 // constant address space so uniform fields come in with scalar loads.
@@ -195,15 +210,23 @@ __device__ __forceinline__ T* slot_ptr(const CONST_AS Seg& sg, int j) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_diag(const DiagTerm* __restrict__ terms, int nt,
-                                                 T* __restrict__ diag, uint32_t dim) {
-  const uint32_t row = blockIdx.x * kBlock + threadIdx.x;
-  if (row >= dim) return;
+                                                 T* __restrict__ diag, uint32_t dim, int tiled_lrb) {
+  const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= dim) return;
+  // tiled_lrb >= 0: entries in the order of the transform's strided tiles
+  // (entry rt * 4096 + tau holds the row ((tau >> lrb) << 12) | (rt << lrb) |
+  // (tau mod 2^lrb)), so each tile reads one contiguous 4096-entry block
+  uint32_t row = e;
+  if (tiled_lrb >= 0) {
+    const uint32_t tau = e & ((1u << kXzTileBits) - 1u), rt = e >> kXzTileBits;
+    row = ((tau >> tiled_lrb) << kXzTileBits) | (rt << tiled_lrb) | (tau & ((1u << tiled_lrb) - 1u));
+  }
   double d = 0.0;
   for (int t = 0; t < nt; ++t) {
     const uint32_t par = __builtin_popcount(row & terms[t].mask) & 1u;
     d += par ? -terms[t].c : terms[t].c;
   }
-  diag[row] = (T)d;
+  diag[e] = (T)d;
 }
 
 // ---------------------------------------------------------------------------
@@ -619,7 +642,7 @@ __device__ __forceinline__ void xz_rearrange(V (&v)[kXzRegs], V* lds, int from, 
   __syncthreads();
 }
 
-__device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg, int b) {
+__device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg, int b, bool strided = false) {
   const CONST_AS Seg* cs = (const CONST_AS Seg*)segs;
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
@@ -627,8 +650,18 @@ __device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg, int b) {
     if (cs[mid].x_base <= b) lo = mid;
     else hi = mid - 1;
   }
-  const int lt = b - cs[lo].x_base;
+  int lt = b - cs[lo].x_base;
   const int nrt = cs[lo].x_tiles;
+  if (strided && cs[lo].nbits > kXzTileBits + 9) {
+    // more than 9 high bits: a strided tile reads runs of fewer than 8 rows
+    // (under 128 bytes), and 128 / (16 * 2^lrb) neighbouring tiles share each
+    // cache line.  Workgroups go round-robin to the 8 XCDs, so the k-th
+    // workgroup of each XCD takes consecutive tiles: lines shared by
+    // neighbours meet in one XCD's L2 instead of being fetched by several.
+    // A bijection on the segment's tiles (a multiple of 8: at least 1024).
+    const int n = nrt * cs[lo].P;
+    lt = (lt & 7) * (n >> 3) + (lt >> 3);
+  }
   const int sl = lt / nrt, rt = lt - sl * nrt;
   return Tile{lo, (uint32_t)rt << kXzTileBits, sl, rt};
 }
@@ -643,14 +676,57 @@ __device__ __forceinline__ void xz_low_transform(V (&v)[kXzRegs], V* lds) {
   xz_rearrange(v, lds, 2, 0);
 }
 
+// W_hi D_X W_hi on a strided tile held in arrangement 0.  The row's high bits
+// are the tau bits lrb..11: 8..11 (arrangement 0), those of 4..7 at or above
+// lrb (arrangement 2) and, in DEEP tiles (more than 8 high bits, lrb < 4),
+// those of 0..3 at or above lrb (arrangement 1).  D_X is stored in row order
+// for shallow operators (read through row_of) and in the strided tiles' own
+// order for deep ones (tile rt's 4096 entries in tau order from rt * 4096).
+template <bool DEEP, typename T, typename V, typename RowOf>
+__device__ __forceinline__ void xz_high_transform(V (&v)[kXzRegs], V* lds, const T* dx, uint32_t rt, int lrb,
+                                                  RowOf row_of) {
+  constexpr int W = sizeof(V) / sizeof(T);
+  const uint32_t l = threadIdx.x;
+  xz_bfly(v, 0xF);
+  xz_rearrange(v, lds, 0, 2);
+  if constexpr (!DEEP) {
+    const int m2 = 0xF & ~((1 << (lrb - 4)) - 1);
+    xz_bfly(v, m2);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dx, row_of(xz_tau(2, l, q))) * v[q];
+    xz_bfly(v, m2);
+  } else {
+    const int m1 = 0xF & ~((1 << lrb) - 1);
+    xz_bfly(v, 0xF);
+    xz_rearrange(v, lds, 2, 1);
+    xz_bfly(v, m1);
+    // arrangement 1: lane l holds tau = 16 l .. 16 l + 15, contiguous in D_X
+    const V* dv = (const V*)(dx + ((uint64_t)rt << kXzTileBits) + 16u * l);
+#pragma unroll
+    for (int g = 0; g < kXzRegs / W; ++g) {
+      const V dd = ldg(dv, (uint32_t)g);
+#pragma unroll
+      for (int e = 0; e < W; ++e) v[g * W + e] = dd[e] * v[g * W + e];
+    }
+    xz_bfly(v, m1);
+    xz_rearrange(v, lds, 1, 2);
+    xz_bfly(v, 0xF);
+  }
+  xz_rearrange(v, lds, 2, 0);
+  xz_bfly(v, 0xF);
+}
+
 // Plain transform apply Y = H X (MODE_PLAIN segments), H = D_Z + W D_X W:
 // phase 0: R = W_lo X (contiguous tiles); phase 1: R = W_hi D_X W_hi R
 // (strided tiles); phase 2: R = D_Z X + W_lo R (contiguous tiles).
-template <typename T, int PHASE>
+// Strided passes come in two instantiations: DEEP for operators of more than
+// kXzShallowMaxBits bits (more than 8 high bits), the other for the rest;
+// each leaves the other's segments alone.
+template <typename T, int PHASE, bool DEEP>
 __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ segs, int nseg) {
   using V = typename PanelT<T>::V;
   __shared__ V lds[1 << kXzTileBits];
-  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x);
+  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x, DEEP);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const uint64_t pstride = (uint64_t)1 << sg.nbits;
   const V* ub = (const V*)sg.Q + (uint64_t)t.panel0 * pstride;
@@ -680,30 +756,26 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
       stg_stream<PHASE != 0>(rb, t.row0 + xz_tau(0, l, q), PHASE == 0 ? v[q] : d[q] * u[q] + v[q]);
   } else {
     // strided tile: tau = hi * Lr + lr  ->  row = hi * 4096 + rt * Lr + lr,
-    // hb = N - 12 high bits (4 <= hb <= 8), Lr = 2^(12 - hb) >= 16
+    // hb = N - 12 high bits (4 <= hb <= 8 shallow, 9 <= hb <= 12 DEEP;
+    // operators go up to kXzMaxBits), Lr = 2^(12 - hb) >= 1
+    if ((sg.nbits > kXzShallowMaxBits) != DEEP) return;
     const int hb = sg.nbits - kXzTileBits;
     const int lrb = kXzTileBits - hb;
     const uint32_t lrm = (1u << lrb) - 1u;
     const uint32_t base = (uint32_t)t.rtile << lrb;
-    const T* dx = (const T*)sg.dx;
     auto row_of = [&](uint32_t tau) -> uint32_t {
       return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
     };
+    auto run = [&](auto nt_tag) {
+      constexpr bool NT = decltype(nt_tag)::value;
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt((const V*)rb, row_of(xz_tau(0, l, q)));
-    // tau bits lrb..11 are the row's high bits: 8..11 in arrangement 0, the
-    // part of 4..7 at or above lrb in arrangement 2
-    const int m2 = 0xF & ~((1 << (lrb > 4 ? lrb - 4 : 0)) - 1);
-    xz_bfly(v, 0xF);
-    xz_rearrange(v, lds, 0, 2);
-    xz_bfly(v, m2);
+      for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_sel<NT>((const V*)rb, row_of(xz_tau(0, l, q)));
+      xz_high_transform<DEEP>(v, lds, (const T*)sg.dx, t.rtile, lrb, row_of);
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dx, row_of(xz_tau(2, l, q))) * v[q];
-    xz_bfly(v, m2);
-    xz_rearrange(v, lds, 2, 0);
-    xz_bfly(v, 0xF);
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(rb, row_of(xz_tau(0, l, q)), v[q]);
+      for (int q = 0; q < kXzRegs; ++q) stg_sel<NT>(rb, row_of(xz_tau(0, l, q)), v[q]);
+    };
+    if (!DEEP || lrb >= 3) run(std::true_type{});
+    else run(std::false_type{});
   }
 }
 
@@ -726,17 +798,18 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
 //     partial <u_j, r_j> = s sum d u^2 + <u~_j, w> / L
 // boff offsets blockIdx.x in the segments' transform tile numbering.
 // ---------------------------------------------------------------------------
-template <typename T, int PASS, bool REGEN>
+template <typename T, int PASS, bool REGEN, bool DEEP>
 __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ segs, int nseg, int boff) {
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
   __shared__ V lds[1 << kXzTileBits];
   __shared__ double red[4 * W];
-  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x + boff);
+  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x + boff, PASS == 1 && DEEP);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
-  // pass 1 comes in two variants (the regeneration pass needs more
-  // registers); each leaves the other mode's tiles alone
-  if (PASS == 1 && (sg.mode == MODE_REGEN) != REGEN) return;
+  // pass 1 comes in variants (the regeneration pass needs more registers;
+  // DEEP for operators above kXzShallowMaxBits bits); each leaves the
+  // other variants' tiles alone
+  if (PASS == 1 && ((sg.mode == MODE_REGEN) != REGEN || (sg.nbits > kXzShallowMaxBits) != DEEP)) return;
   const int j = PASS == 0 ? 1 : sg.stepc[0];
   if (j > sg.k) return;
   const int cp = sg.cpad;
@@ -764,7 +837,8 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
 
   if (PASS == 1) {
     // strided tile: tau = hi * Lr + lr  ->  row = hi * 4096 + rt * Lr + lr,
-    // hb = N - 12 high bits (4 <= hb <= 8), Lr = 2^(12 - hb) >= 16
+    // hb = N - 12 high bits (4 <= hb <= 8 shallow, 9 <= hb <= 12 DEEP;
+    // operators go up to kXzMaxBits), Lr = 2^(12 - hb) >= 1
     const int hb = sg.nbits - kXzTileBits;
     const int lrb = kXzTileBits - hb;
     const uint32_t lrm = (1u << lrb) - 1u;
@@ -772,71 +846,65 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
     auto row_of = [&](uint32_t tau) -> uint32_t {
       return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
     };
-    V* ucur = (V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
-    V acur;
+    auto run = [&](auto nt_tag) {
+      constexpr bool NT = decltype(nt_tag)::value;
+      V* ucur = (V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
+      V acur;
 #pragma unroll
-    for (int e = 0; e < W; ++e) acur[e] = (T)st[ST_ACUR * cp + t.panel0 * W + e];
+      for (int e = 0; e < W; ++e) acur[e] = (T)st[ST_ACUR * cp + t.panel0 * W + e];
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt((const V*)rb, row_of(xz_tau(0, l, q)));
-    if (uprev) {
-#pragma unroll
-      for (int q = 0; q < kXzRegs; ++q) {
-        const V up = ldg_nt(uprev, row_of(xz_tau(0, l, q)));
-#pragma unroll
-        for (int e = 0; e < W; ++e) v[q][e] = fma_s(-acur[e], up[e], v[q][e]);
-      }
-    }
-    double dsum[W];
-#pragma unroll
-    for (int e = 0; e < W; ++e) dsum[e] = 0.0;
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) {
-      stg(ucur, row_of(xz_tau(0, l, q)), v[q]);
-#pragma unroll
-      for (int e = 0; e < W; ++e) dsum[e] += (double)v[q][e] * (double)v[q][e];
-    }
-    if (REGEN) {
-      const CONST_AS T* yt = (const CONST_AS T*)sg.ytab;
-      for (int b = 0; b < sg.n_beta; ++b) {
-        V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + (uint64_t)t.panel0 * pstride;
-        V y;
-#pragma unroll
-        for (int e = 0; e < W; ++e) y[e] = yt[((uint64_t)b * sg.k + (j - 1)) * cp + t.panel0 * W + e];
+      for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_sel<NT>((const V*)rb, row_of(xz_tau(0, l, q)));
+      if (uprev) {
 #pragma unroll
         for (int q = 0; q < kXzRegs; ++q) {
-          const uint32_t row = row_of(xz_tau(0, l, q));
-          V old;
-          if (j == 1) {
+          const V up = ldg_sel<NT>(uprev, row_of(xz_tau(0, l, q)));
 #pragma unroll
-            for (int e = 0; e < W; ++e) old[e] = T(0);
-          } else {
-            old = ldg((const V*)pb, row);
-          }
-          V nw;
-#pragma unroll
-          for (int e = 0; e < W; ++e) nw[e] = fma_s(y[e], v[q][e], old[e]);
-          stg(pb, row, nw);
+          for (int e = 0; e < W; ++e) v[q][e] = fma_s(-acur[e], up[e], v[q][e]);
         }
       }
-    }
-    double tot;
-    block_sum<W>(dsum, red, &tot);
-    if (threadIdx.x < W)
-      sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot * (double)inv_l;
-    // tau bits lrb..11 are the row's high bits: 8..11 in arrangement 0, the
-    // part of 4..7 at or above lrb in arrangement 2
-    const T* dx = (const T*)sg.dx;
-    const int m2 = 0xF & ~((1 << (lrb > 4 ? lrb - 4 : 0)) - 1);
-    xz_bfly(v, 0xF);
-    xz_rearrange(v, lds, 0, 2);
-    xz_bfly(v, m2);
+      double dsum[W];
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dx, row_of(xz_tau(2, l, q))) * v[q];
-    xz_bfly(v, m2);
-    xz_rearrange(v, lds, 2, 0);
-    xz_bfly(v, 0xF);
+      for (int e = 0; e < W; ++e) dsum[e] = 0.0;
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(rb, row_of(xz_tau(0, l, q)), v[q]);
+      for (int q = 0; q < kXzRegs; ++q) {
+        stg(ucur, row_of(xz_tau(0, l, q)), v[q]);
+#pragma unroll
+        for (int e = 0; e < W; ++e) dsum[e] += (double)v[q][e] * (double)v[q][e];
+      }
+      if (REGEN) {
+        const CONST_AS T* yt = (const CONST_AS T*)sg.ytab;
+        for (int b = 0; b < sg.n_beta; ++b) {
+          V* pb = (V*)sg.psi + (uint64_t)b * (sg.blk / W) + (uint64_t)t.panel0 * pstride;
+          V y;
+#pragma unroll
+          for (int e = 0; e < W; ++e) y[e] = yt[((uint64_t)b * sg.k + (j - 1)) * cp + t.panel0 * W + e];
+#pragma unroll
+          for (int q = 0; q < kXzRegs; ++q) {
+            const uint32_t row = row_of(xz_tau(0, l, q));
+            V old;
+            if (j == 1) {
+#pragma unroll
+              for (int e = 0; e < W; ++e) old[e] = T(0);
+            } else {
+              old = ldg((const V*)pb, row);
+            }
+            V nw;
+#pragma unroll
+            for (int e = 0; e < W; ++e) nw[e] = fma_s(y[e], v[q][e], old[e]);
+            stg(pb, row, nw);
+          }
+        }
+      }
+      double tot;
+      block_sum<W>(dsum, red, &tot);
+      if (threadIdx.x < W)
+        sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot * (double)inv_l;
+      xz_high_transform<DEEP>(v, lds, (const T*)sg.dx, t.rtile, lrb, row_of);
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q) stg_sel<NT>(rb, row_of(xz_tau(0, l, q)), v[q]);
+    };
+    if (!DEEP || lrb >= 3) run(std::true_type{});
+    else run(std::false_type{});
     return;
   }
 
@@ -1445,10 +1513,11 @@ __global__ __launch_bounds__(kBlock) void k_start_block(int ns_log, int nb, int 
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st) {
+hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st, bool xz_tiled) {
   const uint32_t dim = 1u << nbits;
+  if (xz_tiled && (nbits <= kXzShallowMaxBits || nbits > kXzMaxBits)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_diag<T>, dim3((dim + kBlock - 1) / kBlock), dim3(kBlock), 0, st, terms, nt,
-                     diag, dim);
+                     diag, dim, xz_tiled ? 2 * kXzTileBits - nbits : -1);
   return hipGetLastError();
 }
 
@@ -1475,24 +1544,28 @@ hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStre
 }
 
 template <typename T>
-hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st) {
+hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st, bool deep) {
   if (ntiles <= 0) return hipSuccess;
-  switch (pass) {
-    case 0: hipLaunchKernelGGL((k_apply_xz<T, 0>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
-    case 1: hipLaunchKernelGGL((k_apply_xz<T, 1>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
-    default: hipLaunchKernelGGL((k_apply_xz<T, 2>), dim3(ntiles), dim3(kBlock), 0, st, segs, nseg); break;
-  }
+  const dim3 g(ntiles), b(kBlock);
+  if (pass == 0) hipLaunchKernelGGL((k_apply_xz<T, 0, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 1 && deep) hipLaunchKernelGGL((k_apply_xz<T, 1, true>), g, b, 0, st, segs, nseg);
+  else if (pass == 1) hipLaunchKernelGGL((k_apply_xz<T, 1, false>), g, b, 0, st, segs, nseg);
+  else hipLaunchKernelGGL((k_apply_xz<T, 2, false>), g, b, 0, st, segs, nseg);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff, hipStream_t st) {
+hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff, hipStream_t st,
+                             bool deep) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b(kBlock);
-  if (pass == 0) hipLaunchKernelGGL((k_xz_lanczos<T, 0, false>), g, b, 0, st, segs, nseg, boff);
-  else if (pass == 1 && regen) hipLaunchKernelGGL((k_xz_lanczos<T, 1, true>), g, b, 0, st, segs, nseg, boff);
-  else if (pass == 1) hipLaunchKernelGGL((k_xz_lanczos<T, 1, false>), g, b, 0, st, segs, nseg, boff);
-  else hipLaunchKernelGGL((k_xz_lanczos<T, 2, false>), g, b, 0, st, segs, nseg, boff);
+  if (pass == 0) hipLaunchKernelGGL((k_xz_lanczos<T, 0, false, false>), g, b, 0, st, segs, nseg, boff);
+  else if (pass == 1 && regen && deep)
+    hipLaunchKernelGGL((k_xz_lanczos<T, 1, true, true>), g, b, 0, st, segs, nseg, boff);
+  else if (pass == 1 && regen) hipLaunchKernelGGL((k_xz_lanczos<T, 1, true, false>), g, b, 0, st, segs, nseg, boff);
+  else if (pass == 1 && deep) hipLaunchKernelGGL((k_xz_lanczos<T, 1, false, true>), g, b, 0, st, segs, nseg, boff);
+  else if (pass == 1) hipLaunchKernelGGL((k_xz_lanczos<T, 1, false, false>), g, b, 0, st, segs, nseg, boff);
+  else hipLaunchKernelGGL((k_xz_lanczos<T, 2, false, false>), g, b, 0, st, segs, nseg, boff);
   return hipGetLastError();
 }
 
@@ -1585,20 +1658,20 @@ hipError_t launch_start_block(int ns_log, int nb, int C, uint64_t seed, int kind
   return hipGetLastError();
 }
 
-template hipError_t launch_diag<float>(const DiagTerm*, int, float*, int, hipStream_t);
-template hipError_t launch_diag<double>(const DiagTerm*, int, double*, int, hipStream_t);
+template hipError_t launch_diag<float>(const DiagTerm*, int, float*, int, hipStream_t, bool);
+template hipError_t launch_diag<double>(const DiagTerm*, int, double*, int, hipStream_t, bool);
 template hipError_t launch_norm<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_norm<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
-template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t);
+template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t, bool);
 template hipError_t launch_block_update<float>(const BSeg*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_ground_ptrace<float>(const GPSeg*, int, int, hipStream_t);
 template hipError_t launch_ground_ptrace<double>(const GPSeg*, int, int, hipStream_t);
 template hipError_t launch_block_update<double>(const BSeg*, int, int, int, int, int, hipStream_t);
-template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t);
-template hipError_t launch_xz_lanczos<float>(int, bool, const Seg*, int, int, int, hipStream_t);
-template hipError_t launch_xz_lanczos<double>(int, bool, const Seg*, int, int, int, hipStream_t);
+template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t, bool);
+template hipError_t launch_xz_lanczos<float>(int, bool, const Seg*, int, int, int, hipStream_t, bool);
+template hipError_t launch_xz_lanczos<double>(int, bool, const Seg*, int, int, int, hipStream_t, bool);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);

@@ -356,7 +356,7 @@ Launch assign_tiles(std::vector<Seg>& segs) {
     sg.x_base = L.xz;
     if (sg.xz) {
       L.xz += sg.x_tiles * sg.P;
-      (sg.mode == MODE_REGEN ? L.xz_regen : L.xz_lanczos) = true;
+      (sg.mode == MODE_REGEN ? L.xz_regen : L.xz_lanczos)[sg.nbits > kXzShallowMaxBits] = true;
     }
   }
   return L;
@@ -377,11 +377,12 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
   RDM_HIP(d ? launch_norm<double>(dsegs, nseg, L.norm, slab, st) : launch_norm<float>(dsegs, nseg, L.norm, slab, st));
   if (tm) RDM_HIP(tm->norm.mark(st));
   if (tm) RDM_HIP(tm->xz1.mark(st));
-  for (int regen = 0; regen < 2; ++regen) {
-    if (!(regen ? L.xz_regen : L.xz_lanczos)) continue;
-    RDM_HIP(d ? launch_xz_lanczos<double>(1, regen, dsegs, nseg, L.xz, 0, st)
-              : launch_xz_lanczos<float>(1, regen, dsegs, nseg, L.xz, 0, st));
-  }
+  for (int regen = 0; regen < 2; ++regen)
+    for (int deep = 0; deep < 2; ++deep) {
+      if (!(regen ? L.xz_regen : L.xz_lanczos)[deep]) continue;
+      RDM_HIP(d ? launch_xz_lanczos<double>(1, regen, dsegs, nseg, L.xz, 0, st, deep)
+                : launch_xz_lanczos<float>(1, regen, dsegs, nseg, L.xz, 0, st, deep));
+    }
   if (tm) RDM_HIP(tm->xz1.mark(st));
   RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
   if (tm) RDM_HIP(tm->apply.mark(st));

@@ -100,7 +100,9 @@ void bind_apply(Seg& s, const OpDevice* op);
 // workgroups of the norm launch and of the two kinds of apply launch
 struct Launch {
   int norm = 0, apply = 0, xz = 0;
-  bool xz_lanczos = false, xz_regen = false;  // transform segments in each mode
+  // transform segments in each mode, shallow [0] and deep [1] (more than
+  // kXzShallowMaxBits bits)
+  bool xz_lanczos[2] = {false, false}, xz_regen[2] = {false, false};
 };
 // sets every segment's tile_base / ap_base / x_base
 Launch assign_tiles(std::vector<Seg>& segs);

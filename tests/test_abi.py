@@ -56,7 +56,7 @@ def test_hamiltonian_tables():
 
 
 def test_transform_apply_selection():
-    # operators whose hops are all X-type (J^y = 0) on 16..20 bits are applied
+    # operators whose hops are all X-type (J^y = 0) on 16..22 bits are applied
     # as D_Z + W D_X W; anything with a YY part, or outside that size range,
     # keeps the hop tables
     full = rdm.Hamiltonian.from_instance(cfg_long_range(0)).info()      # 2 + 18
@@ -66,7 +66,11 @@ def test_transform_apply_selection():
     mid = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=15)).info()   # 2 + 15: bath 15 bits
     assert mid["transform"] == 1 and mid["bath_transform"] == 0
     big = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=20)).info()   # 22 bits
-    assert big["transform"] == 0
+    assert big["transform"] == 1 and big["bath_transform"] == 1
+    over = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=21)).info()  # 23 bits, bath 21
+    assert over["transform"] == 0 and over["bath_transform"] == 1
+    over = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=23)).info()  # 25 bits, bath 23
+    assert over["transform"] == 0 and over["bath_transform"] == 0
     xxz = rdm.Hamiltonian.from_instance(long_range_xxz(2, 16, 1)).info()   # J^x = J^y
     assert xxz["transform"] == 0 and xxz["bath_transform"] == 0
 
