@@ -433,6 +433,20 @@ def test_two_pass_is_bitwise_stored(prec, name):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["tfim_1+21", "lr_1+20"])
+def test_two_pass_is_bitwise_stored_beyond_20_bits(prec, name):
+    # the regeneration pass of the deep strided variant (21 and 22 bits)
+    inst = DEEP_CASES[name]()
+    h = H(inst)
+    assert h.info()["transform"] == 1
+    a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision=prec, mode="stored")
+    b = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision=prec, mode="two_pass")
+    assert not a["two_pass"] and b["two_pass"]
+    for key in ("rho", "h_star", "log_z", "entropy"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_graph_replay_equals_eager(prec):
     # the default path replays the captured Lanczos steps as one hipGraph;
     # several replays, with eager solves and other device work in between,
@@ -596,6 +610,17 @@ def test_transform_beyond_20_bits_matches_hop_tables(name):
     check_result(a, want, 1e-10, "transform vs hop tables " + name)
     m = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed")
     check_result(m, want, 1e-5, "mixed transform vs FP64 hop tables " + name)
+
+
+@pytest.mark.parametrize("name", ["tfim_1+21", "lr_1+20"])
+def test_block_beyond_20_bits_matches_hop_tables(name):
+    # the block variant's plain transform passes with the deep strided kernel
+    inst = DEEP_CASES[name]()
+    h, hh = H(inst), H(_with_hop_tables(inst))
+    a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    want = [{key: b[key][t] for key in ("rho", "h_star", "log_z", "entropy")} for t in range(len(inst.betas))]
+    check_result(a, want, 1e-10, "block: transform vs hop tables " + name)
 
 
 def test_serving_alone_equals_in_mix_large_requests():
