@@ -514,19 +514,25 @@ def main():
         t0 = time.perf_counter()
         if concurrent:
             lats = [[] for _ in insts]
+            errors = []
 
             def worker(t):
-                with torch.cuda.stream(streams[t]):
-                    for _ in range(steps):
-                        t1 = time.perf_counter()
-                        res[t] = solve_one(t, streams[t])
-                        lats[t].append(time.perf_counter() - t1)
+                try:
+                    with torch.cuda.stream(streams[t]):
+                        for _ in range(steps):
+                            t1 = time.perf_counter()
+                            res[t] = solve_one(t, streams[t])
+                            lats[t].append(time.perf_counter() - t1)
+                except BaseException as e:  # re-raised below, in the main thread
+                    errors.append(e)
 
             th = [threading.Thread(target=worker, args=(t,)) for t in range(len(insts))]
             for x in th:
                 x.start()
             for x in th:
                 x.join()
+            if errors:
+                raise errors[0]
             lat = [v for l_ in lats for v in l_]
         else:
             for _ in range(steps):
