@@ -420,6 +420,34 @@ def test_solve_outputs_are_density_matrices():
             assert np.linalg.eigvalsh(rho).min() > -tol
 
 
+def test_full_size_solve_properties():
+    # the bench's workload (2 + 18 spins, 64 columns, k = 60, four
+    # temperatures) in its launch configuration: no oracle answer exists at
+    # this size, so properties that hold at any size -- density matrices, the
+    # mixed path within its bar of FP64, the block quadrature and k + 20 steps
+    # agreeing with the converged per-column result, S from the spectrum of rho*
+    inst = cfg_long_range(0)
+    h = H(inst)
+    d64 = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    mix = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="stored")
+    for r, tol in ((d64, 1e-13), (mix, 1e-6)):
+        for b in range(len(inst.betas)):
+            rho = r["rho"][b]
+            assert np.abs(rho - rho.T).max() < tol
+            assert abs(np.trace(rho) - 1) < tol
+            p = np.linalg.eigvalsh(rho)
+            assert p.min() > -tol
+            p = p[p > 0]
+            assert abs(r["entropy"][b] + (p * np.log(p)).sum()) < 10 * tol
+            assert np.abs(r["h_star"][b] - r["h_star"][b].T).max() < 1e3 * tol
+    want = [{key: d64[key][b] for key in ("rho", "h_star", "log_z", "entropy")} for b in range(len(inst.betas))]
+    check_result(mix, want, 1e-5, "full size: mixed vs FP64")
+    blk = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    check_result(blk, want, 1e-5, "full size: block vs per-column")
+    longer = rdm.solve(h, inst.betas, inst.n_v, inst.k + 20, inst.seed, precision="fp64")
+    check_result(longer, want, 1e-9, "full size: k + 20 vs k")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["lr_2+9", "xz_2+14"])
 def test_two_pass_is_bitwise_stored(prec, name):
