@@ -589,6 +589,49 @@ def test_xx_chain_against_closed_form():
     assert abs(got["log_z"][0] - cf["log_z"]) < 0.05
 
 
+def _library_estimates(inst, seeds, n_v):
+    # M(beta) = tr M * rho* from the library's outputs, rescaled to the shift
+    # lambda_min of the exact spectrum: tr M = exp(ln Z_t + beta E0 - ln d_b)
+    h = H(inst)
+    items = [dict(h=h, betas=inst.betas, n_v=n_v, k=inst.k, seed=s) for s in seeds]
+    out = rdm.solve_batch(items, precision="fp64")
+    ev = np.linalg.eigvalsh(spin.dense_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz))
+    beta = inst.betas[0]
+    ms = []
+    for r in out:
+        assert r["status"] == 0
+        ms.append(r["rho"][0] * np.exp(r["log_z_t"][0] + beta * ev[0] - inst.n_b * np.log(2.0)))
+    return np.array(ms), ev[0]
+
+
+def test_estimator_error_on_the_gpu_matches_exact_variance():
+    # Section "Trace estimators": over 200 seeds the library's estimate of
+    # tr_b exp(-beta (H - E)) / d_b has the per-entry variance of the exact
+    # Rademacher formula (O6) divided by n_v, no bias beyond 5 standard
+    # errors, and every run within 5 sigma; its error shrinks as n_v^-1/2
+    from oracle import variance
+    inst = cfg_small_chain()
+    beta = inst.betas[0]
+    dense = spin.dense_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    e, u = np.linalg.eigh(dense)
+    a = (u * np.exp(-beta * (e - e[0]))) @ u.T
+    target = exact.partial_trace_bath(a, inst.d_s, inst.d_b) / inst.d_b
+    var = variance.entry_variance(a, inst.d_s, inst.d_b)
+    ms, _ = _library_estimates(inst, range(200), inst.n_v)
+    errs = ms - target
+    ratio = (errs ** 2).mean(axis=0) / (var / inst.n_v)
+    assert np.all((ratio > 0.75) & (ratio < 1.3)), ratio
+    assert np.all(np.abs(errs.mean(axis=0)) < 5 * np.sqrt(var / inst.n_v / 200))
+    assert np.all(np.abs(errs) <= 5 * np.sqrt(var / inst.n_v))
+    nvs = [4, 16, 64, 256]
+    rms = []
+    for n_v in nvs:
+        ms, _ = _library_estimates(inst, range(100, 160), n_v)
+        rms.append(np.sqrt(np.mean([np.linalg.norm(m - target) ** 2 for m in ms])))
+    slope = np.polyfit(np.log(nvs), np.log(rms), 1)[0]
+    assert abs(slope + 0.5) < 0.06, slope
+
+
 def test_serving_alone_equals_in_mix():
     insts = [tfim_request(r, n_range=(10, 16)) for r in range(6)]
     hs = [H(i) for i in insts]
