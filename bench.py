@@ -98,6 +98,56 @@ def _oracle_worker(h_index, n_b, column, steps):
         return time.perf_counter() - t0
 
 
+def _make_instance(kind, arg):
+    from workloads import cfg_large, random_sparse_xxz, tfim_request
+    if kind == "batch":
+        return random_sparse_xxz(arg)
+    if kind == "serve":
+        return tfim_request(arg)
+    return cfg_large()
+
+
+def _oracle_step_worker(kind, arg, n_rows):
+    """One host process: the oracle's FP64 work on one start column of the
+    named instance.  n_rows = 0: one Lanczos step (apply, recurrence, dots);
+    returns its seconds.  n_rows > 0 (instances whose full apply takes many
+    minutes): the oracle's apply restricted to n_rows random rows; returns
+    its seconds scaled to all rows."""
+    from threadpoolctl import threadpool_limits
+    from oracle import exact, lanczos as olz, spin
+    inst = _make_instance(kind, arg)
+    op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    with threadpool_limits(limits=1):
+        if n_rows == 0:
+            x0 = exact.start_columns(inst)[:, 0]
+            t0 = time.perf_counter()
+            olz.lanczos(op.apply, x0, 1, keep_q=False)
+            return time.perf_counter() - t0
+        rng = np.random.default_rng(arg)
+        x = rng.standard_normal(inst.dim)
+        rows = rng.integers(0, inst.dim, n_rows)
+        t0 = time.perf_counter()
+        op.rows(rows, x)
+        return (time.perf_counter() - t0) * inst.dim / n_rows
+
+
+def cpu_baseline_sample(kind, args_list, n_rows=0):
+    """Oracle seconds per column step for each listed instance, one host
+    process each (at most 16 at a time, BLAS one thread per process)."""
+    import multiprocessing as mp
+    nproc = max(1, min(16, os.cpu_count() or 1, len(args_list)))
+    ctx = mp.get_context("spawn")  # fresh interpreters: the parent holds a GPU context
+    with ctx.Pool(nproc) as pool:
+        return nproc, pool.starmap(_oracle_step_worker, [(kind, a, n_rows) for a in args_list])
+
+
+def _solve_seconds(inst, t_col_step, applies_per_step=1):
+    """A whole solve from one column step: every column (bath columns count
+    by their size) for k steps."""
+    cols = inst.n_cols + inst.n_v * (inst.d_b / inst.dim)
+    return inst.k * cols * t_col_step * applies_per_step
+
+
 def cpu_baseline(inst, h_index, n_b, steps=2):
     """The oracle's FP64 Lanczos path (as it stands), parallel over start
     columns with one process per host core (at most 16), on a bounded sample:
@@ -199,7 +249,17 @@ def bench_batch(args):
     # waves the event average is per launch of the wave, so report the sum
     t_step = float(np.mean([step_ms(o) for o in prof])) * 1e-3
     n = len(insts) * args.steps
-    return {"metric": "batched solves/s (64 heterogeneous instances)", "value": round(n / wall, 3),
+    cpu = None
+    if not args.no_cpu_baseline:
+        stage("oracle on the host (every fourth instance)")
+        sample = list(range(0, len(insts), 4))
+        cores, secs = cpu_baseline_sample("batch", [insts[i].seed for i in sample])
+        t_all = 4 * sum(_solve_seconds(insts[i], t) for i, t in zip(sample, secs))
+        cpu = {"value": len(insts) / t_all * cores, "unit": "solves/s", "cores": cores, "kind": "oracle",
+               "sample": f"one FP64 Lanczos step of one start column of every fourth instance "
+                         f"({len(sample)} instances, one process each), scaled to k steps x all columns "
+                         f"per instance and x4 for the other instances; throughput with one solve per core"}
+    return {"metric": "batched solves/s (64 heterogeneous instances)", "value": round(n / wall, 3), "cpu_baseline": cpu,
             "unit": "solves/s", "ms_per_step": round(1e3 * wall / args.steps, 2), "steps": args.steps,
             "warmup": args.warmup, "dtype": "f32 vectors + f64 reductions",
             "config": {"workload": "64 random sparse XXZ instances, N in [12,22], N_s in {1,2,3}, "
@@ -218,18 +278,29 @@ def bench_large(args):
     from workloads import cfg_large
     inst = cfg_large()
     h = rdm.Hamiltonian.from_instance(inst)
-    res = None
+    # a warm-up solve (device tables, workspace, the slab choice), the timed
+    # solve on the default launch path (graph replay), then, untimed, one with
+    # HIP-event timing of the kernels (launched one by one)
+    stage("large instance: warm-up solve")
+    rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="two_pass")
+    torch.cuda.synchronize()
+    stage("large instance: timed solve")
     t0 = time.perf_counter()
-    res = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="two_pass",
-                    profile=True)
+    rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="two_pass")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    stage("large instance: profiled solve")
+    res = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="two_pass",
+                    profile=True)
     by, fl = step_work([inst], 4)
     t_step = step_ms(res) * 1e-3
     # the paper's block variant keeps three blocks instead of the basis, so it
     # needs no regeneration pass: one apply per step instead of two
     block = None
     if not args.no_block:
+        stage("large instance: block variant")
+        rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", method="block")
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         rb = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", method="block")
         torch.cuda.synchronize()
@@ -238,7 +309,18 @@ def bench_large(args):
                  "rho_rel_diff_vs_two_pass": float(np.linalg.norm(rb["rho"][0] - res["rho"][0]) /
                                                    np.linalg.norm(res["rho"][0])),
                  "entropy": float(rb["entropy"][0])}
-    return {"metric": "large-instance solve time", "value": round(wall, 3), "unit": "s/solve",
+    cpu = None
+    if not args.no_cpu_baseline:
+        stage("oracle on the host (row sample of one apply)")
+        cores, secs = cpu_baseline_sample("large", list(range(16)), n_rows=1 << 16)
+        # two-pass: the regeneration pass applies H again; one column-apply per
+        # process, the solve's columns spread over the cores
+        t_solve = _solve_seconds(inst, float(np.mean(secs)), applies_per_step=2) / cores
+        cpu = {"value": t_solve, "unit": "s/solve", "cores": cores, "kind": "oracle",
+               "sample": f"the oracle's apply restricted to 65536 random rows of the 2^26-row operator, "
+                         f"{len(secs)} processes, scaled to all rows (extrapolated), then to k steps x "
+                         f"2 passes x all columns spread over {cores} cores"}
+    return {"metric": "large-instance solve time", "value": round(wall, 3), "unit": "s/solve", "cpu_baseline": cpu,
             "higher_is_better": False, "dtype": "f32 vectors + f64 reductions",
             "config": {"workload": "long-range XXZ 3+23 spins (dim 2^26), alpha=1.2, Delta=0.8, "
                                    "x-field 1.0, beta=2, n_v=4 (32 columns), k=80, two-pass"},
@@ -339,7 +421,17 @@ def bench_serve(args):
         for h in keep:
             h.close()
     pct = lambda lat, q: round(1e3 * float(np.percentile(lat, q)), 2)  # noqa: E731
-    return {"metric": "serving: solves/s and p50/p99 latency", "value": round(rate_a, 3),
+    cpu = None
+    if not args.no_cpu_baseline:
+        stage("oracle on the host (16 requests)")
+        from workloads import tfim_request
+        cores, secs = cpu_baseline_sample("serve", list(range(16)))
+        t_mean = float(np.mean([_solve_seconds(tfim_request(r), t) for r, t in zip(range(16), secs)]))
+        cpu = {"value": cores / t_mean, "unit": "solves/s", "cores": cores, "kind": "oracle",
+               "sample": "one FP64 Lanczos step of one start column of each of the first 16 requests "
+                         "(one process each), scaled to k steps x all columns; capacity with one "
+                         "request per core"}
+    return {"metric": "serving: solves/s and p50/p99 latency", "value": round(rate_a, 3), "cpu_baseline": cpu,
             "unit": "solves/s", "dtype": "f32 vectors + f64 reductions",
             "config": {"workload": f"Poisson arrivals {args.rate}/s of transverse-field ZZ-chain "
                                    "requests, N in [14,24], d_s in {2,4}, beta log-U[0.1,10], n_v=8, k=60",
