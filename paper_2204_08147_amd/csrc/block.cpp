@@ -133,12 +133,17 @@ rdm_status run_block(const BlockPlan& bp, const OpDevice* op_t, char* ws, char* 
   // Q_1: the start block |m> (x) |v_j> (exactly orthonormal per group)
   RDM_HIP(launch_start_block<T>(bp.ds_log, bp.h->n_b, bp.C, seed, START_SYSBATH, (T*)ap[0].Q, bp.h->n, bp.cpad,
                                 st));
+  // transform operators: the blocks live in the orthogonal basis W_lo Q / 64
+  // (inner products unchanged, so A_j, B_j and the quadrature are too), and
+  // each product H Q_j takes two streaming passes instead of three
+  const bool deep = bp.h->n > kXzShallowMaxBits;
+  if (op_t->xz) RDM_HIP(launch_xz_pass<T>(3, dsegs, 1, L.xz, st, deep));
   for (int j = 1; j <= bp.k; ++j) {
     const Seg* sj = dsegs + (j - 1) % 3;
     if (tm) RDM_HIP(tm->apply.mark(st));
     RDM_HIP(launch_apply<T>(sj, 1, L.apply, 1, st));
-    for (int pass = 0; pass <= 2; ++pass)
-      RDM_HIP(launch_xz_pass<T>(pass, sj, 1, L.xz, st, bp.h->n > kXzShallowMaxBits));
+    if (op_t->xz)
+      for (int pass = 4; pass <= 5; ++pass) RDM_HIP(launch_xz_pass<T>(pass, sj, 1, L.xz, st, deep));
     if (tm) RDM_HIP(tm->apply.mark(st));
     if (tm) RDM_HIP(tm->norm.mark(st));
     RDM_HIP(launch_block_update<T>(dbs, bp.ds, BLK_A, j, bp.n_rt, bp.n_cb, st));

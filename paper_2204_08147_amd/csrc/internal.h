@@ -186,8 +186,10 @@ hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStrea
 template <typename T>
 hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 // pass 0, 1 or 2 of the plain transform apply Y = H X (MODE_PLAIN segments
-// with xz = 1); pass 1 on the segments of more than kXzShallowMaxBits bits
-// if deep, else on the others
+// with xz = 1); passes 3 (once: X^ = W_lo X / 64 in place), 4 and 5 the same
+// product on blocks kept as X^, giving R = W_lo H X / 64; the strided pass
+// (1 or 4) on the segments of more than kXzShallowMaxBits bits if deep, else
+// on the others
 template <typename T>
 hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st, bool deep = false);
 // Lanczos step over the segments with xz = 1, basis kept in the low-bit

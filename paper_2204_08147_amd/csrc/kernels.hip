@@ -719,6 +719,11 @@ __device__ __forceinline__ void xz_high_transform(V (&v)[kXzRegs], V* lds, const
 // Plain transform apply Y = H X (MODE_PLAIN segments), H = D_Z + W D_X W:
 // phase 0: R = W_lo X (contiguous tiles); phase 1: R = W_hi D_X W_hi R
 // (strided tiles); phase 2: R = D_Z X + W_lo R (contiguous tiles).
+// The same product on blocks kept in the orthogonal basis X^ = W_lo X / 64
+// (W_lo W_lo = L I, L = 4096; the block Lanczos keeps its blocks there):
+// phase 3: X^ = W_lo X / 64 in place (contiguous, once per run); phase 4:
+// R = L W_hi D_X W_hi X^ (strided); phase 5: R = W_lo D_Z W_lo X^ / L + R
+// (contiguous), so that R = (W_lo / 64) H X: two passes per product.
 // Strided passes come in two instantiations: DEEP for operators of more than
 // kXzShallowMaxBits bits (more than 8 high bits), the other for the rest;
 // each leaves the other's segments alone.
@@ -734,7 +739,34 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
   const uint32_t l = threadIdx.x;
   V v[kXzRegs];
 
-  if (PHASE == 0 || PHASE == 2) {
+  if (PHASE == 3) {
+    // contiguous tile, in place on X
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(ub, t.row0 + xz_tau(0, l, q));
+    xz_low_transform(v, lds);
+    const T sc = T(1) / T(1 << (kXzTileBits / 2));
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg((V*)ub, t.row0 + xz_tau(0, l, q), sc * v[q]);
+  } else if (PHASE == 5) {
+    // contiguous tile: the diagonal term in the transformed basis
+    const T* dg = (const T*)sg.diag;
+    V w[kXzRegs];
+    T d[kXzRegs];
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const uint32_t row = t.row0 + xz_tau(0, l, q);
+      v[q] = ldg_nt(ub, row);
+      w[q] = ldg_nt((const V*)rb, row);
+      d[q] = ldg_s(dg, row);
+    }
+    xz_low_transform(v, lds);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = d[q] * v[q];
+    xz_low_transform(v, lds);
+    const T inv_l = T(1) / T(1 << kXzTileBits);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(rb, t.row0 + xz_tau(0, l, q), inv_l * v[q] + w[q]);
+  } else if (PHASE == 0 || PHASE == 2) {
     // contiguous tile: row = row0 + tau; arrangement 0 loads and stores coalesced
     const V* src = PHASE == 0 ? ub : (const V*)rb;
 #pragma unroll
@@ -766,11 +798,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     auto row_of = [&](uint32_t tau) -> uint32_t {
       return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
     };
+    // phase 1 transforms R in place; phase 4 reads X^ and scales by L
+    const V* src = PHASE == 4 ? ub : (const V*)rb;
     auto run = [&](auto nt_tag) {
       constexpr bool NT = decltype(nt_tag)::value;
 #pragma unroll
-      for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_sel<NT>((const V*)rb, row_of(xz_tau(0, l, q)));
+      for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_sel<NT>(src, row_of(xz_tau(0, l, q)));
       xz_high_transform<DEEP>(v, lds, (const T*)sg.dx, t.rtile, lrb, row_of);
+      if (PHASE == 4) {
+#pragma unroll
+        for (int q = 0; q < kXzRegs; ++q) v[q] = T(1 << kXzTileBits) * v[q];
+      }
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q) stg_sel<NT>(rb, row_of(xz_tau(0, l, q)), v[q]);
     };
@@ -1550,7 +1588,11 @@ hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipSt
   if (pass == 0) hipLaunchKernelGGL((k_apply_xz<T, 0, false>), g, b, 0, st, segs, nseg);
   else if (pass == 1 && deep) hipLaunchKernelGGL((k_apply_xz<T, 1, true>), g, b, 0, st, segs, nseg);
   else if (pass == 1) hipLaunchKernelGGL((k_apply_xz<T, 1, false>), g, b, 0, st, segs, nseg);
-  else hipLaunchKernelGGL((k_apply_xz<T, 2, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 2) hipLaunchKernelGGL((k_apply_xz<T, 2, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 3) hipLaunchKernelGGL((k_apply_xz<T, 3, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 4 && deep) hipLaunchKernelGGL((k_apply_xz<T, 4, true>), g, b, 0, st, segs, nseg);
+  else if (pass == 4) hipLaunchKernelGGL((k_apply_xz<T, 4, false>), g, b, 0, st, segs, nseg);
+  else hipLaunchKernelGGL((k_apply_xz<T, 5, false>), g, b, 0, st, segs, nseg);
   return hipGetLastError();
 }
 
