@@ -148,13 +148,14 @@ def _cfg_large():
 
 
 @pytest.mark.parametrize("make,cols", [(lambda: cfg_long_range(2), 64), (lambda: tfim_request(3, n_range=(24, 24)), 32),
+                                       (lambda: tfim_request(4, n_range=(21, 21)), 16),
                                        (lambda: long_range_xx_zz(1, 21, 1.0, 6), 16), (_cfg_large, 32)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_apply_full_size_sampled_rows(make, cols, prec):
     # full-size shapes (dim 2^20, 2^24 and the largest, 2^26 with all-pairs
     # XXZ) in the bench's launch configuration, checked on 300 sampled rows
-    # computed one by one by the oracle; 2^22 runs the transform apply with 10
-    # high bits (and the XCD grouping of strided tiles)
+    # computed one by one by the oracle; 2^21 and 2^22 run the transform apply
+    # with 9 and 10 high bits (2^22 with the XCD grouping of strided tiles)
     inst = make()
     h = H(inst)
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
