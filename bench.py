@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Non-packed FP32 and FP64 vector FMA issue at the same rate on gfx950:
 # 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.  (The 157.3
-# TFLOP/s FP32 figure needs packed FP32 FMA, which this build does not emit.)
+# TFLOP/s FP32 figure needs packed FP32 FMA, which the library is compiled without.)
 VALU_PEAK_TFLOPS = 78.6
 
 METRIC = ("ρ_s solves/s & spin-H apply GB/s, mixed vs FP64 plain; p50/p99 solve latency")
@@ -545,9 +545,9 @@ def stage(msg: str) -> None:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the path would shard bath-vector groups across GPUs, see the design notes.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU (asked for --gpus {args.gpus}): the bath-vector groups are "
+              "independent and would be sharded across GPUs with one final reduce of the d_s x d_s sums, "
+              "which is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2204_08147_amd as rdm
