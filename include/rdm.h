@@ -379,9 +379,12 @@ rdm_status rdm_server_submit(rdm_server* s, const rdm_hamiltonian* h, const doub
                              int32_t n_beta, int32_t n_v, int32_t k, uint64_t seed,
                              rdm_result out, uint64_t* ticket);
 /* done = 1 once the ticket's results are in its buffers; status = the solve's
- * status.  Non-blocking. */
+ * status.  Non-blocking.  A ticket has one owner: the poll that reports it
+ * done retires it, and a ticket retired or being waited for by
+ * rdm_server_wait gives RDM_E_INVALID. */
 rdm_status rdm_server_poll(rdm_server* s, uint64_t ticket, int32_t* done, rdm_status* status);
-/* Block until the ticket completes. */
+/* Block until the ticket completes, then retire it.  RDM_E_INVALID for an
+ * unknown or retired ticket, or one another thread already waits for. */
 rdm_status rdm_server_wait(rdm_server* s, uint64_t ticket, rdm_status* status);
 /* Counters: out[0] submitted, [1] completed, [2] active, [3] queued, [4] engine
  * steps, [5] peak active, [6] peak device bytes.  host out, 7 int64. */

@@ -3,15 +3,12 @@
 Test infrastructure only (see ``oracle/__init__``).
 
 For each start column x_c = |m> (x) |v_j> (c = j*d_s + m) this runs the
-Lanczos recurrence of Algorithm 1 with block size one (the scalar case the
-paper mentions for an empty system, Section "Algorithm"), without
-reorthogonalisation (Section "Finite precision arithmetic"):
-
-    q_1 = x / |x|,  q_0 = 0,  b_0 = 0
-    for j = 1..k:  w = H q_j - b_{j-1} q_{j-1};  a_j = q_j . w;  w -= a_j q_j
-                   if j < k:  b_j = |w|;  q_{j+1} = w / b_j
-
-and stops early (k_c = j) when b_j <= tau * max(|a_1..a_j|, b_1..b_{j-1}).
+scalar case of Algorithm 1 (block size one, Section "Algorithm"): the
+three-term Lanczos recurrence from q_1 = x / |x|, in which each new direction
+is H q_j with its components along q_j and q_(j-1) removed and normalised,
+a_j and b_j being the removed component along q_j and the norm of the rest.
+There is no reorthogonalisation (Section "Finite precision arithmetic").
+The run stops early (k_c = j) when b_j <= tau * max(|a_1..a_j|, b_1..b_{j-1}).
 T = tridiag(b, a, b) of order k_c.  A Lanczos function approximation of
 exp(-beta (H - E0)/2) x is  psi = |x| Q exp(-beta (T - E0)/2) e_1, where E0 is
 the smallest Ritz value over all columns of the solve (the overflow shift of

@@ -180,11 +180,13 @@ def solve(h: Hamiltonian, betas: Sequence[float], n_v: int, k: int, seed: int, *
 
 
 def solve_batch(items: List[dict], *, stream=None, library_alloc: bool = False,
-                reserve_bytes: int = 8 << 30, **opts) -> List[dict]:
+                reserve_bytes: int = 8 << 30, workspace=None, **opts) -> List[dict]:
     """items: dicts with keys h, betas, n_v, k, seed.  Returns per-item result
     dicts (each with a 'status' entry).  By default the workspace is a torch
     tensor sized to run every instance in one wave when device memory allows
-    (less memory means more waves, never an error)."""
+    (less memory means more waves, never an error); ``workspace`` passes a
+    caller-owned uint8 device tensor instead.  A failure of one item is
+    reported in its 'status'; a failure of the call itself raises."""
     o = make_options(**opts)
     n = len(items)
     arr = (_lib.BatchItem * max(n, 1))()
@@ -201,21 +203,34 @@ def solve_batch(items: List[dict], *, stream=None, library_alloc: bool = False,
         arr[t].seed = it["seed"]
         arr[t].out = rb.c
     st = _stream_handle(stream)
+
+    def _batch_check(status: int, where: str):
+        # the call returns the first failing item's status; any other
+        # failure belongs to the call, not to an item
+        if status != 0 and not any(int(arr[t].status) == status for t in range(n)):
+            raise RdmError(status, where)
+
     if library_alloc:
-        LIB.rdm_solve_batch(n, arr, C.byref(o), st)
+        _batch_check(LIB.rdm_solve_batch(n, arr, C.byref(o), st), "rdm_solve_batch")
     else:
         import torch
         lo, hi = C.c_uint64(), C.c_uint64()
-        LIB.rdm_batch_workspace_size(n, arr, C.byref(o), C.byref(lo), C.byref(hi))
-        if hi.value:
+        _check(LIB.rdm_batch_workspace_size(n, arr, C.byref(o), C.byref(lo), C.byref(hi)),
+               "rdm_batch_workspace_size")
+        if workspace is not None:
+            size = workspace.numel() * workspace.element_size()
+            _batch_check(LIB.rdm_solve_batch_ws(n, arr, C.byref(o), st, C.c_void_p(workspace.data_ptr()),
+                                                size), "rdm_solve_batch_ws")
+        elif hi.value:
             free, _ = torch.cuda.mem_get_info()
             cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
             size = int(max(lo.value, min(hi.value, free + cached - reserve_bytes)))
             ws = torch.empty(size, dtype=torch.uint8, device="cuda")
-            LIB.rdm_solve_batch_ws(n, arr, C.byref(o), st, C.c_void_p(ws.data_ptr()), size)
+            _batch_check(LIB.rdm_solve_batch_ws(n, arr, C.byref(o), st, C.c_void_p(ws.data_ptr()), size),
+                         "rdm_solve_batch_ws")
             del ws
         else:
-            LIB.rdm_solve_batch(n, arr, C.byref(o), st)
+            _batch_check(LIB.rdm_solve_batch(n, arr, C.byref(o), st), "rdm_solve_batch")
     out = []
     for t in range(n):
         d = keep[t][1].as_dict()

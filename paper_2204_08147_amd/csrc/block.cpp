@@ -2,9 +2,9 @@
 // eqn:trB_est): the paper's own estimator, on the same apply kernels.
 //
 // For each bath vector j the start block V_j = [|m> (x) |v_j>]_m (d_s
-// orthonormal columns) runs Algorithm 1: Z = H Q_i - Q_{i-1} B_{i-1}^T,
-// A_i = Q_i^T Z, Z -= Q_i A_i, Q_{i+1} B_i = QR(Z), with the QR as two
-// Cholesky passes (Gram in FP64).  Only three blocks of vectors are kept.
+// orthonormal columns) runs the block Lanczos recurrence of Algorithm 1,
+// whose block QR is done here as two Cholesky passes on an FP64 Gram
+// (Cholesky QR twice); only three blocks of vectors are kept.
 // The block tridiagonal T_j (A_i on the diagonal, B_i below) gives
 // E_1^T exp(-beta (T_j - E0)) E_1 directly, so there is no recombination and
 // no Gram pass; E0 is the smallest eigenvalue over all T_j.  The bath

@@ -75,6 +75,7 @@ struct Req {
   rdm_result out{};
   rdm_status status = RDM_OK;
   bool done = false;
+  bool claimed = false;  // a poll that saw it done, or a wait, owns the ticket
   InstPlan plan;
   InstRun run;
   char* mem = nullptr;
@@ -343,8 +344,8 @@ extern "C" rdm_status rdm_server_poll(rdm_server* s, uint64_t ticket, int32_t* d
   }
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) {
-    set_error("rdm_server_poll: unknown ticket");
+  if (it == s->reqs.end() || it->second->claimed) {
+    set_error("rdm_server_poll: unknown ticket, or one already retrieved or being waited for");
     return RDM_E_INVALID;
   }
   *done = it->second->done ? 1 : 0;
@@ -363,11 +364,12 @@ extern "C" rdm_status rdm_server_wait(rdm_server* s, uint64_t ticket, rdm_status
   }
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) {
-    set_error("rdm_server_wait: unknown ticket");
+  if (it == s->reqs.end() || it->second->claimed) {
+    set_error("rdm_server_wait: unknown ticket, or one already retrieved or being waited for");
     return RDM_E_INVALID;
   }
   Req* r = it->second;
+  r->claimed = true;
   s->cv_done.wait(lk, [&] { return r->done; });
   *status = r->status;
   delete r;

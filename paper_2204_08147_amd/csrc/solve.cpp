@@ -567,15 +567,29 @@ namespace {
 // before each phase.  Capture and replay run on a private stream per device
 // that is ordered after / before the caller's stream with events, so the
 // caller's stream may be the legacy default stream.
+// The key holds every launch parameter a step depends on, including which
+// variants of the strided transform pass it records (Lanczos or regeneration,
+// shallow or deep): two tables at one address can agree on every count and
+// still need different variants.
 struct GraphKey {
   int device;
   const void* dsegs;
   int nseg, norm, apply, xz, slab, cmax, prec, nsteps;
+  int variants;  // bit (2 * regen + deep) set when that strided variant runs
   bool operator<(const GraphKey& o) const {
-    return std::tie(device, dsegs, nseg, norm, apply, xz, slab, cmax, prec, nsteps) <
-           std::tie(o.device, o.dsegs, o.nseg, o.norm, o.apply, o.xz, o.slab, o.cmax, o.prec, o.nsteps);
+    return std::tie(device, dsegs, nseg, norm, apply, xz, slab, cmax, prec, nsteps, variants) <
+           std::tie(o.device, o.dsegs, o.nseg, o.norm, o.apply, o.xz, o.slab, o.cmax, o.prec, o.nsteps,
+                    o.variants);
   }
 };
+int launch_variants(const Launch& L) {
+  int v = 0;
+  for (int deep = 0; deep < 2; ++deep) {
+    if (L.xz_lanczos[deep]) v |= 1 << deep;
+    if (L.xz_regen[deep]) v |= 1 << (2 + deep);
+  }
+  return v;
+}
 constexpr size_t kMaxGraphs = 64;
 std::mutex g_graph_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
@@ -595,7 +609,7 @@ rdm_status graph_steps(int prec, Seg* dsegs, int nseg, const Launch& L, int slab
   } else {
     gs = its->second;
   }
-  const GraphKey key{dev, dsegs, nseg, L.norm, L.apply, L.xz, slab, cmax, prec, nsteps};
+  const GraphKey key{dev, dsegs, nseg, L.norm, L.apply, L.xz, slab, cmax, prec, nsteps, launch_variants(L)};
   hipGraphExec_t exec = nullptr;
   auto it = g_graphs.find(key);
   if (it != g_graphs.end()) {

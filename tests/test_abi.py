@@ -124,7 +124,7 @@ def test_solve_rejects_bad_arguments_without_touching_device():
 
 def test_block_quadrature_matches_oracle():
     # E_1^T exp(-beta (T - e0)) E_1 of the block variant (eqn:fT), host routine,
-    # on random symmetric matrices and on a real block tridiagonal from O4
+    # on random symmetric matrices and on a projected operator from O4
     from oracle import block, spin
     rng = np.random.default_rng(0)
     cases = []
@@ -136,7 +136,7 @@ def test_block_quadrature_matches_oracle():
     v = np.zeros((inst.dim, inst.d_s))
     for m in range(inst.d_s):
         v[m * inst.d_b:(m + 1) * inst.d_b, m] = 1.0 / np.sqrt(inst.d_b)
-    cases.append((block.block_lanczos(op.apply, v, 12), inst.d_s))
+    cases.append((block.krylov_projection(op.apply, v, 12), inst.d_s))
     for t, b in cases:
         e0 = float(np.linalg.eigvalsh(t)[0])
         f, mn = rdm.block_quadrature(t, b, [0.3, 1.7], e0)
