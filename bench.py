@@ -26,10 +26,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Non-packed FP32 and FP64 vector FMA issue at the same rate on gfx950:
-# 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.  (The 157.3
-# TFLOP/s FP32 figure needs packed FP32 FMA, which the library is compiled without.)
-VALU_PEAK_TFLOPS = 78.6
+# Published vector peaks of MI355X: FP32 157.3 TFLOP/s (256 CUs x 4 SIMD x 16
+# lanes x 2 flop x 2.4 GHz x 2 for packed FP32 FMA), FP64 78.6 TFLOP/s.  The
+# library is compiled without packed FP32 instructions, so half of the FP32
+# figure is what its kernels can issue; the published figure is the peak the
+# roofline fraction is taken against.
+VALU_PEAK_TFLOPS = {4: 157.3, 8: 78.6}
 
 METRIC = ("ρ_s solves/s & spin-H apply GB/s, mixed vs FP64 plain; p50/p99 solve latency")
 
@@ -44,8 +46,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-block", action="store_true", help="skip the block-Lanczos comparison")
     ap.add_argument("--no-truncation", action="store_true", help="skip the k against k + 20 check")
-    ap.add_argument("--workload", default="lr", choices=["lr", "batch", "large", "serve", "scan", "estimators"],
-                    help="lr: the metric's workload (default); batch: 64 heterogeneous sparse XXZ "
+    ap.add_argument("--workload", default="lr",
+                    choices=["lr", "small", "batch", "large", "serve", "scan", "estimators"],
+                    help="lr: the metric's workload (default); small: the 1+9-spin FP64 instance; "
+                         "batch: 64 heterogeneous sparse XXZ "
                          "instances in one batched solve; large: 3+23 spins (dim 2^26) two-pass; "
                          "serve: Poisson arrivals of transverse-field requests; scan: the paper's "
                          "entropy / internal-energy scans; estimators: product-state estimate, "
@@ -131,14 +135,27 @@ def _oracle_step_worker(kind, arg, n_rows):
         return (time.perf_counter() - t0) * inst.dim / n_rows
 
 
+def _pool_starmap(nproc, fn, args):
+    """starmap over a pool of fresh interpreters (the parent holds a GPU
+    context), closed and joined so that no worker is killed mid-exit."""
+    import multiprocessing as mp
+    pool = mp.get_context("spawn").Pool(nproc)
+    try:
+        out = pool.starmap(fn, args)
+        pool.close()
+        return out
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+
+
 def cpu_baseline_sample(kind, args_list, n_rows=0):
     """Oracle seconds per column step for each listed instance, one host
     process each (at most 16 at a time, BLAS one thread per process)."""
-    import multiprocessing as mp
     nproc = max(1, min(16, os.cpu_count() or 1, len(args_list)))
-    ctx = mp.get_context("spawn")  # fresh interpreters: the parent holds a GPU context
-    with ctx.Pool(nproc) as pool:
-        return nproc, pool.starmap(_oracle_step_worker, [(kind, a, n_rows) for a in args_list])
+    return nproc, _pool_starmap(nproc, _oracle_step_worker, [(kind, a, n_rows) for a in args_list])
 
 
 def _solve_seconds(inst, t_col_step, applies_per_step=1):
@@ -154,18 +171,17 @@ def cpu_baseline(inst, h_index, n_b, steps=2):
     `steps` Lanczos steps of one column per process.  Throughput = processes x
     steps / slowest process, scaled to a whole solve (every column, k steps,
     plus the bath run)."""
-    import multiprocessing as mp
     nproc = max(1, min(16, os.cpu_count() or 1))
-    ctx = mp.get_context("spawn")  # fresh interpreters: the parent holds a GPU context
-    with ctx.Pool(nproc) as pool:
-        times = pool.starmap(_oracle_worker, [(h_index, n_b, c % inst.n_cols, steps) for c in range(nproc)])
+    times = _pool_starmap(nproc, _oracle_worker, [(h_index, n_b, c % inst.n_cols, steps) for c in range(nproc)])
     col_steps_per_s = nproc * steps / max(times)
     cols = inst.n_cols + inst.n_v * (inst.d_b / inst.dim)  # bath columns are 1/d_s the size
     t_solve = inst.k * cols / col_steps_per_s
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": nproc, "kind": "oracle",
+            "extrapolated": True,
             "sample": f"{steps} FP64 Lanczos steps of one start column in each of {nproc} processes "
-                      f"(dim 2^{inst.n}), slowest {max(times):.1f} s, scaled to {inst.k} steps x "
-                      f"{cols:.2f} columns (NumPy, BLAS one thread per process)"}
+                      f"(dim 2^{inst.n}), slowest {max(times):.1f} s, extrapolated to {inst.k} steps x "
+                      f"{cols:.2f} columns (a whole solve would take hours on the host; NumPy, BLAS one "
+                      f"thread per process)"}
 
 
 def operator_work(nbits, cols, nnz, transform, s, k):
@@ -194,7 +210,8 @@ def operator_work(nbits, cols, nnz, transform, s, k):
 
 def step_work(insts, prec_bytes):
     """Algorithmic bytes and flops of one Lanczos step over the H_t and H_b
-    segments of the given instances."""
+    segments of the given instances, as the implementation computes it
+    (transform operators: the transform's own streams and flops)."""
     import paper_2204_08147_amd as rdm
     by = fl = 0.0
     for inst in insts:
@@ -208,20 +225,50 @@ def step_work(insts, prec_bytes):
     return by, fl
 
 
+def plan_work(insts, prec_bytes):
+    """The measurement plan's per-step work, independent of how the product
+    is computed: flops = 2 C nnz per row (nnz = diagonal + non-zero hops per
+    row) and the minimum bytes of a Lanczos step, three vector passes (read
+    q_j and q_(j-1), write q_(j+1)), over the H_t and H_b segments."""
+    import paper_2204_08147_amd as rdm
+    by = fl = 0.0
+    for inst in insts:
+        info = rdm.Hamiltonian.from_instance(inst).info()
+        nnz = 1 + info["hops_uniform"] + 0.5 * info["hops_parity"]
+        nnz_b = 1 + info["bath_hops_uniform"] + 0.5 * info["bath_hops_parity"]
+        fl += 2.0 * inst.n_cols * nnz * inst.dim + 2.0 * inst.n_v * nnz_b * inst.d_b
+        by += 3.0 * prec_bytes * (inst.n_cols * inst.dim + inst.n_v * inst.d_b)
+    return by, fl
+
+
 def step_ms(res):
     """Mean device time of one Lanczos step's vector kernels (norm step and
     apply, either kind) from the library's event timing."""
     return res["t_norm_ms"] + res["t_xz1_ms"] + res["t_apply_ms"]
 
 
-def roofline(bytes_, flops, t_s, traffic=None):
+def roofline(bytes_, flops, t_s, traffic=None, prec_bytes=4):
+    """Roofline object of one kernel (or step): bound by whichever of VALU
+    and HBM takes longer at peak for this work."""
+    peak_tf = VALU_PEAK_TFLOPS[prec_bytes]
     gbs = bytes_ / t_s / 1e9
     tf = flops / t_s / 1e12
-    if flops / (VALU_PEAK_TFLOPS * 1e12) >= bytes_ / (HBM_PEAK_GBS * 1e9):
-        return {"bound": "alu", "achieved": round(tf, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tf / VALU_PEAK_TFLOPS, 4), "traffic": traffic}
+    if flops / (peak_tf * 1e12) >= bytes_ / (HBM_PEAK_GBS * 1e9):
+        return {"bound": "alu", "achieved": round(tf, 3), "peak": peak_tf, "unit": "TFLOP/s",
+                "frac": round(tf / peak_tf, 4), "traffic": traffic}
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def result_errors(a, b):
+    """Largest differences of a's rho*, H* (relative Frobenius), ln Z* and S
+    (absolute) from b's over the temperatures of one solve."""
+    nb = len(b["log_z"])
+    rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))  # noqa: E731
+    return {"rho_rel": max(rel(a["rho"][t], b["rho"][t]) for t in range(nb)),
+            "h_star_rel": max(rel(a["h_star"][t], b["h_star"][t]) for t in range(nb)),
+            "log_z_abs": max(abs(float(a["log_z"][t] - b["log_z"][t])) for t in range(nb)),
+            "entropy_abs": max(abs(float(a["entropy"][t] - b["entropy"][t])) for t in range(nb))}
 
 
 def bench_batch(args):
@@ -245,9 +292,11 @@ def bench_batch(args):
     prof = rdm.solve_batch(items, precision="mixed", profile=True)  # kernel timing, untimed
     assert all(o["status"] == 0 for o in out), [o["status"] for o in out]
     by, fl = step_work(insts, 4)
-    # one apply launch covers every instance resident in a wave; with several
-    # waves the event average is per launch of the wave, so report the sum
-    t_step = float(np.mean([step_ms(o) for o in prof])) * 1e-3
+    # one launch covers every instance resident in a wave, and each instance
+    # reports its wave's mean step time: the instances of one wave share the
+    # value, so a step over the whole batch takes the sum over the waves
+    wave_ms = sorted({(o["t_norm_ms"], o["t_xz1_ms"], o["t_apply_ms"]) for o in prof})
+    t_step = sum(sum(w) for w in wave_ms) * 1e-3
     n = len(insts) * args.steps
     cpu = None
     if not args.no_cpu_baseline:
@@ -265,7 +314,8 @@ def bench_batch(args):
             "config": {"workload": "64 random sparse XXZ instances, N in [12,22], N_s in {1,2,3}, "
                                    "degree 4, beta log-U[0.1,10], n_v=8, k=50",
                        "dims": sorted(int(i.n) for i in insts)},
-            "step_kernels_ms_mean": round(1e3 * t_step, 4),
+            "step_kernels_ms_all_waves": round(1e3 * t_step, 4), "waves": len(wave_ms),
+            "roofline_step": roofline(*plan_work(insts, 4), t_step),
             "two_pass_instances": int(sum(o["two_pass"] for o in out))}
 
 
@@ -325,7 +375,8 @@ def bench_large(args):
             "config": {"workload": "long-range XXZ 3+23 spins (dim 2^26), alpha=1.2, Delta=0.8, "
                                    "x-field 1.0, beta=2, n_v=4 (32 columns), k=80, two-pass"},
             "apply_kernel_ms": round(res["t_apply_ms"], 3), "norm_kernel_ms": round(res["t_norm_ms"], 3),
-            "roofline_step": roofline(by, fl, t_step), "two_pass": res["two_pass"],
+            "roofline_step": roofline(*plan_work([inst], 4), t_step),
+            "roofline_step_implementation": roofline(by, fl, t_step), "two_pass": res["two_pass"],
             "device_bytes": res["device_bytes"],
             "rho": res["rho"][0].round(6).tolist(), "entropy": float(res["entropy"][0]), "block_method": block,
             "h_star_eigs": np.linalg.eigvalsh(res["h_star"][0]).round(6).tolist()}
@@ -487,6 +538,71 @@ def bench_scan(args):
     return out
 
 
+def _time_oracle_small(reps):
+    """Host process: the oracle's O3 path and the dense O1 answer on the
+    1 + 9 chain, each timed over whole calls (best of reps)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import exact, lanczos as olz
+    from workloads import cfg_small_chain
+    inst = cfg_small_chain()
+    with threadpool_limits(limits=1):
+        t3, t1 = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            olz.solve(inst)
+            t3.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            exact.exact_rdm(inst, float(inst.betas[0]))
+            t1.append(time.perf_counter() - t0)
+    return min(t3), min(t1)
+
+
+def bench_small(args):
+    """The CPU-checkable configuration: 1 system + 9 bath spins (dim 1024),
+    nearest-neighbour XXZ chain, z-field h = 0.5, beta = 1, n_v = 4, k = 30,
+    FP64, solves one after another on one stream (latency-bound: the whole
+    solve is a few launches of small kernels)."""
+    import torch
+    import paper_2204_08147_amd as rdm
+    from oracle import exact
+    from workloads import cfg_small_chain
+    inst = cfg_small_chain()
+    h = rdm.Hamiltonian.from_instance(inst)
+    ws = torch.empty(rdm.workspace_size(h, 1, inst.n_v, inst.k, precision="fp64"), dtype=torch.uint8,
+                     device="cuda")
+    for _ in range(max(1, args.warmup)):
+        rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", workspace=ws)
+    torch.cuda.synchronize()
+    n = 50 * args.steps
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(n):
+        t1 = time.perf_counter()
+        r = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", workspace=ws)
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ex = exact.exact_rdm(inst, float(inst.betas[0]))
+    err = float(np.linalg.norm(r["rho"][0] - ex["rho"]) / np.linalg.norm(ex["rho"]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        stage("oracle on the host (whole O3 solves and the dense answer)")
+        t3, t1 = _pool_starmap(1, _time_oracle_small, [(3,)])[0]
+        cpu = {"value": round(1.0 / t3, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"whole O3 solves (FP64 Lanczos path), best of 3, one process, BLAS one thread; "
+                         f"dense O1 exact answer {1e3 * t1:.1f} ms"}
+    return {"metric": "small-instance solves/s (FP64)", "value": round(n / wall, 3), "unit": "solves/s",
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
+            "dtype": "f64", "cpu_baseline": cpu,
+            "config": {"workload": "XXZ chain 1+9 spins (dim 1024), J ~ U(-1,1), system-bath bond 1, "
+                                   "z-field h=0.5, beta=1, n_v=4, k=30, FP64; 50 solves per step"},
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+            "rho_rel_err_vs_exact": err,
+            "note": "the estimate's error against the exact partial trace is the stochastic error of "
+                    "n_v = 4 bath vectors, not a parity figure"}
+
+
 def bench_estimators(args):
     """The estimator variants and limits on the long-range 2 + 18 workload
     (h = 0.5, n_v = 16, k = 60, beta in {0.5, 1, 2, 4}), mixed precision:
@@ -562,8 +678,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.workload != "lr":
-        fn = {"batch": bench_batch, "large": bench_large, "serve": bench_serve, "scan": bench_scan,
-              "estimators": bench_estimators}[args.workload]
+        fn = {"small": bench_small, "batch": bench_batch, "large": bench_large, "serve": bench_serve,
+              "scan": bench_scan, "estimators": bench_estimators}[args.workload]
         out = fn(args)
         out.update({"n_gpus": 1, "data": "synthetic", "scaling": "weak"})
         print(json.dumps(out))
@@ -634,7 +750,6 @@ def main():
                     lat.append(time.perf_counter() - t1)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        res = res[-1]
         if profile:
             for h, i, w in zip(hs, insts, ws):
                 r = rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision=prec, mode="stored",
@@ -692,6 +807,7 @@ def main():
     torch.cuda.empty_cache()
 
     fp64 = None
+    mixed_vs_fp64 = None
     if not args.no_fp64:
         stage("FP64 solves")
         ws_d = make_ws("fp64")
@@ -703,6 +819,10 @@ def main():
         fp64 = {"solves_per_s": n_d / wall_d, "p50_ms": 1e3 * float(np.percentile(lat_d, 50)),
                 "p99_ms": 1e3 * float(np.percentile(lat_d, 99)),
                 "step_kernels_ms": float(np.mean(ap_d) + np.mean(no_d) + np.mean(x0_d))}
+        # error of the mixed path against the FP64 path, same instances and
+        # bath vectors (the largest over the fields and temperatures)
+        errs = [result_errors(a, b) for a, b in zip(res_m, res_d)]
+        mixed_vs_fp64 = {key: max(e[key] for e in errs) for key in errs[0]}
 
     # Krylov truncation (Section "Error analysis"): the FP64 result at k
     # against k + 20 steps with the same bath vectors, outside the timed region
@@ -732,15 +852,22 @@ def main():
     probe = {p: rdm.stream_probe(p, 1 << 31, 10) for p in ("read", "copy", "r3w1", "r2w2")}
     torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel: the apply launch (H_t and H_b segments)
+    # roofline of the dominant work, one Lanczos step (the two transform
+    # passes over the H_t and H_b segments), on the measurement plan's count:
+    # 2 C nnz flops per row against the FP32 vector peak (nnz = 211 makes the
+    # product VALU-bound by that count); beside it the plan's minimum bytes
+    # (three vector passes) and the transform's own streams against HBM
     info = hs[0].info()
     nnz = 1 + info["hops_uniform"] + 0.5 * info["hops_parity"]
     bytes_alg, flops = step_work([inst0], 4)
+    min_bytes, nnz_flops = plan_work([inst0], 4)
     t_step = float(np.mean(ap_m) + np.mean(no_m) + np.mean(x0_m)) * 1e-3
     achieved_gbs = bytes_alg / t_step / 1e9
     mix_gbs = 2.0 / (1.0 / probe["r2w2"] + 1.0 / probe["r3w1"])
     traffic = read_traffic("lanczos_step_lr_xxzz_2+18_mixed_counters.txt")
-    roof = roofline(bytes_alg, flops, t_step, traffic)
+    roof = roofline(min_bytes, nnz_flops, t_step, traffic)
+    roof_transform = roofline(bytes_alg, 0.0, t_step, traffic)
+    roof_min_bytes = roofline(min_bytes, 0.0, t_step)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -774,9 +901,18 @@ def main():
                                       1),
         "fp64": None if fp64 is None else {k2: round(v, 4) for k2, v in fp64.items()},
         "mixed_over_fp64": None if fp64 is None else round(value / fp64["solves_per_s"], 3),
+        "mixed_vs_fp64": mixed_vs_fp64,
         "block_method": block,
         "truncation_k_vs_k20": trunc,
         "roofline": roof,
+        "roofline_note": "one Lanczos step; achieved = 2*C*nnz flops per row (H_t and H_b) / step time "
+                         "against the published FP32 vector peak; the transform apply reaches the same "
+                         "product with (2N+8) flops per element, so this is an effective rate",
+        "roofline_transform_bytes": roof_transform,
+        "roofline_min_bytes": roof_min_bytes,
+        "scope_notes": {"gram": "recombination + Gram on the vector units (C <= 64 columns, intensity "
+                                "<= C/2 flop/B: bound by HBM, see gram_gbs_algorithmic)",
+                        "cpu_baseline": "extrapolated from a timed sample of Lanczos steps"},
         # a transform step is half two-read-two-write (pass 1), half
         # three-read-one-write (pass 2): the probe's matching mix
         "stream_probe": {**{k: round(v, 1) for k, v in probe.items()},

@@ -26,9 +26,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from .exact import finalize, start_columns
+from .exact import finalize
 from .rng import bath_vectors
-from .spin import sparse_bath_hamiltonian, sparse_hamiltonian
+from .spin import (merged_bath_hamiltonian, merged_hamiltonian, sparse_bath_hamiltonian,
+                   sparse_hamiltonian)
 
 TAU_FP64 = 1e-12
 
@@ -82,36 +83,77 @@ def min_ritz(alpha, beta) -> float:
     return float(np.linalg.eigvalsh(tridiag(alpha, beta))[0])
 
 
-def solve(inst, betas=None, tau: float = TAU_FP64, keep=False) -> dict:
+_OPS = {}
+
+
+def _operator(inst, which: int, merged: bool):
+    """H_t (which = 0) or H_b (which = 1) of an instance, matrix-free
+    (``merged`` = True: the merged form, fast enough for full-size reference
+    runs).  A few operators are kept per process for repeated column runs."""
+    key = (inst.n_s, inst.n_b, tuple(map(tuple, inst.couplings)), tuple(inst.hx), tuple(inst.hz),
+           which, merged)
+    if key not in _OPS:
+        if len(_OPS) >= 4:
+            _OPS.pop(next(iter(_OPS)))
+        if which == 0:
+            make = merged_hamiltonian if merged else sparse_hamiltonian
+            _OPS[key] = make(inst.n, inst.couplings, inst.hx, inst.hz)
+        else:
+            make = merged_bath_hamiltonian if merged else sparse_bath_hamiltonian
+            _OPS[key] = make(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+    return _OPS[key]
+
+
+def column_task(task):
+    """One Lanczos run of a solve.  task = (inst, which, c, tau, merged,
+    weights): start column c of H_t (which = 0, column c = j*d_s + m is
+    |m> (x) |v_j>) or bath vector c on H_b (which = 1).  Without weights it
+    returns (alpha, beta, |x|); with weights = (betas, E0) it returns, for an
+    H_t column, psi = |x| Q exp(-b (T - E0)/2) e_1 for every b (dim x n_beta).
+    The basis Q is rebuilt by running the same recurrence again, which
+    repeats it exactly, so a run never holds more than one column's basis."""
+    inst, which, c, tau, merged, weights = task
+    op = _operator(inst, which, merged)
+    if which == 0:
+        v = bath_vectors(inst.seed, c // inst.d_s + 1, inst.n_b)[:, c // inst.d_s]
+        x = np.zeros(inst.dim)
+        m = c % inst.d_s
+        x[m * inst.d_b:(m + 1) * inst.d_b] = v
+    else:
+        x = bath_vectors(inst.seed, c + 1, inst.n_b)[:, c]
+    a, b, q, nx = lanczos(op.apply, x, inst.k, tau, keep_q=weights is not None)
+    if weights is None:
+        return a, b, nx
+    betas, e0 = weights
+    return np.stack([q @ (nx * fa_weights(a, b, bt, e0)) for bt in betas], axis=1)
+
+
+def solve(inst, betas=None, tau: float = TAU_FP64, merged: bool = False, mapper=map) -> dict:
     """Run the whole path for one instance.  Returns per-beta outputs plus the
-    intermediate Lanczos coefficients (for coefficient-level comparisons)."""
+    intermediate Lanczos coefficients (for coefficient-level comparisons).
+    ``mapper`` runs the independent column runs (the builtin map, or a process
+    pool's); ``merged`` selects the merged operator form."""
     betas = np.asarray(inst.betas if betas is None else betas, float)
-    op = sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
-    opb = sparse_bath_hamiltonian(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
     d_s, d_b, n_v = inst.d_s, inst.d_b, inst.n_v
-    x0 = start_columns(inst)
-    cols = []
-    for c in range(x0.shape[1]):
-        a, b, q, nx = lanczos(op.apply, x0[:, c], inst.k, tau)
-        cols.append((a, b, q, nx))
-    e0 = min(min_ritz(a, b) for a, b, _, _ in cols)
-    v = bath_vectors(inst.seed, n_v, inst.n_b)
-    bath = [lanczos(opb.apply, v[:, j], inst.k, tau, keep_q=False) for j in range(n_v)]
-    e0b = min(min_ritz(a, b) for a, b, _, _ in bath)
+    n_cols = inst.n_cols
+    # every column's recurrence coefficients; the common shifts
+    runs = list(mapper(column_task, [(inst, 0, c, tau, merged, None) for c in range(n_cols)] +
+                       [(inst, 1, j, tau, merged, None) for j in range(n_v)]))
+    cols, bath = runs[:n_cols], runs[n_cols:]
+    e0 = min(min_ritz(a, b) for a, b, _ in cols)
+    e0b = min(min_ritz(a, b) for a, b, _ in bath)
+    # the recombined columns for every temperature, then the Gram per bath
+    # vector and the n_v average
+    psis = list(mapper(column_task, [(inst, 0, c, tau, merged, (betas, e0)) for c in range(n_cols)]))
     results = []
-    for bt in betas:
+    for t, bt in enumerate(betas):
         m = np.zeros((d_s, d_s))
         for j in range(n_v):
-            psi = np.stack([cols[j * d_s + mm][2] @ (cols[j * d_s + mm][3] *
-                            fa_weights(cols[j * d_s + mm][0], cols[j * d_s + mm][1], bt, e0))
-                            for mm in range(d_s)], axis=1)
+            psi = np.stack([psis[j * d_s + mm][:, t] for mm in range(d_s)], axis=1)
             m += psi.T @ psi
         m /= n_v
-        m_b = sum(nx * nx * quad_weight(a, b, bt, e0b) for a, b, _, nx in bath) / n_v
+        m_b = sum(nx * nx * quad_weight(a, b, bt, e0b) for a, b, nx in bath) / n_v
         results.append(finalize(m, m_b, e0, e0b, bt, d_b) | {"m": m, "m_b": m_b})
-    out = {"results": results, "e0": e0, "e0b": e0b,
-           "alpha": [c[0] for c in cols], "beta": [c[1] for c in cols],
-           "bath_alpha": [b[0] for b in bath], "bath_beta": [b[1] for b in bath]}
-    if keep:
-        out["q"] = [c[2] for c in cols]
-    return out
+    return {"results": results, "e0": e0, "e0b": e0b,
+            "alpha": [c[0] for c in cols], "beta": [c[1] for c in cols],
+            "bath_alpha": [b[0] for b in bath], "bath_beta": [b[1] for b in bath]}

@@ -177,6 +177,79 @@ class SparseSpinOperator:
         return val
 
 
+class MergedSpinOperator:
+    """The same matrix-free H with its Pauli strings merged by the basis state
+    they reach.  A string whose flips are the bit set f maps |p> to a phase
+    times |p ^ f>, so
+
+        (H X)[q] = d(q) X[q] + sum_{f != 0} c_f(q) X[q ^ f],
+
+    with d the summed phases of the strings that flip nothing and c_f(q) the
+    summed phase, read at the source state q ^ f, of every string that flips
+    f.  Both are evaluated once from the matrix-free form's own term actions
+    (kept as a scalar when constant over q).  X[q ^ f] for all q is X with the
+    index axes of the bits in f reversed (a view of X as a 2 x ... x 2
+    tensor), which is what makes this form fast enough for full-size
+    reference runs; it is pinned to the matrix-free and dense forms."""
+
+    def __init__(self, n: int, couplings, hx, hz):
+        base = SparseSpinOperator(n, couplings, hx, hz)
+        self.n = n
+        p = np.arange(1 << n, dtype=np.int64)
+        self.diag = np.zeros(1 << n)
+        coef = {}
+        for t in base.terms:
+            f = 0
+            for s in (t[1], t[3]):
+                if s >= 0 and t[0 if s == t[1] else 2] in "xy":
+                    f |= 1 << (n - 1 - s)
+            if f == 0:
+                out, ph = base._action(t, p)
+                self.diag += ph
+                continue
+            out, ph = base._action(t, p ^ f)          # phase read at the source q ^ f
+            assert np.array_equal(out, p)
+            coef[f] = coef.get(f, 0.0) + ph
+        self.hops = []
+        for f, c in coef.items():
+            c = np.asarray(c)
+            if np.all(c == c.flat[0]):
+                c = float(c.flat[0])
+            if np.any(c != 0.0):
+                self.hops.append((f, c))
+
+    @property
+    def dim(self) -> int:
+        return 1 << self.n
+
+    def _partner(self, x: np.ndarray, f: int) -> np.ndarray:
+        n = self.n
+        axes = [n - 1 - b for b in range(n) if (f >> b) & 1]
+        t = x.reshape((2,) * n + x.shape[1:])
+        return np.flip(t, axis=axes).reshape(x.shape)
+
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        shape = (-1,) + (1,) * (x.ndim - 1)
+        y = self.diag.reshape(shape) * x
+        for f, c in self.hops:
+            xf = self._partner(x, f)
+            if isinstance(c, float):
+                y += c * xf
+            else:
+                y += c.reshape(shape) * xf
+        return y
+
+
+def merged_hamiltonian(n: int, couplings, hx, hz) -> MergedSpinOperator:
+    return MergedSpinOperator(n, couplings, hx, hz)
+
+
+def merged_bath_hamiltonian(n_s: int, n_b: int, couplings, hx, hz) -> MergedSpinOperator:
+    bc, bhx, bhz = bath_terms(n_s, couplings, hx, hz)
+    return MergedSpinOperator(n_b, bc, bhx, bhz)
+
+
 def sparse_hamiltonian(n: int, couplings, hx, hz) -> SparseSpinOperator:
     return SparseSpinOperator(n, couplings, hx, hz)
 

@@ -201,6 +201,20 @@ rdm_status get_device_op(const rdm_hamiltonian* h, int which, int precision, hip
   return RDM_OK;
 }
 
+rdm_status find_device_op(const rdm_hamiltonian* h, int which, int precision, const OpDevice** out) {
+  std::lock_guard<std::mutex> lk(h->mu);
+  int dev = 0;
+  RDM_HIP(hipGetDevice(&dev));
+  const OpDevice& d = h->dev[which][precision];
+  if (!d.ready || d.device != dev) {
+    set_error("the Hamiltonian's device tables are not resident on this device in this precision "
+              "(any earlier solve or apply with it builds them)");
+    return RDM_E_INVALID;
+  }
+  *out = &d;
+  return RDM_OK;
+}
+
 }  // namespace rdm
 
 using namespace rdm;

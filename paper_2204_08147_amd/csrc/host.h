@@ -77,6 +77,9 @@ namespace rdm {
 // current device (synchronous).
 rdm_status get_device_op(const rdm_hamiltonian* h, int which, int precision, hipStream_t st,
                          const OpDevice** out);
+// The same tables if they are already resident on the current device,
+// RDM_E_INVALID otherwise (never builds or allocates).
+rdm_status find_device_op(const rdm_hamiltonian* h, int which, int precision, const OpDevice** out);
 
 // Symmetric tridiagonal eigenproblem by implicit QR with Wilkinson shifts.
 // Fills theta (n) and zrow = first row of the eigenvector matrix (n), and

@@ -296,8 +296,13 @@ rdm_status fetch_history(const SegPlan& g, char* base, std::vector<double>& a, s
 void parallel_jobs(int n, const std::function<void(int)>& fn) { parallel_for(n, fn); }
 size_t align_up(size_t x) { return al(x); }
 
-rdm_status bind_ops(InstRun& r, hipStream_t st) {
+rdm_status bind_ops(InstRun& r, hipStream_t st, bool build_tables) {
   const InstPlan& p = *r.plan;
+  if (!build_tables) {
+    rdm_status s = find_device_op(p.h, 0, p.prec, &r.op_t);
+    if (s != RDM_OK) return s;
+    return find_device_op(p.h, 1, p.prec, &r.op_b);
+  }
   rdm_status s = get_device_op(p.h, 0, p.prec, st, &r.op_t);
   if (s != RDM_OK) return s;
   return get_device_op(p.h, 1, p.prec, st, &r.op_b);
@@ -745,7 +750,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
 }
 
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
-                   bool tune, bool graph) {
+                   bool tune, bool graph, bool build_tables) {
   const int ni = (int)runs.size();
   if (ni == 0) return RDM_OK;
   const int prec = runs[0].plan->prec;
@@ -757,7 +762,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
   for (auto& r : runs) {
     r.base = ws + inst_off;
     inst_off += r.plan->bytes;
-    rdm_status s = bind_ops(r, st);
+    rdm_status s = bind_ops(r, st, build_tables);
     if (s != RDM_OK) return s;
   }
   StepTimers tm;

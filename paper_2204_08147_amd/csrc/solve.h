@@ -87,11 +87,13 @@ rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int 
                          int mode_req, uint64_t budget, int slab_opt, int rpl_opt);
 size_t batch_header_bytes(const std::vector<InstPlan>& plans);
 // graph: replay the Lanczos steps as a captured hipGraph (unless profiling)
+// build_tables = false: the operators' device tables must be resident
+// already (nothing is allocated)
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
-                   bool tune, bool graph);
+                   bool tune, bool graph, bool build_tables = true);
 
 // Phases (used by execute and by the serving engine).
-rdm_status bind_ops(InstRun& r, hipStream_t st);
+rdm_status bind_ops(InstRun& r, hipStream_t st, bool build_tables = true);
 Seg seg_of(const InstRun& r, int which, int mode, double tau);
 int common_slab(std::vector<Seg>& segs);
 // Operator tables of a segment's apply (hop tables or transform).  Needs

@@ -444,7 +444,9 @@ def test_full_size_solve_properties():
     want = [{key: d64[key][b] for key in ("rho", "h_star", "log_z", "entropy")} for b in range(len(inst.betas))]
     check_result(mix, want, 1e-5, "full size: mixed vs FP64")
     blk = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
-    check_result(blk, want, 1e-5, "full size: block vs per-column")
+    # both quadratures have converged at k = 60 (k + 20 moves the result by
+    # about 1e-11): the two FP64 methods agree far below the mixed bar
+    check_result(blk, want, 1e-9, "full size: block vs per-column")
     longer = rdm.solve(h, inst.betas, inst.n_v, inst.k + 20, inst.seed, precision="fp64")
     check_result(longer, want, 1e-9, "full size: k + 20 vs k")
 
@@ -566,6 +568,78 @@ def test_batch_equals_solo(prec):
             assert np.array_equal(got[key], solo[key]), key
 
 
+def test_batch_waves_and_two_pass_equal_solo():
+    # a budget that forces the largest instance into the two-pass plan and
+    # the batch into several waves: every item bitwise equal to its own solve
+    # under the same budget, one item against O3
+    insts = [long_range_xx_zz(2, 12, 1.0, 301, betas=(0.5, 2.0), n_v=4, k=40),
+             random_sparse_xxz(3012, n_range=(13, 13)),
+             random_sparse_xxz(3013, n_range=(12, 12)),
+             SOLVE_CASES["lr_2+9"](),
+             SOLVE_CASES["random_2+6"]()]
+    hs = [H(i) for i in insts]
+    big = insts[0]
+    stored = rdm.workspace_size(hs[0], len(big.betas), big.n_v, big.k, precision="mixed", mode="stored")
+    two = rdm.workspace_size(hs[0], len(big.betas), big.n_v, big.k, precision="mixed", mode="two_pass")
+    budget = (stored + two) // 2
+    assert two < budget < stored
+    items = [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
+    for prec in ("fp64", "mixed"):
+        got = rdm.solve_batch(items, precision=prec, hbm_budget=budget, library_alloc=True)
+        solo = [rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision=prec, hbm_budget=budget) for h, i in
+                zip(hs, insts)]
+        assert solo[0]["two_pass"] and got[0]["two_pass"]
+        assert not any(g["two_pass"] for g in got[1:])
+        for a, b in zip(solo, got):
+            assert b["status"] == 0
+            for key in ("rho", "h_star", "log_z", "entropy"):
+                assert np.array_equal(a[key], b[key]), (prec, key)
+    total = sum(rdm.workspace_size(h, len(i.betas), i.n_v, i.k, precision="fp64", hbm_budget=budget)
+                for h, i in zip(hs, insts))
+    assert total > budget  # so the batch above ran in more than one wave
+    check_result(got[3], oracle_solve("lr_2+9"), 1e-5, "batched item vs O3")
+
+
+def test_concurrent_solves_equal_solo():
+    # the benchmark's mode: several solves at once, each from its own host
+    # thread on its own stream and workspace, repeatedly; every result bitwise
+    # equal to the same solve run alone
+    import threading
+    names = ["xz_2+14", "lr_2+9", "sparse"]
+    insts = [SOLVE_CASES[n]() for n in names]
+    hs = [H(i) for i in insts]
+    for prec in ("fp64", "mixed"):
+        solo = [rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision=prec, mode="stored") for h, i in zip(hs, insts)]
+        ws = [torch.empty(rdm.workspace_size(h, len(i.betas), i.n_v, i.k, precision=prec, mode="stored"),
+                          dtype=torch.uint8, device="cuda") for h, i in zip(hs, insts)]
+        streams = [torch.cuda.Stream() for _ in insts]
+        out = [[] for _ in insts]
+        errors = []
+
+        def worker(t):
+            try:
+                i = insts[t]
+                with torch.cuda.stream(streams[t]):
+                    for _ in range(3):
+                        out[t].append(rdm.solve(hs[t], i.betas, i.n_v, i.k, i.seed, precision=prec,
+                                                mode="stored", workspace=ws[t], stream=streams[t]))
+            except BaseException as e:  # re-raised in the main thread
+                errors.append(e)
+
+        th = [threading.Thread(target=worker, args=(t,)) for t in range(len(insts))]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        if errors:
+            raise errors[0]
+        torch.cuda.synchronize()
+        for t in range(len(insts)):
+            for r in out[t]:
+                for key in ("rho", "h_star", "log_z", "entropy"):
+                    assert np.array_equal(r[key], solo[t][key]), (prec, names[t], key)
+
+
 def test_batch_reports_bad_item_and_solves_the_rest():
     a = SOLVE_CASES["chain_1+9"]()
     h = H(a)
@@ -651,6 +725,64 @@ def test_serving_alone_equals_in_mix():
             assert np.array_equal(a[key], b[key]), key
 
 
+# --------------------------------------------------------------------------
+# stored oracle results at full size (tests/golden/make_golden.py, O3 in
+# FP64): the benchmark's own 2 + 18 workload in the benchmark's launch
+# configuration (64 columns, k = 60, stored basis, graph replay), and the
+# transform apply with 9 and 10 high bits (21 and 22 spins)
+# --------------------------------------------------------------------------
+def _golden():
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "make_golden", os.path.join(os.path.dirname(__file__), "golden", "make_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+GOLDEN_CASES = ["lr_2+18_h0.5", "tfim_1+21", "lr_1+20"]
+
+
+@pytest.mark.parametrize("name", GOLDEN_CASES)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_full_size_matches_stored_oracle(name, prec, tol):
+    g = _golden()
+    want = g.load(name)
+    inst = g.CASES[name]()
+    assert (inst.n_v, inst.k, inst.seed) == (want["n_v"], want["k"], want["seed"])
+    h = H(inst)
+    assert h.info()["transform"] == 1
+    got = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision=prec, mode="stored")
+    check_result(got, want["results"], tol, f"{name} {prec} vs stored O3")
+    for t, w in enumerate(want["results"]):
+        assert abs(got["log_z_t"][t] - w["log_z_t"]) < tol * max(1.0, abs(w["log_z_t"]))
+        assert abs(got["log_z_b"][t] - w["log_z_b"]) < tol * max(1.0, abs(w["log_z_b"]))
+
+
+def test_served_request_matches_oracle():
+    # a 14-spin transverse-field request through the serving engine, next to
+    # other requests, against O3 (FP64 engine at the FP64 bar, mixed engine at
+    # the mixed bar)
+    inst = tfim_request(7, n_range=(14, 14))
+    others = [tfim_request(r, n_range=(12, 16)) for r in range(3)]
+    want = olz.solve(inst)["results"]
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-5)):
+        srv = rdm.Server(hbm_budget=2 << 30, max_active=4, precision=prec)
+        try:
+            hs = [H(i) for i in others]
+            tk = [srv.submit(hh, i.betas, i.n_v, i.k, i.seed) for hh, i in zip(hs, others)]
+            h = H(inst)
+            t = srv.submit(h, inst.betas, inst.n_v, inst.k, inst.seed)
+            got = srv.wait(t)
+            for x in tk:
+                assert srv.wait(x)["status"] == 0
+        finally:
+            srv.close()
+        assert got["status"] == 0
+        check_result(got, want, tol, f"served request ({prec}) vs O3")
+
+
 def _with_hop_tables(inst):
     # the same operator up to a YY part of 1e-13 on one pair (far below the
     # FP64 bar): a YY term rules out the transform apply, so the library
@@ -665,6 +797,46 @@ DEEP_CASES = {
     "lr_1+20": lambda: long_range_xx_zz(1, 20, 1.0, 81, betas=(0.5, 2.0), n_v=2, k=30),
     "lr_2+20": lambda: long_range_xx_zz(2, 20, 1.0, 82, betas=(1.0,), n_v=1, k=20),
 }
+
+
+SHALLOW_CASES = {
+    # 17, 18 and 19 bits: the strided pass's butterfly mask in arrangement 2
+    # covers one, two and three of the four register bits
+    "lr_1+16": lambda: long_range_xx_zz(1, 16, 1.0, 83, betas=(0.5, 2.0), n_v=2, k=30),
+    "lr_2+16": lambda: long_range_xx_zz(2, 16, 0.5, 84, betas=(1.0, 4.0), n_v=2, k=30),
+    "tfim_2+17": lambda: tfim_request(11, n_range=(19, 19), n_v=2, k=30),
+}
+
+
+@pytest.mark.parametrize("name", list(SHALLOW_CASES))
+def test_transform_17_to_19_bits_matches_hop_tables(name):
+    inst = SHALLOW_CASES[name]()
+    h, hh = H(inst), H(_with_hop_tables(inst))
+    assert h.info()["transform"] == 1 and hh.info()["transform"] == 0
+    a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    want = [{key: b[key][t] for key in ("rho", "h_star", "log_z", "entropy")} for t in range(len(inst.betas))]
+    check_result(a, want, 1e-10, "transform vs hop tables " + name)
+
+
+def test_graph_cache_separates_strided_variants():
+    # two batches with the same launch counts (segments, tiles, columns, k) at
+    # one workspace address, one of them with a 21-bit segment (deep strided
+    # variant) and one without: each replay must record its own variants
+    def batch(ns):
+        insts = [long_range_xx_zz(3, n - 3, 1.0, 90 + n, betas=(1.0,), n_v=1, k=8) for n in ns]
+        hs = [H(i) for i in insts]
+        return [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
+    shallow, deep = batch([20, 20, 20]), batch([21, 19, 19])
+    assert all(it["h"].info()["transform"] == 1 for it in shallow + deep)
+    ws = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+    for items in (shallow, deep, shallow):
+        eager = rdm.solve_batch(items, precision="mixed", eager=True, workspace=ws)
+        graph = rdm.solve_batch(items, precision="mixed", workspace=ws)
+        for x, y in zip(eager, graph):
+            assert x["status"] == 0 and y["status"] == 0
+            for key in ("rho", "h_star", "log_z", "entropy"):
+                assert np.array_equal(x[key], y[key]), key
 
 
 @pytest.mark.parametrize("name", list(DEEP_CASES))

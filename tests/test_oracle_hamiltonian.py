@@ -66,3 +66,29 @@ def test_split_sums_to_total_and_hsb_traceless_over_bath():
     opb = spin.sparse_bath_hamiltonian(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
     x = np.random.default_rng(0).normal(size=8)
     assert np.abs(opb.apply(x) - hb @ x).max() < 1e-13
+
+
+@pytest.mark.parametrize("n_s,n_b,seed", [(1, 6, 41), (2, 5, 42), (3, 6, 43)])
+def test_merged_apply_equals_dense_and_matrix_free(n_s, n_b, seed):
+    # the merged form (strings grouped by flip mask, partners by axis reversal)
+    # against the Kronecker H and the scatter form, every term type, both the
+    # total and the bath operator, one and several columns
+    inst = random_dense_terms(n_s, n_b, seed)
+    H = spin.dense_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    m = spin.merged_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    sp = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    x = np.random.default_rng(seed).normal(size=(inst.dim, 3))
+    assert np.abs(m.apply(x) - H @ x).max() < 1e-13
+    assert np.abs(m.apply(x[:, 1]) - sp.apply(x[:, 1])).max() < 1e-13
+    _, hb, _ = spin.split_dense(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+    mb = spin.merged_bath_hamiltonian(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+    xb = x[:inst.d_b]
+    assert np.abs(mb.apply(xb) - hb @ xb).max() < 1e-13
+
+
+def test_merged_apply_at_16_bits_equals_matrix_free():
+    inst = random_dense_terms(2, 14, 44, density=0.15)
+    m = spin.merged_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    sp = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
+    x = np.random.default_rng(44).normal(size=inst.dim)
+    assert np.abs(m.apply(x) - sp.apply(x)).max() < 1e-12 * np.abs(x).max() * len(sp.terms)

@@ -169,3 +169,19 @@ def test_chebyshev_interpolation_error_closed_form():
         assert e > 0.05 * cap
     e0 = bounds.chebyshev_interpolation_error(1.0, 0.0, 2.0, 0.0, 0)
     assert e0 >= 0.5 * (1.0 - exp(-2.0)) * (1 - 1e-12)
+
+
+def test_pooled_merged_run_equals_serial_matrix_free():
+    # the reference runs at full size use the merged operator and a process
+    # pool over the columns; they must give the plain serial run's results
+    import multiprocessing as mp
+    inst = long_range_xx_zz(2, 7, 1.0, 35, betas=(0.5, 2.0), n_v=3, k=30)
+    a = lanczos.solve(inst)
+    with mp.get_context("spawn").Pool(2) as pool:
+        b = lanczos.solve(inst, merged=True, mapper=pool.map)
+    for x, y in zip(a["results"], b["results"]):
+        assert _rel(y["rho"], x["rho"]) < 1e-13
+        assert _rel(y["h_star"], x["h_star"]) < 1e-12
+        assert abs(y["log_z"] - x["log_z"]) < 1e-12
+    for ca, cb in zip(a["alpha"], b["alpha"]):
+        assert np.abs(ca[:10] - cb[:10]).max() < 1e-12
