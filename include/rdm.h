@@ -55,12 +55,14 @@ typedef enum {
   RDM_E_NOMEM = -2,     /* not enough device memory even for the two-pass plan */
   RDM_E_DEVICE = -3,    /* a HIP runtime call failed                         */
   RDM_E_NONFINITE = -4, /* a non-finite value appeared during the solve      */
-  RDM_E_BUSY = -5       /* serving queue full                                */
+  RDM_E_BUSY = -5,      /* serving queue full                                */
+  RDM_E_CANCELLED = -6  /* serving: the request was cancelled                */
 } rdm_status;
 
 enum { RDM_FP64 = 0, RDM_MIXED = 1 };                 /* rdm_options.precision */
 enum { RDM_AUTO = 0, RDM_STORED_Q = 1, RDM_TWO_PASS = 2 };  /* rdm_options.mode */
 enum { RDM_PER_COLUMN = 0, RDM_BLOCK = 1, RDM_METHOD_AUTO = 2 };  /* rdm_options.method */
+enum { RDM_APPLY_AUTO = 0, RDM_APPLY_HOPS = 1, RDM_APPLY_TRANSFORM = 2 };  /* rdm_hamiltonian_create_ex */
 
 /* One two-site term: jx sx_i sx_j + jy sy_i sy_j + jz sz_i sz_j (Pauli),
  * eqn:Ht.  0 <= i, j < N, i != j; (i, j) and (j, i) denote the same pair. */
@@ -143,6 +145,22 @@ typedef struct {
 rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm_coupling* couplings,
                                   int64_t n_couplings, const double* hx, const double* hz,
                                   rdm_hamiltonian** out);
+/* As rdm_hamiltonian_create, choosing how products with H_t and H_b are
+ * computed (the results agree to rounding either way):
+ *   RDM_APPLY_HOPS: gathers of the partner rows idx ^ f from hop tables;
+ *   RDM_APPLY_TRANSFORM: on 16..22 sites, H = D_Z + W D_X W + T W D_Y W T
+ *     (W the Walsh-Hadamard transform, in whose basis XX couplings and
+ *     x-fields are diagonal, D_X; YY couplings are T (XX) T with
+ *     T = diag((-1)^floor(popcount(idx)/2)), D_Y), streamed in tiles;
+ *     other sizes use hop tables;
+ *   RDM_APPLY_AUTO (what rdm_hamiltonian_create does): the transform where
+ *     available, unless a hop table would read fewer partner rows per row
+ *     than the transform streams vectors (sparse operators with YY terms).
+ * rdm_hamiltonian_info reports the choice for H_t and H_b.  RDM_E_INVALID
+ * for another value of apply. */
+rdm_status rdm_hamiltonian_create_ex(int32_t n_s, int32_t n_b, const rdm_coupling* couplings,
+                                     int64_t n_couplings, const double* hx, const double* hz,
+                                     int32_t apply, rdm_hamiltonian** out);
 void rdm_hamiltonian_destroy(rdm_hamiltonian* h);
 
 /* H_s, the system part of the split H_t = H_s (x) I + I (x) H_b + H_sb
@@ -158,10 +176,9 @@ rdm_status rdm_system_hamiltonian(const rdm_hamiltonian* h, double* out);
  * apply kernel stages in LDS for H_t / H_b (hops grouped by their flip bits
  * above a 256-row tile; the own tile plus every tile read by at least three
  * hops), [11] / [12] hops it gathers directly from memory instead, [13] /
- * [14] 1 when H_t / H_b is applied as D_Z + W D_X W instead (every
- * off-diagonal term X-type, i.e. J^y = 0 on every pair, and 16..22 sites; W
- * is the Walsh-Hadamard transform, in whose basis X-type terms are diagonal).
- * out: host array of 15 int64. */
+ * [14] 1 when H_t / H_b is applied by the transform (rdm_hamiltonian_create_ex)
+ * instead, [15] / [16] 1 when that transform has a YY part.
+ * out: host array of 17 int64. */
 rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* out);
 
 /* Full solve (blocking; results on the host).  beta: host array of n_beta
@@ -386,6 +403,14 @@ rdm_status rdm_server_poll(rdm_server* s, uint64_t ticket, int32_t* done, rdm_st
 /* Block until the ticket completes, then retire it.  RDM_E_INVALID for an
  * unknown or retired ticket, or one another thread already waits for. */
 rdm_status rdm_server_wait(rdm_server* s, uint64_t ticket, rdm_status* status);
+/* Cancel a request: one still queued completes at once, one resident leaves
+ * the engine at its next step boundary (its memory returns once the steps
+ * already launched for it are done), one being finished is finished unless
+ * it still has a regeneration pass to run.  A cancelled request completes
+ * with status RDM_E_CANCELLED and its result buffers are not written.
+ * RDM_OK also when the request had completed already (its status tells);
+ * RDM_E_INVALID for an unknown or retired ticket or one being waited for. */
+rdm_status rdm_server_cancel(rdm_server* s, uint64_t ticket);
 /* Counters: out[0] submitted, [1] completed, [2] active, [3] queued, [4] engine
  * steps, [5] peak active, [6] peak device bytes.  host out, 7 int64. */
 rdm_status rdm_server_stats(rdm_server* s, int64_t* out);

@@ -71,13 +71,18 @@ def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_l
     return o
 
 
+APPLY_KINDS = {"auto": 0, "hops": 1, "transform": 2}
+
+
 class Hamiltonian:
     """H_t of eqn:Ht (and its bath part) on n_s system + n_b bath spins.
 
     couplings: iterable of (i, j, jx, jy, jz); hx, hz: coefficients of the
-    one-site Pauli terms (length n_s + n_b)."""
+    one-site Pauli terms (length n_s + n_b).  apply: how products with H are
+    computed -- "auto", "hops" (hop-table gathers) or "transform" (the
+    Walsh-Hadamard form on 16..22 sites)."""
 
-    def __init__(self, n_s: int, n_b: int, couplings: Iterable, hx=None, hz=None):
+    def __init__(self, n_s: int, n_b: int, couplings: Iterable, hx=None, hz=None, apply: str = "auto"):
         cps = list(couplings)
         arr = (_lib.Coupling * max(len(cps), 1))()
         for t, (i, j, jx, jy, jz) in enumerate(cps):
@@ -89,23 +94,24 @@ class Hamiltonian:
             if f is not None and f.shape != (n,):
                 raise ValueError("fields must have length n_s + n_b")
         out = C.c_void_p()
-        _check(LIB.rdm_hamiltonian_create(n_s, n_b, arr, len(cps),
-                                          None if self._hx is None else _dptr(self._hx),
-                                          None if self._hz is None else _dptr(self._hz),
-                                          C.byref(out)), "rdm_hamiltonian_create")
+        _check(LIB.rdm_hamiltonian_create_ex(n_s, n_b, arr, len(cps),
+                                             None if self._hx is None else _dptr(self._hx),
+                                             None if self._hz is None else _dptr(self._hz),
+                                             APPLY_KINDS[apply], C.byref(out)), "rdm_hamiltonian_create_ex")
         self.handle = out.value
         self.n_s, self.n_b, self.n = n_s, n_b, n
 
     @classmethod
-    def from_instance(cls, inst) -> "Hamiltonian":
-        return cls(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+    def from_instance(cls, inst, apply: str = "auto") -> "Hamiltonian":
+        return cls(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz, apply=apply)
 
     def info(self) -> dict:
-        out = (C.c_int64 * 15)()
+        out = (C.c_int64 * 17)()
         _check(LIB.rdm_hamiltonian_info(self.handle, out), "rdm_hamiltonian_info")
         keys = ["n", "n_s", "n_b", "hops_uniform", "hops_parity", "diag_terms",
                 "bath_hops_uniform", "bath_hops_parity", "bath_diag_terms", "tile_groups",
-                "bath_tile_groups", "direct_hops", "bath_direct_hops", "transform", "bath_transform"]
+                "bath_tile_groups", "direct_hops", "bath_direct_hops", "transform", "bath_transform",
+                "transform_yy", "bath_transform_yy"]
         return dict(zip(keys, list(out)))
 
     def system_matrix(self) -> np.ndarray:
@@ -403,6 +409,12 @@ class Server:
         st = C.c_int32()
         _check(LIB.rdm_server_wait(self.handle, ticket, C.byref(st)), "rdm_server_wait")
         return self._finish(ticket, st.value)
+
+    def cancel(self, ticket: int) -> None:
+        """Cancel a request (it completes with status RDM_E_CANCELLED unless
+        it had completed already); its result is still retrieved with wait
+        or poll."""
+        _check(LIB.rdm_server_cancel(self.handle, ticket), "rdm_server_cancel")
 
     def _finish(self, ticket, status):
         rb, _, _ = self._pending.pop(ticket)

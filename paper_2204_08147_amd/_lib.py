@@ -12,13 +12,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librdm.so")
 
 RDM_OK, RDM_E_INVALID, RDM_E_NOMEM, RDM_E_DEVICE, RDM_E_NONFINITE, RDM_E_BUSY = 0, -1, -2, -3, -4, -5
+RDM_E_CANCELLED = -6
 RDM_FP64, RDM_MIXED = 0, 1
 RDM_AUTO, RDM_STORED_Q, RDM_TWO_PASS = 0, 1, 2
 RDM_PER_COLUMN, RDM_BLOCK, RDM_METHOD_AUTO = 0, 1, 2
+RDM_APPLY_AUTO, RDM_APPLY_HOPS, RDM_APPLY_TRANSFORM = 0, 1, 2
 DIAG_FIXED = 16
 
 STATUS_NAMES = {0: "RDM_OK", -1: "RDM_E_INVALID", -2: "RDM_E_NOMEM", -3: "RDM_E_DEVICE",
-                -4: "RDM_E_NONFINITE", -5: "RDM_E_BUSY"}
+                -4: "RDM_E_NONFINITE", -5: "RDM_E_BUSY", -6: "RDM_E_CANCELLED"}
 
 
 class Coupling(C.Structure):
@@ -60,6 +62,9 @@ SIGNATURES = [
     ("rdm_hamiltonian_create", C.c_int32,
      [C.c_int32, C.c_int32, C.POINTER(Coupling), C.c_int64, C.POINTER(C.c_double),
       C.POINTER(C.c_double), C.POINTER(C.c_void_p)]),
+    ("rdm_hamiltonian_create_ex", C.c_int32,
+     [C.c_int32, C.c_int32, C.POINTER(Coupling), C.c_int64, C.POINTER(C.c_double),
+      C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_void_p)]),
     ("rdm_hamiltonian_destroy", None, [C.c_void_p]),
     ("rdm_hamiltonian_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("rdm_system_hamiltonian", C.c_int32, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -105,6 +110,7 @@ SIGNATURES = [
     ("rdm_server_poll", C.c_int32,
      [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     ("rdm_server_wait", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),
+    ("rdm_server_cancel", C.c_int32, [C.c_void_p, C.c_uint64]),
     ("rdm_server_stats", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("rdm_server_destroy", None, [C.c_void_p]),
     ("rdm_last_error", C.c_char_p, []),

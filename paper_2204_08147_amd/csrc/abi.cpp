@@ -389,16 +389,23 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
   std::vector<Seg> one{sg};
   const Launch L = assign_tiles(one);
   sg = one[0];
-  static_assert(sizeof(Seg) <= 256, "segment descriptor must fit its 256-byte buffer");
+  // the segment descriptor, then the scratch block of a YY transform part
+  const size_t dbytes = align_up(sizeof(Seg));
+  const size_t ybytes = sg.xy ? g.blk * (precision == RDM_FP64 ? 8 : 4) : 0;
   char* d = nullptr;
-  RDM_HIP(hipMalloc(&d, 256));
+  RDM_HIP(hipMalloc(&d, dbytes + ybytes));
+  if (sg.xy) sg.Y = d + dbytes;
   rdm_status r = RDM_OK;
   auto run = [&]() -> rdm_status {
     RDM_HIP(hipMemcpyAsync(d, &sg, sizeof(Seg), hipMemcpyHostToDevice, st));
-    const bool deep = sg.nbits > kXzShallowMaxBits;
+    const int deep = xz_geom(sg.nbits);
     for (int pass = 0; pass <= 2; ++pass)
       RDM_HIP(precision == RDM_FP64 ? launch_xz_pass<double>(pass, (Seg*)d, 1, L.xz, st, deep)
                                     : launch_xz_pass<float>(pass, (Seg*)d, 1, L.xz, st, deep));
+    if (sg.xy)
+      for (int pass : {6, 7, 8})
+        RDM_HIP(precision == RDM_FP64 ? launch_xz_pass<double>(pass, (Seg*)d, 1, L.xz, st, deep)
+                                      : launch_xz_pass<float>(pass, (Seg*)d, 1, L.xz, st, deep));
     RDM_HIP(precision == RDM_FP64 ? launch_apply<double>((Seg*)d, 1, L.apply, g.S, st)
                                   : launch_apply<float>((Seg*)d, 1, L.apply, g.S, st));
     RDM_HIP(hipStreamSynchronize(st));

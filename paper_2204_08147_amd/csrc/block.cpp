@@ -55,6 +55,9 @@ rdm_status block_plan(BlockPlan& bp, const rdm_hamiltonian* h, int n_beta, int n
   size_t off = 0;
   bp.o_Q = off; off = align_up(off + 3 * bp.blk * sb);
   bp.o_R = off; off = align_up(off + bp.blk * sb);
+  // scratch block of the YY part of a transform apply
+  bp.o_Y = off;
+  if (needs_ybuf(h, 0)) off = align_up(off + bp.blk * sb);
   bp.o_part = off; off = align_up(off + (size_t)bp.n_rt * bp.G * NE * 8);
   bp.o_mats = off; off = align_up(off + (size_t)BM_COUNT * bp.G * NE * 8);
   bp.o_ah = off; off = align_up(off + (size_t)bp.k * bp.G * NE * 8);
@@ -63,7 +66,7 @@ rdm_status block_plan(BlockPlan& bp, const rdm_hamiltonian* h, int n_beta, int n
   // geometry of the plain apply segments (no storage of their own)
   size_t dummy = 0;
   plan_seg(bp.apply, h->n, bp.cpad, 1, prec, 1, 0, 1, dummy);
-  plan_seg(bp.bath, h->n_b, n_v, bp.kb, prec, 0, 0, 2, off);
+  plan_seg(bp.bath, h->n_b, n_v, bp.kb, prec, 0, 0, 2, off, needs_ybuf(h, 1));
   bp.bytes = bp.header + off;
   if (budget != 0 && bp.bytes > budget) {
     set_error("block solve needs " + std::to_string(bp.bytes) + " device bytes, budget " +
@@ -101,6 +104,7 @@ rdm_status run_block(const BlockPlan& bp, const OpDevice* op_t, char* ws, char* 
     sg.blk = bp.blk;
     sg.Q = base + bp.o_Q + (size_t)r * bp.blk * sb;
     sg.R = base + bp.o_R;
+    sg.Y = sg.xy ? base + bp.o_Y : nullptr;
     std::vector<Seg> one{sg};
     L = assign_tiles(one);
     sg = one[0];
@@ -136,7 +140,7 @@ rdm_status run_block(const BlockPlan& bp, const OpDevice* op_t, char* ws, char* 
   // transform operators: the blocks live in the orthogonal basis W_lo Q / 64
   // (inner products unchanged, so A_j, B_j and the quadrature are too), and
   // each product H Q_j takes two streaming passes instead of three
-  const bool deep = bp.h->n > kXzShallowMaxBits;
+  const int deep = xz_geom(bp.h->n);
   if (op_t->xz) RDM_HIP(launch_xz_pass<T>(3, dsegs, 1, L.xz, st, deep));
   for (int j = 1; j <= bp.k; ++j) {
     const Seg* sj = dsegs + (j - 1) % 3;
@@ -144,6 +148,8 @@ rdm_status run_block(const BlockPlan& bp, const OpDevice* op_t, char* ws, char* 
     RDM_HIP(launch_apply<T>(sj, 1, L.apply, 1, st));
     if (op_t->xz)
       for (int pass = 4; pass <= 5; ++pass) RDM_HIP(launch_xz_pass<T>(pass, sj, 1, L.xz, st, deep));
+    if (op_t->xz && op_t->xy)
+      for (int pass : {9, 7, 10}) RDM_HIP(launch_xz_pass<T>(pass, sj, 1, L.xz, st, deep));
     if (tm) RDM_HIP(tm->apply.mark(st));
     if (tm) RDM_HIP(tm->norm.mark(st));
     RDM_HIP(launch_block_update<T>(dbs, bp.ds, BLK_A, j, bp.n_rt, bp.n_cb, st));

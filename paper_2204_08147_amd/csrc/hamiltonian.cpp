@@ -108,12 +108,40 @@ void compile(const rdm_hamiltonian& h, int first_site, OpTables& t) {
     for (int h = gr.start; uni && h < gr.start + gr.n1; ++h) uni = (t.g_m[h] & lo_mask) == 0u;
     gr.tile_uniform = uni ? 1 : 0;
   }
-  // an operator whose hops are all X-type (no YY part, so every coefficient
-  // is independent of the bits) is D_Z + W D_X W / 2^N with W the Hadamard
-  // transform; D_X has one term per hop, c (1 - 2 parity(s & f))
-  t.xz = t.pf.empty() && !t.uf.empty() && t.nbits >= kXzMinBits && t.nbits <= kXzMaxBits;
-  if (t.xz)
-    for (size_t i = 0; i < t.uf.size(); ++i) t.xterms.push_back(DiagTerm{t.uf[i], 0, std::ldexp(t.uc[i], -t.nbits)});
+  // Transform form (Section "Spin systems": products of site Paulis).  With
+  // W the unnormalised Walsh-Hadamard transform on all nbits bits (W W =
+  // 2^N I), W Z_i Z_j W = 2^N X_i X_j and W Z_i W = 2^N X_i, so the XX
+  // couplings and x-fields are W D_X W with D_X(s) = 2^-N sum c (1 - 2
+  // parity(s & f)).  For a pair, Y_i Y_j = T X_i X_j T with
+  // T = diag((-1)^floor(popcount(idx)/2)) (flipping two equal bits moves the
+  // popcount by 2, two different bits leave it), so the YY couplings are
+  // T W D_Y W T with D_Y built the same way from J^y.
+  bool any_x = false, any_y = false;
+  std::vector<DiagTerm> xt, yt;
+  for (const auto& kv : pairs) {
+    const rdm_coupling& c = kv.second;
+    const uint32_t f = (1u << (n - 1 - c.i)) | (1u << (n - 1 - c.j));
+    if (c.jx != 0.0) xt.push_back(DiagTerm{f, 0, std::ldexp(c.jx, -t.nbits)});
+    if (c.jy != 0.0) yt.push_back(DiagTerm{f, 0, std::ldexp(c.jy, -t.nbits)});
+  }
+  for (int s = first_site; s < n; ++s)
+    if (h.hx[s] != 0.0) xt.push_back(DiagTerm{1u << (n - 1 - s), 0, std::ldexp(h.hx[s], -t.nbits)});
+  any_x = !xt.empty();
+  any_y = !yt.empty();
+  const bool in_range = t.nbits >= kXzMinBits && t.nbits <= kXzMaxBits && (any_x || any_y);
+  // a hop-table step streams about 6 vectors plus one per partner tile it
+  // stages and one per hop it gathers; a transform step streams 8 vectors,
+  // 13 with a YY part: sparse operators with YY terms keep the hop tables
+  const int partners = (int)(t.groups.size() - 1 + thin[0].size() + thin[1].size() + thin[2].size());
+  bool use = false;
+  if (h.apply == RDM_APPLY_TRANSFORM) use = in_range;
+  else if (h.apply == RDM_APPLY_AUTO) use = in_range && (!any_y || 6 + partners >= 13);
+  t.xz = use;
+  t.xy = use && any_y;
+  if (use) {
+    t.xterms = xt;
+    t.yterms = yt;
+  }
   for (int k = 0; k < 3; ++k) {
     t.nt[k] = (int)thin[k].size();
     for (const H& x : thin[k]) {
@@ -150,14 +178,25 @@ rdm_status upload(const OpTables& t, OpDevice& d, hipStream_t st) {
                            hipMemcpyHostToDevice, st));
   RDM_HIP(launch_diag<T>((const DiagTerm*)d.dterms, (int)t.diag.size(), (T*)d.diag, t.nbits, st));
   d.xz = t.xz;
+  d.xy = t.xy;
   if (t.xz) {
-    RDM_HIP(hipMalloc(&d.xterms, t.xterms.size() * sizeof(DiagTerm)));
+    // D_X and D_Y of deep operators (21, 22 bits) in the order of the strided tiles that
+    // read them (an operator without XX / x terms gets D_X = 0)
+    RDM_HIP(hipMalloc(&d.xterms, std::max<size_t>(16, t.xterms.size() * sizeof(DiagTerm))));
     RDM_HIP(hipMalloc(&d.dx, dim * sizeof(T)));
-    RDM_HIP(hipMemcpyAsync(d.xterms, t.xterms.data(), t.xterms.size() * sizeof(DiagTerm),
-                           hipMemcpyHostToDevice, st));
-    // D_X of deep operators in the order of the strided tiles that read it
+    if (!t.xterms.empty())
+      RDM_HIP(hipMemcpyAsync(d.xterms, t.xterms.data(), t.xterms.size() * sizeof(DiagTerm),
+                             hipMemcpyHostToDevice, st));
     RDM_HIP(launch_diag<T>((const DiagTerm*)d.xterms, (int)t.xterms.size(), (T*)d.dx, t.nbits, st,
-                           t.nbits > kXzShallowMaxBits));
+                           xz_geom(t.nbits) == XG_DEEP));
+  }
+  if (t.xy) {
+    RDM_HIP(hipMalloc(&d.yterms, t.yterms.size() * sizeof(DiagTerm)));
+    RDM_HIP(hipMalloc(&d.dy, dim * sizeof(T)));
+    RDM_HIP(hipMemcpyAsync(d.yterms, t.yterms.data(), t.yterms.size() * sizeof(DiagTerm),
+                           hipMemcpyHostToDevice, st));
+    RDM_HIP(launch_diag<T>((const DiagTerm*)d.yterms, (int)t.yterms.size(), (T*)d.dy, t.nbits, st,
+                           xz_geom(t.nbits) == XG_DEEP));
   }
   RDM_HIP(hipStreamSynchronize(st));
   d.ngroups = (int)t.groups.size();
@@ -172,6 +211,8 @@ void free_dev(rdm::OpDevice& d) {
   if (d.diag) (void)hipFree(d.diag);
   if (d.dx) (void)hipFree(d.dx);
   if (d.xterms) (void)hipFree(d.xterms);
+  if (d.dy) (void)hipFree(d.dy);
+  if (d.yterms) (void)hipFree(d.yterms);
   if (d.dterms) (void)hipFree(d.dterms);
   d = rdm::OpDevice{};
 }
@@ -222,11 +263,21 @@ using namespace rdm;
 extern "C" rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm_coupling* couplings,
                                              int64_t n_couplings, const double* hx, const double* hz,
                                              rdm_hamiltonian** out) {
+  return rdm_hamiltonian_create_ex(n_s, n_b, couplings, n_couplings, hx, hz, RDM_APPLY_AUTO, out);
+}
+
+extern "C" rdm_status rdm_hamiltonian_create_ex(int32_t n_s, int32_t n_b, const rdm_coupling* couplings,
+                                                int64_t n_couplings, const double* hx, const double* hz,
+                                                int32_t apply, rdm_hamiltonian** out) {
   if (!out) {
     set_error("rdm_hamiltonian_create: out is NULL");
     return RDM_E_INVALID;
   }
   *out = nullptr;
+  if (apply != RDM_APPLY_AUTO && apply != RDM_APPLY_HOPS && apply != RDM_APPLY_TRANSFORM) {
+    set_error("rdm_hamiltonian_create_ex: apply must be RDM_APPLY_AUTO, RDM_APPLY_HOPS or RDM_APPLY_TRANSFORM");
+    return RDM_E_INVALID;
+  }
   if (n_s < 1 || n_s > 3 || n_b < 1 || n_s + n_b > 28) {
     set_error("rdm_hamiltonian_create: need 1 <= n_s <= 3, n_b >= 1, n_s + n_b <= 28");
     return RDM_E_INVALID;
@@ -254,6 +305,7 @@ extern "C" rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm
     }
   }
   auto* h = new rdm_hamiltonian();
+  h->apply = apply;
   h->n_s = n_s;
   h->n_b = n_b;
   h->n = n;
@@ -292,6 +344,7 @@ extern "C" rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* ou
     out[9 + w] = (int64_t)h->op[w].groups.size();
     out[11 + w] = (int64_t)h->op[w].t_f.size();
     out[13 + w] = h->op[w].xz ? 1 : 0;
+    out[15 + w] = h->op[w].xy ? 1 : 0;
   }
   return RDM_OK;
 }

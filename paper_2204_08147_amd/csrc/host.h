@@ -38,10 +38,11 @@ struct OpTables {
   std::vector<uint32_t> t_f, t_m;
   std::vector<double> t_cs, t_cd;
   int nt[3] = {0, 0, 0};
-  // transform apply (only X-type off-diagonal terms, kXzMinBits..kXzMaxBits
-  // bits): D_X terms, coefficients already scaled by 2^-nbits
-  bool xz = false;
-  std::vector<DiagTerm> xterms;
+  // transform apply (kXzMinBits..kXzMaxBits bits): D_X terms (XX couplings
+  // and x-fields) and D_Y terms (YY couplings), coefficients already scaled
+  // by 2^-nbits; xy when there are D_Y terms
+  bool xz = false, xy = false;
+  std::vector<DiagTerm> xterms, yterms;
 };
 
 // Device copy of an operator's tables in one precision.
@@ -55,15 +56,18 @@ struct OpDevice {
   void* diag = nullptr;
   void* dterms = nullptr;
   int ngroups = 0;
-  bool xz = false;
+  bool xz = false, xy = false;
   void* dx = nullptr;      // D_X / 2^N (transform apply); strided-tile order above 20 bits
+  void* dy = nullptr;      // D_Y / 2^N, same order (operators with YY couplings)
   void* xterms = nullptr;
+  void* yterms = nullptr;
 };
 
 }  // namespace rdm
 
 struct rdm_hamiltonian {
   int n_s = 0, n_b = 0, n = 0;
+  int apply = RDM_APPLY_AUTO;    // apply kind requested at creation
   std::vector<rdm_coupling> couplings;
   std::vector<double> hx, hz;
   rdm::OpTables op[2];           // [0] H_t, [1] H_b

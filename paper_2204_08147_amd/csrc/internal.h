@@ -31,10 +31,22 @@ enum { START_SYSBATH = 0, START_BATH = 1, START_PRODUCT = 2 };
 constexpr int kTileBits = 8;       // the apply stages 2^8 = kBlock-row partner tiles in LDS
 constexpr int kXzTileBits = 12;    // transform apply: 4096-element tiles ...
 constexpr int kXzRegs = 16;        // ... as kBlock lanes x 16 registers
-constexpr int kXzMinBits = 16;     // operators on 16..22 bits use the transform apply; above
-constexpr int kXzMaxBits = 22;     // 22 bits a strided tile's row runs (16 or 32 bytes) make
-                                   // the hop tables faster
-constexpr int kXzShallowMaxBits = 20;  // up to 8 high bits: strided tiles of 16-row runs
+constexpr int kXzMinBits = 16;     // operators on 16..28 bits can use the transform apply
+constexpr int kXzMaxBits = 28;
+// Geometry of the strided passes over the N - 12 high bits:
+//   shallow (up to 20 bits): one pass, tiles of every high-bit value and runs
+//     of at least 16 consecutive rows;
+//   deep (21, 22 bits): one pass, runs of 8 or 4 rows (a third LDS exchange);
+//   split (23 bits and more): the high bits in two groups A (bits 12 ..
+//     12+a-1) and B (the rest), W_hi D W_hi = W_A (W_B D W_B) W_A as three
+//     passes whose tiles keep runs of at least 16 rows.
+constexpr int kXzShallowMaxBits = 20;
+constexpr int kXzDeepMaxBits = 22;
+enum { XG_SHALLOW = 0, XG_DEEP = 1, XG_SPLIT = 2 };
+__host__ __device__ inline int xz_geom(int nbits) {
+  return nbits <= kXzShallowMaxBits ? XG_SHALLOW : nbits <= kXzDeepMaxBits ? XG_DEEP : XG_SPLIT;
+}
+__host__ __device__ inline int xz_split_a(int nbits) { return (nbits - 12) / 2; }  // bits in group A
 constexpr int kFatGroup = 3;       // partner tiles read by at least this many hops go through LDS
 
 // One off-diagonal term of H as the apply sees it: row idx couples to the
@@ -93,10 +105,14 @@ struct Seg {
   int32_t ap_base;     // first workgroup of this segment in a (256-row) apply launch
   int32_t ap_rows;     // partial-sum rows the apply writes (row tiles of its kind)
   int32_t nm_rows;     // partial-sum rows the norm step writes
-  int32_t xz;          // 1: transform apply (D_Z + W D_X W), 0: hop tables
+  int32_t xz;          // 1: transform apply (D_Z + W D_X W [+ T W D_Y W T]), 0: hop tables
   int32_t x_tiles;     // transform apply: tiles of 2^kXzTileBits rows
   int32_t x_base;      // transform apply: first workgroup of this segment
+  int32_t xy;          // transform apply with a YY part (D_Y, the block Y)
+  int32_t pad_xy;
   const void* dx;      // transform apply: D_X / 2^N in T (tile order above 20 bits)
+  const void* dy;      // transform apply: D_Y / 2^N in T, same order (xy segments)
+  void* Y;             // xy segments: one block of dim x cpad for the YY part
   uint64_t seed;
   uint64_t blk;        // elements per vector block = dim * cpad
   void* Q;
@@ -188,21 +204,31 @@ hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStre
 // pass 0, 1 or 2 of the plain transform apply Y = H X (MODE_PLAIN segments
 // with xz = 1); passes 3 (once: X^ = W_lo X / 64 in place), 4 and 5 the same
 // product on blocks kept as X^, giving R = W_lo H X / 64; the strided pass
-// (1 or 4) on the segments of more than kXzShallowMaxBits bits if deep, else
-// on the others
+// (1, 4 or 7) on the segments of geometry geo only (split: as three
+// launch_xz_split passes).  The YY part (xy segments, block Y as scratch): passes
+// 6 (Y = W_lo T X), 7 (Y = W_hi D_Y W_hi Y), 8 (R += T W_lo Y) after 0-2, or
+// 9 (Y = W_lo T W_lo X^ / 64), 7, 10 (R += W_lo T W_lo Y / 64) after 4-5
 template <typename T>
-hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st, bool deep = false);
+hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st, int geo = XG_SHALLOW);
+// The strided passes of split segments (three launches for one strided pass
+// of the other geometries): op 0: R = W_A R; 1: R = W_B D_X W_B R; 2: Y =
+// W_A Y; 3: Y = W_B D_Y W_B Y; 4: R = L W_A X (X the block Q, L = 4096).
+template <typename T>
+hipError_t launch_xz_split(int op, const Seg* segs, int nseg, int ntiles, hipStream_t st);
 // Lanczos step over the segments with xz = 1, basis kept in the low-bit
 // Hadamard basis: pass 0 = start block (once per run), 1 = norm step + high
-// transform, 2 = low transforms + recurrence.  Pass 1 runs on the
-// MODE_REGEN segments if regen, else on the others, and on the segments of
-// more than kXzShallowMaxBits bits if deep, else on the others.  boff: first
-// transform tile.
+// transform (split segments: the norm step and W_A only), 2 = low transforms
+// + recurrence.  Pass 1 runs on the MODE_REGEN segments if regen, else on the
+// others, and on the segments of geometry geo only.  boff: first transform
+// tile.
 template <typename T>
 hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff,
-                             hipStream_t st, bool deep = false);
+                             hipStream_t st, int geo = XG_SHALLOW, bool xy = false);
 // Recombination weights of a segment whose basis is kept as W_lo u: L^-1/2
 constexpr double kXzBasisScale = 1.0 / (1 << (kXzTileBits / 2));
+// Lanczos-step passes of the YY part (xy segments): 3 = Y <- W_lo T W_lo u~ / L
+// (contiguous), 4 = Y <- W_hi D_Y W_hi Y (strided; deep variant as for pass 1);
+// pass 2 then adds W_lo T W_lo Y to the step's residual (xy variant)
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st);

@@ -136,6 +136,13 @@ __device__ __forceinline__ const CONST_AS CSeg& cseg(const Seg* segs, int i) {
 
 __device__ __forceinline__ float fma_s(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_s(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename V>
+__device__ __forceinline__ V fma_v(V a, V b, V c) {
+  V r;
+#pragma unroll
+  for (int e = 0; e < (int)(sizeof(V) / sizeof(a[0])); ++e) r[e] = fma_s(a[e], b[e], c[e]);
+  return r;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -652,7 +659,7 @@ __device__ __forceinline__ Tile xz_tile_of(const Seg* segs, int nseg, int b, boo
   }
   int lt = b - cs[lo].x_base;
   const int nrt = cs[lo].x_tiles;
-  if (strided && cs[lo].nbits > kXzTileBits + 9) {
+  if (strided && cs[lo].nbits > kXzTileBits + 9 && cs[lo].nbits <= kXzDeepMaxBits) {
     // more than 9 high bits: a strided tile reads runs of fewer than 8 rows
     // (under 128 bytes), and 128 / (16 * 2^lrb) neighbouring tiles share each
     // cache line.  Workgroups go round-robin to the 8 XCDs, so the k-th
@@ -716,6 +723,117 @@ __device__ __forceinline__ void xz_high_transform(V (&v)[kXzRegs], V* lds, const
   xz_bfly(v, 0xF);
 }
 
+// The YY twist T = diag(t(idx)), t = (-1)^floor(popcount(idx)/2): Y_i Y_j =
+// T X_i X_j T for every pair, so the YY couplings are T W D_Y W T.
+__device__ __forceinline__ bool yy_twist_neg(uint32_t row) { return (__builtin_popcount(row) >> 1) & 1u; }
+
+template <typename T, typename V>
+__device__ __forceinline__ void yy_twist(V (&v)[kXzRegs], uint32_t row0, T scale) {
+  const uint32_t l = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) {
+    const bool neg = yy_twist_neg(row0 + xz_tau(0, l, q));
+    v[q] = (neg ? -scale : scale) * v[q];
+  }
+}
+
+// In-place strided pass buf = W_hi D W_hi buf on the strided tile t of a
+// segment (the row map and cache hints of the strided passes below).
+template <typename T, bool DEEP>
+__device__ __forceinline__ void xz_strided_inplace(const CONST_AS CSeg& sg, const Tile& t, typename PanelT<T>::V* buf,
+                                                   const T* dd, typename PanelT<T>::V* lds) {
+  using V = typename PanelT<T>::V;
+  const uint32_t l = threadIdx.x;
+  const int hb = sg.nbits - kXzTileBits;
+  const int lrb = kXzTileBits - hb;
+  const uint32_t lrm = (1u << lrb) - 1u;
+  const uint32_t base = (uint32_t)t.rtile << lrb;
+  auto row_of = [&](uint32_t tau) -> uint32_t {
+    return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
+  };
+  V v[kXzRegs];
+  auto run = [&](auto nt_tag) {
+    constexpr bool NT = decltype(nt_tag)::value;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_sel<NT>((const V*)buf, row_of(xz_tau(0, l, q)));
+    xz_high_transform<DEEP>(v, lds, dd, t.rtile, lrb, row_of);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg_sel<NT>(buf, row_of(xz_tau(0, l, q)), v[q]);
+  };
+  if (!DEEP || lrb >= 3) run(std::true_type{});
+  else run(std::false_type{});
+}
+
+// Transform over one group of high bits on a split tile held in arrangement
+// 0: the group's g bits are the tau bits lrb..11 (lrb = 12 - g >= 4), so the
+// butterflies act on arrangement 0 (tau bits 8..11) and on the bits of 4..7
+// at or above lrb (arrangement 2), as in shallow tiles.  WITH_D: the sandwich
+// W_G D W_G with D read in row order through row_of; otherwise W_G alone.
+template <bool WITH_D, typename T, typename V, typename RowOf>
+__device__ __forceinline__ void xz_group_transform(V (&v)[kXzRegs], V* lds, const T* dd, int lrb, RowOf row_of) {
+  const uint32_t l = threadIdx.x;
+  const int m2 = 0xF & ~((1 << (lrb - 4)) - 1);
+  xz_bfly(v, 0xF);
+  xz_rearrange(v, lds, 0, 2);
+  xz_bfly(v, m2);
+  if (WITH_D) {
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dd, row_of(xz_tau(2, l, q))) * v[q];
+    xz_bfly(v, m2);
+  }
+  xz_rearrange(v, lds, 2, 0);
+  if (WITH_D) xz_bfly(v, 0xF);
+}
+
+// Row of tau in a split tile of group A (B = false: bits 12 .. 12+a-1) or B
+// (bits 12+a .. N-1) of a segment on nbits bits; the tile index rt holds the
+// other group's bits above the g low-rest bits lrb..11 of the row.
+struct SplitRows {
+  int lrb;
+  uint32_t lrm, fixed;
+  int gshift;
+  __device__ __forceinline__ SplitRows(int nbits, bool B, uint32_t rt) {
+    const int a = xz_split_a(nbits);
+    const int g = B ? nbits - kXzTileBits - a : a;
+    lrb = kXzTileBits - g;
+    lrm = (1u << lrb) - 1u;
+    const uint32_t lowrest = rt & ((1u << g) - 1u), other = rt >> g;
+    gshift = B ? kXzTileBits + a : kXzTileBits;
+    fixed = (lowrest << lrb) | (other << (B ? kXzTileBits : kXzTileBits + a));
+  }
+  __device__ __forceinline__ uint32_t operator()(uint32_t tau) const {
+    return ((tau >> lrb) << gshift) | fixed | (tau & lrm);
+  }
+};
+
+// The strided passes of split segments (ops of launch_xz_split), in place.
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_xz_split(const Seg* __restrict__ segs, int nseg) {
+  using V = typename PanelT<T>::V;
+  __shared__ V lds[1 << kXzTileBits];
+  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x);
+  const CONST_AS CSeg& sg = cseg(segs, t.seg);
+  if (xz_geom(sg.nbits) != XG_SPLIT) return;
+  if ((OP == 2 || OP == 3) && !sg.xy) return;
+  if (sg.mode != MODE_PLAIN && sg.stepc[0] > sg.k) return;
+  const uint64_t pstride = (uint64_t)1 << sg.nbits;
+  constexpr bool B = OP == 1 || OP == 3;
+  const SplitRows row_of(sg.nbits, B, (uint32_t)t.rtile);
+  V* buf = (V*)(OP == 2 || OP == 3 ? sg.Y : sg.R) + (uint64_t)t.panel0 * pstride;
+  const V* src = OP == 4 ? (const V*)sg.Q + (uint64_t)t.panel0 * pstride : buf;
+  const uint32_t l = threadIdx.x;
+  V v[kXzRegs];
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(src, row_of(xz_tau(0, l, q)));
+  xz_group_transform<B>(v, lds, (const T*)(OP == 3 ? sg.dy : sg.dx), row_of.lrb, row_of);
+  if (OP == 4) {
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = T(1 << kXzTileBits) * v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(buf, row_of(xz_tau(0, l, q)), v[q]);
+}
+
 // Plain transform apply Y = H X (MODE_PLAIN segments), H = D_Z + W D_X W:
 // phase 0: R = W_lo X (contiguous tiles); phase 1: R = W_hi D_X W_hi R
 // (strided tiles); phase 2: R = D_Z X + W_lo R (contiguous tiles).
@@ -739,7 +857,38 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
   const uint32_t l = threadIdx.x;
   V v[kXzRegs];
 
-  if (PHASE == 3) {
+  if (PHASE >= 6) {
+    // the YY part (xy segments): T W D_Y W T X = T W_lo (W_hi D_Y W_hi) W_lo T X
+    if (!sg.xy) return;
+    V* yb = (V*)sg.Y + (uint64_t)t.panel0 * pstride;
+    if (PHASE == 7) {
+      if (xz_geom(sg.nbits) != (DEEP ? XG_DEEP : XG_SHALLOW)) return;
+      xz_strided_inplace<T, DEEP>(sg, t, yb, (const T*)sg.dy, lds);
+      return;
+    }
+    if (PHASE == 6 || PHASE == 9) {
+      // 6: Y = W_lo T X;  9: Y = W_lo T W_lo X^ / 64 (= W_lo T X, X kept as X^)
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(ub, t.row0 + xz_tau(0, l, q));
+      if (PHASE == 9) xz_low_transform(v, lds);
+      yy_twist<T>(v, t.row0, PHASE == 9 ? T(1) / T(1 << (kXzTileBits / 2)) : T(1));
+      xz_low_transform(v, lds);
+#pragma unroll
+      for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(yb, t.row0 + xz_tau(0, l, q), v[q]);
+      return;
+    }
+    // 8: R += T W_lo Y;  10: R += W_lo T W_lo Y / 64
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt((const V*)yb, t.row0 + xz_tau(0, l, q));
+    xz_low_transform(v, lds);
+    yy_twist<T>(v, t.row0, PHASE == 10 ? T(1) / T(1 << (kXzTileBits / 2)) : T(1));
+    if (PHASE == 10) xz_low_transform(v, lds);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const uint32_t row = t.row0 + xz_tau(0, l, q);
+      stg_stream<true>(rb, row, ldg_nt((const V*)rb, row) + v[q]);
+    }
+  } else if (PHASE == 3) {
     // contiguous tile, in place on X
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(ub, t.row0 + xz_tau(0, l, q));
@@ -790,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
     // strided tile: tau = hi * Lr + lr  ->  row = hi * 4096 + rt * Lr + lr,
     // hb = N - 12 high bits (4 <= hb <= 8 shallow, 9 <= hb <= 12 DEEP;
     // operators go up to kXzMaxBits), Lr = 2^(12 - hb) >= 1
-    if ((sg.nbits > kXzShallowMaxBits) != DEEP) return;
+    if (xz_geom(sg.nbits) != (DEEP ? XG_DEEP : XG_SHALLOW)) return;
     const int hb = sg.nbits - kXzTileBits;
     const int lrb = kXzTileBits - hb;
     const uint32_t lrm = (1u << lrb) - 1u;
@@ -836,18 +985,24 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
 //     partial <u_j, r_j> = s sum d u^2 + <u~_j, w> / L
 // boff offsets blockIdx.x in the segments' transform tile numbering.
 // ---------------------------------------------------------------------------
-template <typename T, int PASS, bool REGEN, bool DEEP>
+template <typename T, int PASS, bool REGEN, int GEOM, bool XY = false>
 __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ segs, int nseg, int boff) {
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
+  constexpr bool DEEP = GEOM == XG_DEEP;
   __shared__ V lds[1 << kXzTileBits];
   __shared__ double red[4 * W];
-  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x + boff, PASS == 1 && DEEP);
+  const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x + boff, (PASS == 1 || PASS == 4) && DEEP);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   // pass 1 comes in variants (the regeneration pass needs more registers;
-  // DEEP for operators above kXzShallowMaxBits bits); each leaves the
-  // other variants' tiles alone
-  if (PASS == 1 && ((sg.mode == MODE_REGEN) != REGEN || (sg.nbits > kXzShallowMaxBits) != DEEP)) return;
+  // one per strided geometry), pass 2 in two (with and without a YY part);
+  // each leaves the other variants' tiles alone.  Passes 3 and 4 run on the
+  // segments with a YY part only (pass 4: shallow and deep; split segments
+  // take launch_xz_split).
+  if (PASS == 1 && ((sg.mode == MODE_REGEN) != REGEN || xz_geom(sg.nbits) != GEOM)) return;
+  if (PASS == 2 && (sg.xy != 0) != XY) return;
+  if ((PASS == 3 || PASS == 4) && !sg.xy) return;
+  if (PASS == 4 && xz_geom(sg.nbits) != GEOM) return;
   const int j = PASS == 0 ? 1 : sg.stepc[0];
   if (j > sg.k) return;
   const int cp = sg.cpad;
@@ -875,14 +1030,16 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
 
   if (PASS == 1) {
     // strided tile: tau = hi * Lr + lr  ->  row = hi * 4096 + rt * Lr + lr,
-    // hb = N - 12 high bits (4 <= hb <= 8 shallow, 9 <= hb <= 12 DEEP;
-    // operators go up to kXzMaxBits), Lr = 2^(12 - hb) >= 1
+    // hb = N - 12 high bits (4 <= hb <= 8 shallow, 9 <= hb <= 10 DEEP),
+    // Lr = 2^(12 - hb) >= 4; split segments: a tile of group A (SplitRows)
     const int hb = sg.nbits - kXzTileBits;
-    const int lrb = kXzTileBits - hb;
+    const SplitRows srows(sg.nbits, false, (uint32_t)t.rtile);
+    const int lrb = GEOM == XG_SPLIT ? srows.lrb : kXzTileBits - hb;
     const uint32_t lrm = (1u << lrb) - 1u;
     const uint32_t base = (uint32_t)t.rtile << lrb;
     auto row_of = [&](uint32_t tau) -> uint32_t {
-      return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
+      if constexpr (GEOM == XG_SPLIT) return srows(tau);
+      else return ((tau >> lrb) << kXzTileBits) | (base + (tau & lrm));
     };
     auto run = [&](auto nt_tag) {
       constexpr bool NT = decltype(nt_tag)::value;
@@ -937,7 +1094,8 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
       block_sum<W>(dsum, red, &tot);
       if (threadIdx.x < W)
         sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot * (double)inv_l;
-      xz_high_transform<DEEP>(v, lds, (const T*)sg.dx, t.rtile, lrb, row_of);
+      if constexpr (GEOM == XG_SPLIT) xz_group_transform<false>(v, lds, (const T*)nullptr, lrb, row_of);
+      else xz_high_transform<DEEP>(v, lds, (const T*)sg.dx, t.rtile, lrb, row_of);
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q) stg_sel<NT>(rb, row_of(xz_tau(0, l, q)), v[q]);
     };
@@ -946,22 +1104,62 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
     return;
   }
 
+  if (PASS == 3) {
+    // contiguous tile: Y = W_lo T W_lo u~_j / L = W_lo T u_j
+    const V* ub = (const V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
+    V* yb = (V*)sg.Y + (uint64_t)t.panel0 * pstride;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg(ub, t.row0 + xz_tau(0, l, q));
+    xz_low_transform(v, lds);
+    yy_twist<T>(v, t.row0, T(1) / T(1 << kXzTileBits));
+    xz_low_transform(v, lds);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(yb, t.row0 + xz_tau(0, l, q), v[q]);
+    return;
+  }
+  if (PASS == 4) {
+    // strided tile: Y = W_hi D_Y W_hi Y
+    xz_strided_inplace<T, DEEP>(sg, t, (V*)sg.Y + (uint64_t)t.panel0 * pstride, (const T*)sg.dy, lds);
+    return;
+  }
+
   // PASS 2: contiguous tile, row = row0 + tau
   const V* ub = (const V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
   const T* dg = (const T*)sg.diag;
   V w[kXzRegs];
   T d[kXzRegs];
-#pragma unroll
-  for (int q = 0; q < kXzRegs; ++q) {
-    const uint32_t row = t.row0 + xz_tau(0, l, q);
-    v[q] = ldg_nt(ub, row);
-    w[q] = ldg_nt((const V*)rb, row);
-    d[q] = ldg_s(dg, row);
-  }
   const V sc = scur_of<T, 1>(st, cp, t.panel0, 0, false);
   const V scl = sc * T(1 << kXzTileBits);
+  if (XY) {
+    // the YY part first: w = s W_lo T W_lo Y (= s W_lo (T W D_Y W T u_j)),
+    // then the XX part, w += s L R, with the tile of u~_j loaded afterwards
+    const V* yb = (const V*)sg.Y + (uint64_t)t.panel0 * pstride;
 #pragma unroll
-  for (int q = 0; q < kXzRegs; ++q) w[q] = scl * w[q];
+    for (int q = 0; q < kXzRegs; ++q) w[q] = ldg_nt(yb, t.row0 + xz_tau(0, l, q));
+    xz_low_transform(w, lds);
+    yy_twist<T>(w, t.row0, T(1));
+    xz_low_transform(w, lds);
+    // the loads below stay after the YY transforms (hoisted above them they
+    // would hold three tiles of registers at once and halve the occupancy)
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const uint32_t row = t.row0 + xz_tau(0, l, q);
+      w[q] = fma_v(scl, ldg_nt((const V*)rb, row), sc * w[q]);
+      v[q] = ldg_nt(ub, row);
+      d[q] = ldg_s(dg, row);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const uint32_t row = t.row0 + xz_tau(0, l, q);
+      v[q] = ldg_nt(ub, row);
+      w[q] = ldg_nt((const V*)rb, row);
+      d[q] = ldg_s(dg, row);
+    }
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) w[q] = scl * w[q];
+  }
   if (uprev) {
     const V bp = bps_of<T, 1>(st, cp, t.panel0, 0);
 #pragma unroll
@@ -1553,7 +1751,7 @@ __global__ __launch_bounds__(kBlock) void k_start_block(int ns_log, int nb, int 
 template <typename T>
 hipError_t launch_diag(const DiagTerm* terms, int nt, T* diag, int nbits, hipStream_t st, bool xz_tiled) {
   const uint32_t dim = 1u << nbits;
-  if (xz_tiled && (nbits <= kXzShallowMaxBits || nbits > kXzMaxBits)) return hipErrorInvalidValue;
+  if (xz_tiled && xz_geom(nbits) != XG_DEEP) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_diag<T>, dim3((dim + kBlock - 1) / kBlock), dim3(kBlock), 0, st, terms, nt,
                      diag, dim, xz_tiled ? 2 * kXzTileBits - nbits : -1);
   return hipGetLastError();
@@ -1582,9 +1780,35 @@ hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStre
 }
 
 template <typename T>
-hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st, bool deep) {
+hipError_t launch_xz_split(int op, const Seg* segs, int nseg, int ntiles, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b(kBlock);
+  switch (op) {
+    case 0: hipLaunchKernelGGL((k_xz_split<T, 0>), g, b, 0, st, segs, nseg); break;
+    case 1: hipLaunchKernelGGL((k_xz_split<T, 1>), g, b, 0, st, segs, nseg); break;
+    case 2: hipLaunchKernelGGL((k_xz_split<T, 2>), g, b, 0, st, segs, nseg); break;
+    case 3: hipLaunchKernelGGL((k_xz_split<T, 3>), g, b, 0, st, segs, nseg); break;
+    case 4: hipLaunchKernelGGL((k_xz_split<T, 4>), g, b, 0, st, segs, nseg); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipStream_t st, int geo) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 g(ntiles), b(kBlock);
+  const bool deep = geo == XG_DEEP;
+  if (geo == XG_SPLIT && (pass == 1 || pass == 4 || pass == 7)) {
+    // W_hi D W_hi = W_A (W_B D W_B) W_A as three passes
+    const int ops[3][3] = {{0, 1, 0}, {4, 1, 0}, {2, 3, 2}};
+    const int* o = ops[pass == 1 ? 0 : pass == 4 ? 1 : 2];
+    for (int i = 0; i < 3; ++i) {
+      const hipError_t e = launch_xz_split<T>(o[i], segs, nseg, ntiles, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (pass == 0) hipLaunchKernelGGL((k_apply_xz<T, 0, false>), g, b, 0, st, segs, nseg);
   else if (pass == 1 && deep) hipLaunchKernelGGL((k_apply_xz<T, 1, true>), g, b, 0, st, segs, nseg);
   else if (pass == 1) hipLaunchKernelGGL((k_apply_xz<T, 1, false>), g, b, 0, st, segs, nseg);
@@ -1592,22 +1816,38 @@ hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipSt
   else if (pass == 3) hipLaunchKernelGGL((k_apply_xz<T, 3, false>), g, b, 0, st, segs, nseg);
   else if (pass == 4 && deep) hipLaunchKernelGGL((k_apply_xz<T, 4, true>), g, b, 0, st, segs, nseg);
   else if (pass == 4) hipLaunchKernelGGL((k_apply_xz<T, 4, false>), g, b, 0, st, segs, nseg);
-  else hipLaunchKernelGGL((k_apply_xz<T, 5, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 5) hipLaunchKernelGGL((k_apply_xz<T, 5, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 6) hipLaunchKernelGGL((k_apply_xz<T, 6, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 7 && deep) hipLaunchKernelGGL((k_apply_xz<T, 7, true>), g, b, 0, st, segs, nseg);
+  else if (pass == 7) hipLaunchKernelGGL((k_apply_xz<T, 7, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 8) hipLaunchKernelGGL((k_apply_xz<T, 8, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 9) hipLaunchKernelGGL((k_apply_xz<T, 9, false>), g, b, 0, st, segs, nseg);
+  else if (pass == 10) hipLaunchKernelGGL((k_apply_xz<T, 10, false>), g, b, 0, st, segs, nseg);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff, hipStream_t st,
-                             bool deep) {
+                             int geo, bool xy) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b(kBlock);
-  if (pass == 0) hipLaunchKernelGGL((k_xz_lanczos<T, 0, false, false>), g, b, 0, st, segs, nseg, boff);
-  else if (pass == 1 && regen && deep)
-    hipLaunchKernelGGL((k_xz_lanczos<T, 1, true, true>), g, b, 0, st, segs, nseg, boff);
-  else if (pass == 1 && regen) hipLaunchKernelGGL((k_xz_lanczos<T, 1, true, false>), g, b, 0, st, segs, nseg, boff);
-  else if (pass == 1 && deep) hipLaunchKernelGGL((k_xz_lanczos<T, 1, false, true>), g, b, 0, st, segs, nseg, boff);
-  else if (pass == 1) hipLaunchKernelGGL((k_xz_lanczos<T, 1, false, false>), g, b, 0, st, segs, nseg, boff);
-  else hipLaunchKernelGGL((k_xz_lanczos<T, 2, false, false>), g, b, 0, st, segs, nseg, boff);
+#define RDM_XZL(P, R, G, X) hipLaunchKernelGGL((k_xz_lanczos<T, P, R, G, X>), g, b, 0, st, segs, nseg, boff)
+  if (pass == 0) RDM_XZL(0, false, XG_SHALLOW, false);
+  else if (pass == 1) {
+    if (regen && geo == XG_SPLIT) RDM_XZL(1, true, XG_SPLIT, false);
+    else if (regen && geo == XG_DEEP) RDM_XZL(1, true, XG_DEEP, false);
+    else if (regen) RDM_XZL(1, true, XG_SHALLOW, false);
+    else if (geo == XG_SPLIT) RDM_XZL(1, false, XG_SPLIT, false);
+    else if (geo == XG_DEEP) RDM_XZL(1, false, XG_DEEP, false);
+    else RDM_XZL(1, false, XG_SHALLOW, false);
+  } else if (pass == 2 && xy) RDM_XZL(2, false, XG_SHALLOW, true);
+  else if (pass == 2) RDM_XZL(2, false, XG_SHALLOW, false);
+  else if (pass == 3) RDM_XZL(3, false, XG_SHALLOW, false);
+  else if (pass == 4 && geo == XG_DEEP) RDM_XZL(4, false, XG_DEEP, false);
+  else if (pass == 4 && geo == XG_SHALLOW) RDM_XZL(4, false, XG_SHALLOW, false);
+  else return hipErrorInvalidValue;
+#undef RDM_XZL
   return hipGetLastError();
 }
 
@@ -1706,14 +1946,16 @@ template hipError_t launch_norm<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_norm<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
-template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t, bool);
+template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t, int);
+template hipError_t launch_xz_split<float>(int, const Seg*, int, int, hipStream_t);
+template hipError_t launch_xz_split<double>(int, const Seg*, int, int, hipStream_t);
 template hipError_t launch_block_update<float>(const BSeg*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_ground_ptrace<float>(const GPSeg*, int, int, hipStream_t);
 template hipError_t launch_ground_ptrace<double>(const GPSeg*, int, int, hipStream_t);
 template hipError_t launch_block_update<double>(const BSeg*, int, int, int, int, int, hipStream_t);
-template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t, bool);
-template hipError_t launch_xz_lanczos<float>(int, bool, const Seg*, int, int, int, hipStream_t, bool);
-template hipError_t launch_xz_lanczos<double>(int, bool, const Seg*, int, int, int, hipStream_t, bool);
+template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t, int);
+template hipError_t launch_xz_lanczos<float>(int, bool, const Seg*, int, int, int, hipStream_t, int, bool);
+template hipError_t launch_xz_lanczos<double>(int, bool, const Seg*, int, int, int, hipStream_t, int, bool);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);

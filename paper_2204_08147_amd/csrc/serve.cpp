@@ -4,11 +4,16 @@
 // step (norm, beta reduction, apply, alpha reduction) for *all* resident
 // requests at once, each at its own step index.  Requests waiting in the
 // queue are admitted at step boundaries when a slot and enough arena memory
-// are free (admission by device footprint); a request that finishes its
-// recurrences leaves the batch for its host eigen-work, recombination and
-// Gram, and its memory returns to the arena.  Each request's reductions run
-// over its own tiles in a fixed order, so its result does not depend on what
-// else is resident.
+// are free (admission by device footprint).  A request that finishes its
+// recurrences leaves the batch for a finisher thread, which runs its host
+// eigen-work, recombination and Gram on a stream of its own while the worker
+// goes on launching steps; its memory returns to the arena when it is done
+// (or it comes back for its regeneration pass).  The worker does not wait for
+// the device after each step: it waits only to stay a few steps ahead and
+// before it rewrites a segment table (two alternate).  Each request's
+// reductions run over its own tiles in a fixed order, so its result does not
+// depend on what else is resident.
+#include <algorithm>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -76,21 +81,32 @@ struct Req {
   rdm_status status = RDM_OK;
   bool done = false;
   bool claimed = false;  // a poll that saw it done, or a wait, owns the ticket
+  bool cancel = false;   // rdm_server_cancel asked to drop it
   InstPlan plan;
   InstRun run;
   char* mem = nullptr;
   int phase = 0;       // 0: pass 1 (H_t and H_b), 1: regeneration pass
-  int steps = 0;       // steps run in the current phase
+  int steps = 0;       // steps launched in the current phase
   bool need_init = true;
+  hipEvent_t last = nullptr;  // recorded after the request's last launched step
 };
 
 }  // namespace
 
+// The engine.  The worker thread launches the steps on `stream` and never
+// waits for them except to bound how far it runs ahead (kAhead steps) and to
+// reuse a segment table; finisher threads take the requests whose recurrences
+// are done, each on its own stream: host eigen-work, recombination + Gram and
+// finalisation overlap the worker's next steps.
 struct rdm_server {
+  static constexpr int kAhead = 4;        // steps in flight at most
+  static constexpr int kFinishers = 2;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<Req*> queue;
-  std::vector<Req*> active;
+  std::condition_variable cv_work, cv_done, cv_fin;
+  std::deque<Req*> queue;        // submitted, not admitted
+  std::deque<Req*> regen_ready;  // back from a finisher for their regeneration pass
+  std::deque<Req*> finishing;    // recurrences done (or dropped), for a finisher
+  std::vector<Req*> active;      // resident in the step loop (worker only)
   std::unordered_map<uint64_t, Req*> reqs;
   uint64_t next_ticket = 1;
   uint64_t budget = 0;
@@ -98,56 +114,140 @@ struct rdm_server {
   int prec = RDM_MIXED;
   double tau = 1e-5;
   bool stop = false;
+  bool worker_done_ = false;
+  int busy_finishers = 0;
   int device = 0;
   std::thread worker;
+  std::vector<std::thread> finishers;
   hipStream_t stream = nullptr;
-  Arena arena;
+  Arena arena;                   // guarded by mu
   char* arena_mem = nullptr;
-  Seg* dsegs = nullptr;
-  size_t segs_cap = 0;
+  // two segment tables, each with the event after the last step that read it
+  Seg* dsegs[2] = {nullptr, nullptr};
+  size_t segs_cap[2] = {0, 0};
+  std::vector<Seg> hsegs[2];
+  hipEvent_t seg_done[2] = {nullptr, nullptr};
+  std::deque<hipEvent_t> ahead, spare;  // events after the steps in flight
   int64_t n_submitted = 0, n_completed = 0, n_steps = 0, peak_active = 0, peak_bytes = 0, used = 0;
+  int64_t n_active = 0;  // active.size() as last published by the worker (under mu)
 
   void run();
-  rdm_status ensure_tables(size_t nseg);
+  bool cancelled(const Req* r) {
+    std::lock_guard<std::mutex> lk(mu);
+    return r->cancel;
+  }
+  void finish_loop();
+  rdm_status upload_table(int b, const std::vector<Seg>& segs);
   void complete(Req* r, rdm_status s);
+  void hand_over(Req* r);
 };
 
 void rdm_server::complete(Req* r, rdm_status s) {
-  if (r->mem) arena.release(r->mem, r->plan.bytes);
-  r->mem = nullptr;
+  if (r->last) (void)hipEventDestroy(r->last);
+  r->last = nullptr;
   std::lock_guard<std::mutex> lk(mu);
-  used -= (int64_t)r->plan.bytes;
+  if (r->mem) arena.release(r->mem, r->plan.bytes);
+  if (r->mem) used -= (int64_t)r->plan.bytes;
+  r->mem = nullptr;
   r->status = s;
   r->done = true;
   ++n_completed;
   cv_done.notify_all();
+  cv_work.notify_one();  // freed memory may admit a queued request
 }
 
-rdm_status rdm_server::ensure_tables(size_t nseg) {
-  if (nseg > segs_cap) {
-    if (dsegs) RDM_HIP(hipFree(dsegs));
-    segs_cap = std::max<size_t>(nseg, 2 * segs_cap);
-    RDM_HIP(hipMalloc(&dsegs, segs_cap * sizeof(Seg)));
+void rdm_server::hand_over(Req* r) {
+  std::lock_guard<std::mutex> lk(mu);
+  finishing.push_back(r);
+  cv_fin.notify_one();
+}
+
+rdm_status rdm_server::upload_table(int b, const std::vector<Seg>& segs) {
+  // every step that read table b has completed once seg_done[b] has
+  RDM_HIP(hipEventSynchronize(seg_done[b]));
+  if (segs.size() > segs_cap[b]) {
+    if (dsegs[b]) RDM_HIP(hipFree(dsegs[b]));
+    dsegs[b] = nullptr;
+    segs_cap[b] = std::max<size_t>(segs.size(), 2 * segs_cap[b]);
+    RDM_HIP(hipMalloc(&dsegs[b], segs_cap[b] * sizeof(Seg)));
   }
+  hsegs[b] = segs;  // the host copy lives until the table is reused
+  RDM_HIP(hipMemcpyAsync(dsegs[b], hsegs[b].data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, stream));
   return RDM_OK;
+}
+
+void rdm_server::finish_loop() {
+  (void)hipSetDevice(device);
+  hipStream_t fs = nullptr;
+  if (hipStreamCreateWithFlags(&fs, hipStreamNonBlocking) != hipSuccess) fs = nullptr;
+  while (true) {
+    Req* r;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_fin.wait(lk, [&] { return !finishing.empty() || (stop && worker_done_); });
+      if (finishing.empty()) break;
+      r = finishing.front();
+      finishing.pop_front();
+      ++busy_finishers;
+    }
+    rdm_status q = fs ? RDM_OK : RDM_E_DEVICE;
+    if (q == RDM_OK && hipEventSynchronize(r->last) != hipSuccess) q = RDM_E_DEVICE;
+    bool requeued = false;
+    if (q == RDM_OK && cancelled(r)) q = RDM_E_CANCELLED;
+    if (q == RDM_OK && r->phase == 0) {
+      q = host_phase(r->run, fs);
+      if (q == RDM_OK && r->plan.two_pass) {
+        r->phase = 1;
+        r->steps = 0;
+        r->need_init = true;
+        std::lock_guard<std::mutex> lk(mu);
+        regen_ready.push_back(r);
+        cv_work.notify_one();
+        requeued = true;
+      }
+    }
+    if (!requeued) {
+      if (q == RDM_OK) q = gram_phase(r->run, fs, nullptr);
+      if (q == RDM_OK) q = finalize(r->run, &r->out);
+      complete(r, q);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    --busy_finishers;
+    cv_work.notify_one();
+  }
+  if (fs) (void)hipStreamDestroy(fs);
 }
 
 void rdm_server::run() {
   (void)hipSetDevice(device);
   std::vector<Seg> segs;
+  int cur = 0;
+  bool changed = true;
+  Launch ntiles;
+  int slab = 1, cmax = 0;
   while (true) {
     std::vector<Req*> admitted;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-      if (stop && queue.empty() && active.empty()) break;
-      // admission at a step boundary: FIFO, by slot and device footprint
+      cv_work.wait(lk, [&] {
+        return !queue.empty() || !active.empty() || !regen_ready.empty() ||
+               (stop && finishing.empty() && busy_finishers == 0);
+      });
+      if (stop && queue.empty() && active.empty() && regen_ready.empty() && finishing.empty() &&
+          busy_finishers == 0)
+        break;
+      // admission at a step boundary: regeneration passes first (they hold
+      // their memory already), then the queue in order, by slot and footprint
+      while (!regen_ready.empty()) {
+        admitted.push_back(regen_ready.front());
+        regen_ready.pop_front();
+      }
       while (!queue.empty() && (int)active.size() + (int)admitted.size() < max_active) {
         Req* r = queue.front();
         char* m = arena.alloc(r->plan.bytes);
         if (!m) {
-          if (active.empty() && admitted.empty()) {
-            // cannot ever fit: fail it rather than block the queue
+          if (used == 0) {
+            // cannot fit even in an empty arena: fail it rather than block the queue
             queue.pop_front();
             r->status = RDM_E_NOMEM;
             r->done = true;
@@ -165,94 +265,124 @@ void rdm_server::run() {
       }
     }
     for (Req* r : admitted) {
-      r->run.plan = &r->plan;
-      r->run.base = r->mem;
-      r->phase = 0;
-      r->steps = 0;
-      r->need_init = true;
-      const rdm_status s = bind_ops(r->run, stream);
-      if (s != RDM_OK) {
-        complete(r, s);
+      if (cancelled(r)) {
+        hand_over(r);  // its last event (if any) has completed; nothing to wait for
         continue;
       }
-      std::lock_guard<std::mutex> lk(mu);
+      if (r->phase == 0) {
+        r->run.plan = &r->plan;
+        r->run.base = r->mem;
+        const rdm_status s = bind_ops(r->run, stream);
+        if (s != RDM_OK) {
+          complete(r, s);
+          continue;
+        }
+      }
       active.push_back(r);
-      peak_active = std::max<int64_t>(peak_active, (int64_t)active.size());
+      changed = true;
+    }
+    // requests cancelled while resident leave at this step boundary; their
+    // memory is released once the steps already launched for them are done
+    for (size_t i = 0; i < active.size();) {
+      Req* r = active[i];
+      if (cancelled(r) && hipEventRecord(r->last, stream) == hipSuccess) {
+        active.erase(active.begin() + (long)i);
+        hand_over(r);
+        changed = true;
+      } else {
+        ++i;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      n_active = (int64_t)active.size();
+      peak_active = std::max<int64_t>(peak_active, n_active);
     }
     if (active.empty()) continue;
 
-    // segment table of the resident batch
-    segs.clear();
-    std::vector<std::pair<int, int>> init_ranges;  // (first seg, phase) of segments to initialise
-    int cmax = 0;
-    for (Req* r : active) {
-      const int first = (int)segs.size();
-      if (r->phase == 0) {
-        segs.push_back(seg_of(r->run, 0, MODE_LANCZOS, tau));
-        segs.push_back(seg_of(r->run, 1, MODE_LANCZOS, tau));
-      } else {
-        segs.push_back(seg_of(r->run, 0, MODE_REGEN, tau));
+    rdm_status s = RDM_OK;
+    if (changed) {
+      // a new segment table (in the buffer not in use), and the state of the
+      // requests that start a phase
+      segs.clear();
+      std::vector<std::pair<int, int>> init_ranges;  // (first seg, phase)
+      for (Req* r : active) {
+        const int first = (int)segs.size();
+        if (r->phase == 0) {
+          segs.push_back(seg_of(r->run, 0, MODE_LANCZOS, tau));
+          segs.push_back(seg_of(r->run, 1, MODE_LANCZOS, tau));
+        } else {
+          segs.push_back(seg_of(r->run, 0, MODE_REGEN, tau));
+        }
+        if (r->need_init) {
+          for (int q = first; q < (int)segs.size(); ++q) init_ranges.push_back({q, r->phase});
+          r->need_init = false;
+        }
       }
-      if (r->need_init) {
-        for (int q = first; q < (int)segs.size(); ++q) init_ranges.push_back({q, r->phase});
-        r->need_init = false;
+      slab = tuned_slab(prec, segs);
+      ntiles = assign_tiles(segs);
+      cmax = 0;
+      for (const auto& sg : segs) cmax = std::max(cmax, sg.cpad);
+      cur ^= 1;
+      s = upload_table(cur, segs);
+      for (auto& ir : init_ranges) {
+        const Seg& sg = segs[ir.first];
+        if (s == RDM_OK)
+          s = init_run(prec, dsegs[cur] + ir.first, 1, cmax, ir.second, sg.xz ? sg.x_tiles * sg.P : 0,
+                       sg.x_base, stream);
+      }
+      changed = false;
+    }
+    if (s == RDM_OK) s = launch_step(prec, dsegs[cur], (int)segs.size(), ntiles, slab, cmax, stream, nullptr);
+    if (s == RDM_OK && hipEventRecord(seg_done[cur], stream) != hipSuccess) s = RDM_E_DEVICE;
+    // bound how far the launches run ahead of the device
+    if (s == RDM_OK) {
+      hipEvent_t e = nullptr;
+      if (!spare.empty()) {
+        e = spare.front();
+        spare.pop_front();
+      } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        s = RDM_E_DEVICE;
+      }
+      if (s == RDM_OK && hipEventRecord(e, stream) != hipSuccess) s = RDM_E_DEVICE;
+      if (e) ahead.push_back(e);
+      while (s == RDM_OK && (int)ahead.size() > kAhead) {
+        if (hipEventSynchronize(ahead.front()) != hipSuccess) s = RDM_E_DEVICE;
+        spare.push_back(ahead.front());
+        ahead.pop_front();
       }
     }
-    const int slab = tuned_slab(prec, segs);
-    const Launch ntiles = assign_tiles(segs);
-    for (const auto& sg : segs) cmax = std::max(cmax, sg.cpad);
-    rdm_status s = ensure_tables(segs.size());
-    if (s == RDM_OK && hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg),
-                                      hipMemcpyHostToDevice, stream) != hipSuccess)
-      s = RDM_E_DEVICE;
-    for (auto& ir : init_ranges) {
-      const Seg& sg = segs[ir.first];
-      if (s == RDM_OK)
-        s = init_run(prec, dsegs + ir.first, 1, cmax, ir.second, sg.xz ? sg.x_tiles * sg.P : 0, sg.x_base, stream);
-    }
-    if (s == RDM_OK) s = launch_step(prec, dsegs, (int)segs.size(), ntiles, slab, cmax, stream, nullptr);
-    // the host tables must stay valid until the copies above completed
-    if (s == RDM_OK && hipStreamSynchronize(stream) != hipSuccess) s = RDM_E_DEVICE;
     ++n_steps;
     if (s != RDM_OK) {
+      (void)hipStreamSynchronize(stream);
       std::vector<Req*> failed;
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        failed.swap(active);
-      }
+      failed.swap(active);
       for (Req* r : failed) complete(r, s);
+      changed = true;
       continue;
     }
-    // advance and retire
-    std::vector<Req*> keep;
-    for (Req* r : active) {
+    // requests whose recurrences are complete leave for a finisher
+    for (size_t i = 0; i < active.size();) {
+      Req* r = active[i];
       ++r->steps;
       const int need = r->phase == 0 ? std::max(r->plan.k, r->plan.kb) : r->plan.k;
       if (r->steps < need) {
-        keep.push_back(r);
+        ++i;
         continue;
       }
-      if (r->phase == 0) {
-        rdm_status q = host_phase(r->run, stream);
-        if (q != RDM_OK) {
-          complete(r, q);
-          continue;
-        }
-        if (r->plan.two_pass) {
-          r->phase = 1;
-          r->steps = 0;
-          r->need_init = true;
-          keep.push_back(r);
-          continue;
-        }
+      if (hipEventRecord(r->last, stream) != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
       }
-      rdm_status q = gram_phase(r->run, stream, nullptr);
-      if (q == RDM_OK) q = finalize(r->run, &r->out);
-      complete(r, q);
+      active.erase(active.begin() + (long)i);
+      hand_over(r);
+      changed = true;
     }
-    std::lock_guard<std::mutex> lk(mu);
-    active.swap(keep);
   }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    worker_done_ = true;
+  }
+  cv_fin.notify_all();
 }
 
 extern "C" rdm_status rdm_server_create(uint64_t hbm_budget, int32_t max_active, int32_t precision,
@@ -287,13 +417,19 @@ extern "C" rdm_status rdm_server_create(uint64_t hbm_budget, int32_t max_active,
     return RDM_E_NOMEM;
   }
   s->arena.init(s->arena_mem, hbm_budget);
-  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->seg_done[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->seg_done[1], hipEventDisableTiming) != hipSuccess) {
+    for (auto e : s->seg_done)
+      if (e) (void)hipEventDestroy(e);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
     (void)hipFree(s->arena_mem);
     delete s;
-    set_error("rdm_server_create: cannot create a stream");
+    set_error("rdm_server_create: cannot create a stream or events");
     return RDM_E_DEVICE;
   }
   s->worker = std::thread([s] { s->run(); });
+  for (int f = 0; f < rdm_server::kFinishers; ++f) s->finishers.emplace_back([s] { s->finish_loop(); });
   *out = s;
   return RDM_OK;
 }
@@ -326,6 +462,11 @@ extern "C" rdm_status rdm_server_submit(rdm_server* s, const rdm_hamiltonian* h,
   if (ps != RDM_OK) {
     delete r;
     return ps;
+  }
+  if (hipEventCreateWithFlags(&r->last, hipEventDisableTiming) != hipSuccess) {
+    delete r;
+    set_error("rdm_server_submit: cannot create an event");
+    return RDM_E_DEVICE;
   }
   std::lock_guard<std::mutex> lk(s->mu);
   r->ticket = s->next_ticket++;
@@ -377,6 +518,36 @@ extern "C" rdm_status rdm_server_wait(rdm_server* s, uint64_t ticket, rdm_status
   return RDM_OK;
 }
 
+extern "C" rdm_status rdm_server_cancel(rdm_server* s, uint64_t ticket) {
+  if (!s) {
+    set_error("rdm_server_cancel: NULL server");
+    return RDM_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end() || it->second->claimed) {
+    set_error("rdm_server_cancel: unknown ticket, or one already retrieved or being waited for");
+    return RDM_E_INVALID;
+  }
+  Req* r = it->second;
+  if (r->done) return RDM_OK;
+  auto q = std::find(s->queue.begin(), s->queue.end(), r);
+  if (q != s->queue.end()) {
+    // not admitted yet: done at once
+    s->queue.erase(q);
+    if (r->last) (void)hipEventDestroy(r->last);
+    r->last = nullptr;
+    r->status = RDM_E_CANCELLED;
+    r->done = true;
+    ++s->n_completed;
+    s->cv_done.notify_all();
+    return RDM_OK;
+  }
+  r->cancel = true;  // the engine drops it at its next step boundary
+  s->cv_work.notify_one();
+  return RDM_OK;
+}
+
 extern "C" rdm_status rdm_server_stats(rdm_server* s, int64_t* out) {
   if (!s || !out) {
     set_error("rdm_server_stats: bad arguments");
@@ -385,7 +556,7 @@ extern "C" rdm_status rdm_server_stats(rdm_server* s, int64_t* out) {
   std::lock_guard<std::mutex> lk(s->mu);
   out[0] = s->n_submitted;
   out[1] = s->n_completed;
-  out[2] = (int64_t)s->active.size();
+  out[2] = s->n_active;
   out[3] = (int64_t)s->queue.size();
   out[4] = s->n_steps;
   out[5] = s->peak_active;
@@ -400,9 +571,21 @@ extern "C" void rdm_server_destroy(rdm_server* s) {
     s->stop = true;
   }
   s->cv_work.notify_all();
+  s->cv_fin.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  for (auto& kv : s->reqs) delete kv.second;
-  if (s->dsegs) (void)hipFree(s->dsegs);
+  for (auto& f : s->finishers)
+    if (f.joinable()) f.join();
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& kv : s->reqs) {
+    if (kv.second->last) (void)hipEventDestroy(kv.second->last);
+    delete kv.second;
+  }
+  for (auto e : s->ahead) (void)hipEventDestroy(e);
+  for (auto e : s->spare) (void)hipEventDestroy(e);
+  for (int b = 0; b < 2; ++b) {
+    if (s->dsegs[b]) (void)hipFree(s->dsegs[b]);
+    if (s->seg_done[b]) (void)hipEventDestroy(s->seg_done[b]);
+  }
   if (s->arena_mem) (void)hipFree(s->arena_mem);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;

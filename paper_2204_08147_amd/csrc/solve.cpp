@@ -101,8 +101,10 @@ void parallel_for(int n, const std::function<void(int)>& fn) {
 // ---------------------------------------------------------------------------
 // planning
 // ---------------------------------------------------------------------------
+bool needs_ybuf(const rdm_hamiltonian* h, int which) { return h->op[which].xz && h->op[which].xy; }
+
 void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
-              size_t& off) {
+              size_t& off, bool ybuf) {
   const int W = panel_width(prec);
   const size_t sb = scalar_bytes(prec);
   g.nbits = nbits;
@@ -132,6 +134,11 @@ void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int r
   g.o_part = off; off = al(off + (size_t)g.n_row_tiles * g.cpad * 8);
   g.o_step = off; off = al(off + (size_t)g.cpad * 4);
   g.o_kc = off; off = al(off + (size_t)g.cpad * 4);
+  g.ybuf = ybuf;
+  if (ybuf) {
+    g.o_Y = off;
+    off = al(off + g.blk * sb);
+  }
 }
 
 int max_nb_chunk(int prec, int ds) {
@@ -166,8 +173,8 @@ rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int 
   }
   auto layout = [&](bool two_pass) {
     size_t off = 0;
-    plan_seg(p.tot, h->n, p.ds * n_v, p.k, prec, slab_opt, rpl_opt, two_pass ? 2 : p.k, off);
-    plan_seg(p.bath, h->n_b, n_v, p.kb, prec, slab_opt, rpl_opt, 2, off);
+    plan_seg(p.tot, h->n, p.ds * n_v, p.k, prec, slab_opt, rpl_opt, two_pass ? 2 : p.k, off, needs_ybuf(h, 0));
+    plan_seg(p.bath, h->n_b, n_v, p.kb, prec, slab_opt, rpl_opt, 2, off, needs_ybuf(h, 1));
     p.o_psi = off;
     if (two_pass) off = al(off + (size_t)n_beta * p.tot.blk * sb);
     p.o_y = off; off = al(off + (size_t)n_beta * p.k * p.tot.cpad * sb);
@@ -227,6 +234,7 @@ Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int sta
   s.blk = g.blk;
   s.Q = base + g.o_Q;
   s.R = base + g.o_R;
+  s.Y = g.ybuf ? base + g.o_Y : nullptr;
   s.psi = nullptr;
   s.ytab = nullptr;
   s.st = (double*)(base + g.o_st);
@@ -341,7 +349,9 @@ void bind_apply(Seg& s, const OpDevice* op) {
   s.nt1 = op->nt[1];
   s.nt2 = op->nt[2];
   s.xz = op->xz ? 1 : 0;
+  s.xy = op->xz && op->xy ? 1 : 0;
   s.dx = op->dx;
+  s.dy = op->dy;
   s.x_tiles = op->xz ? 1 << (s.nbits - kXzTileBits) : 0;
   s.ap_rows = op->xz ? s.x_tiles : s.n_row_tiles;
   s.nm_rows = s.ap_rows;
@@ -361,7 +371,8 @@ Launch assign_tiles(std::vector<Seg>& segs) {
     sg.x_base = L.xz;
     if (sg.xz) {
       L.xz += sg.x_tiles * sg.P;
-      (sg.mode == MODE_REGEN ? L.xz_regen : L.xz_lanczos)[sg.nbits > kXzShallowMaxBits] = true;
+      (sg.mode == MODE_REGEN ? L.xz_regen : L.xz_lanczos)[xz_geom(sg.nbits)] = true;
+      if (sg.xy) L.xy[xz_geom(sg.nbits)] = true;
     }
   }
   return L;
@@ -383,18 +394,41 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
   if (tm) RDM_HIP(tm->norm.mark(st));
   if (tm) RDM_HIP(tm->xz1.mark(st));
   for (int regen = 0; regen < 2; ++regen)
-    for (int deep = 0; deep < 2; ++deep) {
-      if (!(regen ? L.xz_regen : L.xz_lanczos)[deep]) continue;
-      RDM_HIP(d ? launch_xz_lanczos<double>(1, regen, dsegs, nseg, L.xz, 0, st, deep)
-                : launch_xz_lanczos<float>(1, regen, dsegs, nseg, L.xz, 0, st, deep));
+    for (int geo = 0; geo < 3; ++geo) {
+      if (!(regen ? L.xz_regen : L.xz_lanczos)[geo]) continue;
+      RDM_HIP(d ? launch_xz_lanczos<double>(1, regen, dsegs, nseg, L.xz, 0, st, geo)
+                : launch_xz_lanczos<float>(1, regen, dsegs, nseg, L.xz, 0, st, geo));
     }
+  // split segments: pass 1 did the norm step and W_A; then W_B D_X W_B, W_A
+  if (L.any_split())
+    for (int op : {1, 0})
+      RDM_HIP(d ? launch_xz_split<double>(op, dsegs, nseg, L.xz, st) : launch_xz_split<float>(op, dsegs, nseg, L.xz, st));
+  // the YY part of transform segments: Y = W_hi D_Y W_hi W_lo T W_lo u~ / L
+  if (L.any_xy()) {
+    RDM_HIP(d ? launch_xz_lanczos<double>(3, false, dsegs, nseg, L.xz, 0, st)
+              : launch_xz_lanczos<float>(3, false, dsegs, nseg, L.xz, 0, st));
+    for (int geo = 0; geo < 2; ++geo) {
+      if (!L.xy[geo]) continue;
+      RDM_HIP(d ? launch_xz_lanczos<double>(4, false, dsegs, nseg, L.xz, 0, st, geo)
+                : launch_xz_lanczos<float>(4, false, dsegs, nseg, L.xz, 0, st, geo));
+    }
+    if (L.xy[XG_SPLIT])
+      for (int op : {2, 3, 2})
+        RDM_HIP(d ? launch_xz_split<double>(op, dsegs, nseg, L.xz, st)
+                  : launch_xz_split<float>(op, dsegs, nseg, L.xz, st));
+  }
   if (tm) RDM_HIP(tm->xz1.mark(st));
   RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(d ? launch_apply<double>(dsegs, nseg, L.apply, slab, st)
             : launch_apply<float>(dsegs, nseg, L.apply, slab, st));
-  RDM_HIP(d ? launch_xz_lanczos<double>(2, false, dsegs, nseg, L.xz, 0, st)
-            : launch_xz_lanczos<float>(2, false, dsegs, nseg, L.xz, 0, st));
+  // pass 2 in two variants (with and without a YY part), each leaving the
+  // other's segments alone
+  for (int xy = 0; xy < 2; ++xy) {
+    if (xy && !L.any_xy()) continue;
+    RDM_HIP(d ? launch_xz_lanczos<double>(2, false, dsegs, nseg, L.xz, 0, st, false, xy)
+              : launch_xz_lanczos<float>(2, false, dsegs, nseg, L.xz, 0, st, false, xy));
+  }
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(launch_red_alpha(dsegs, nseg, cmax, st));
   return RDM_OK;
@@ -574,13 +608,14 @@ namespace {
 // caller's stream may be the legacy default stream.
 // The key holds every launch parameter a step depends on, including which
 // variants of the strided transform pass it records (Lanczos or regeneration,
-// shallow or deep): two tables at one address can agree on every count and
-// still need different variants.
+// by geometry, with or without a YY part): two tables at one address can
+// agree on every count and still need different variants.
 struct GraphKey {
   int device;
   const void* dsegs;
   int nseg, norm, apply, xz, slab, cmax, prec, nsteps;
-  int variants;  // bit (2 * regen + deep) set when that strided variant runs
+  int variants;  // bit (3 * regen + geometry) set when that strided variant runs, bit
+                 // (6 + geometry) when that YY strided variant runs
   bool operator<(const GraphKey& o) const {
     return std::tie(device, dsegs, nseg, norm, apply, xz, slab, cmax, prec, nsteps, variants) <
            std::tie(o.device, o.dsegs, o.nseg, o.norm, o.apply, o.xz, o.slab, o.cmax, o.prec, o.nsteps,
@@ -589,9 +624,10 @@ struct GraphKey {
 };
 int launch_variants(const Launch& L) {
   int v = 0;
-  for (int deep = 0; deep < 2; ++deep) {
-    if (L.xz_lanczos[deep]) v |= 1 << deep;
-    if (L.xz_regen[deep]) v |= 1 << (2 + deep);
+  for (int geo = 0; geo < 3; ++geo) {
+    if (L.xz_lanczos[geo]) v |= 1 << geo;
+    if (L.xz_regen[geo]) v |= 1 << (3 + geo);
+    if (L.xy[geo]) v |= 1 << (6 + geo);
   }
   return v;
 }
@@ -664,6 +700,11 @@ rdm_status graph_steps(int prec, Seg* dsegs, int nseg, const Launch& L, int slab
 rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
                      StepTimers* tm, bool tune, bool graph) {
   if (hsegs.empty()) return RDM_OK;
+  for (const auto& sg : hsegs)
+    if (sg.xy && !sg.Y) {
+      set_error("internal: a segment with a YY transform part has no Y block");
+      return RDM_E_INVALID;
+    }
   int kmax = 0, cmax = 0;
   for (const auto& sg : hsegs) {
     kmax = std::max(kmax, sg.k);
@@ -885,7 +926,7 @@ rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uin
   const int kk = (int)std::min<uint64_t>((uint64_t)k, 1ull << nbits);
   const size_t base_off = al(sizeof(Seg));
   size_t off = base_off;
-  plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, off);
+  plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, off, needs_ybuf(h, which));
   char* ws = nullptr;
   RDM_HIP(hipMalloc(&ws, off));
   const OpDevice* op = nullptr;

@@ -15,7 +15,12 @@ struct SegPlan {
   int nbits = 0, C = 0, cpad = 0, P = 0, S = 1, rpl = 1, n_row_tiles = 0, k = 0, nslots = 0;
   uint64_t dim = 0, blk = 0;
   size_t o_Q = 0, o_R = 0, o_st = 0, o_ha = 0, o_hb = 0, o_hs = 0, o_part = 0, o_step = 0, o_kc = 0;
+  bool ybuf = false;  // one more block (the YY part of a transform operator) at o_Y
+  size_t o_Y = 0;
 };
+// Whether operator `which` of h (0: H_t, 1: H_b) is applied by the transform
+// with a YY part, which needs the scratch block Y.
+bool needs_ybuf(const rdm_hamiltonian* h, int which);
 
 struct InstPlan {
   const rdm_hamiltonian* h = nullptr;
@@ -82,7 +87,7 @@ struct InstRun {
 };
 
 void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
-              size_t& off);
+              size_t& off, bool ybuf = false);
 rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
                          int mode_req, uint64_t budget, int slab_opt, int rpl_opt);
 size_t batch_header_bytes(const std::vector<InstPlan>& plans);
@@ -102,9 +107,12 @@ void bind_apply(Seg& s, const OpDevice* op);
 // workgroups of the norm launch and of the two kinds of apply launch
 struct Launch {
   int norm = 0, apply = 0, xz = 0;
-  // transform segments in each mode, shallow [0] and deep [1] (more than
-  // kXzShallowMaxBits bits)
-  bool xz_lanczos[2] = {false, false}, xz_regen[2] = {false, false};
+  // transform segments in each mode, by strided geometry (XG_SHALLOW,
+  // XG_DEEP, XG_SPLIT); xy: those with a YY part
+  bool xz_lanczos[3] = {false, false, false}, xz_regen[3] = {false, false, false};
+  bool xy[3] = {false, false, false};
+  bool any_xy() const { return xy[0] || xy[1] || xy[2]; }
+  bool any_split() const { return xz_lanczos[XG_SPLIT] || xz_regen[XG_SPLIT]; }
 };
 // sets every segment's tile_base / ap_base / x_base
 Launch assign_tiles(std::vector<Seg>& segs);
@@ -144,7 +152,7 @@ struct BlockPlan {
   int ds = 2, ds_log = 1, C = 0, cpad = 0, G = 0, CB = 0, n_cb = 0, rpl = 1, n_rt = 0;
   uint64_t dim = 0, blk = 0;
   SegPlan apply, bath;
-  size_t o_Q = 0, o_R = 0, o_part = 0, o_mats = 0, o_ah = 0, o_bh = 0, o_kc = 0;
+  size_t o_Q = 0, o_R = 0, o_Y = 0, o_part = 0, o_mats = 0, o_ah = 0, o_bh = 0, o_kc = 0;
   size_t header = 0, bytes = 0;
 };
 rdm_status block_plan(BlockPlan& bp, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,

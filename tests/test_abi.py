@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import lanczos as olz
-from workloads import long_range_xxz, cfg_long_range, cfg_small_chain, random_dense_terms
+from workloads import long_range_xxz, cfg_long_range, cfg_small_chain, nn_xxz_chain, random_dense_terms
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 rdm = pytest.importorskip("paper_2204_08147_amd")
@@ -56,9 +56,8 @@ def test_hamiltonian_tables():
 
 
 def test_transform_apply_selection():
-    # operators whose hops are all X-type (J^y = 0) on 16..22 bits are applied
-    # as D_Z + W D_X W; anything with a YY part, or outside that size range,
-    # keeps the hop tables
+    # operators on 16..28 bits are applied as D_Z + W D_X W (+ T W D_Y W T);
+    # smaller ones keep the hop tables
     full = rdm.Hamiltonian.from_instance(cfg_long_range(0)).info()      # 2 + 18
     assert full["transform"] == 1 and full["bath_transform"] == 1
     small = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=8)).info()  # 2 + 8
@@ -67,12 +66,33 @@ def test_transform_apply_selection():
     assert mid["transform"] == 1 and mid["bath_transform"] == 0
     big = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=20)).info()   # 22 bits
     assert big["transform"] == 1 and big["bath_transform"] == 1
+    # above 22 bits the strided passes split the high bits in two groups
     over = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=21)).info()  # 23 bits, bath 21
-    assert over["transform"] == 0 and over["bath_transform"] == 1
+    assert over["transform"] == 1 and over["bath_transform"] == 1
     over = rdm.Hamiltonian.from_instance(cfg_long_range(0, n_b=23)).info()  # 25 bits, bath 23
-    assert over["transform"] == 0 and over["bath_transform"] == 0
-    xxz = rdm.Hamiltonian.from_instance(long_range_xxz(2, 16, 1)).info()   # J^x = J^y
-    assert xxz["transform"] == 0 and xxz["bath_transform"] == 0
+    assert over["transform"] == 1 and over["bath_transform"] == 1
+    big = rdm.Hamiltonian.from_instance(cfg_long_range(2, n_b=26)).info()   # 28 bits
+    assert big["transform"] == 1
+    # YY couplings (J^x = J^y): the transform with a YY part when the hop
+    # tables would gather many partner rows (all pairs), hop tables for a
+    # sparse chain; either kind on request
+    xxz = rdm.Hamiltonian.from_instance(long_range_xxz(2, 16, 1)).info()
+    assert xxz["transform"] == 1 and xxz["transform_yy"] == 1 and xxz["bath_transform"] == 1
+    # two XXZ bonds on the last four sites (the low index bits): every hop
+    # stays inside a 256-row tile
+    few = [(12, 13, 0.5, 0.5, 1.0), (14, 15, 0.7, 0.7, -1.0)]
+    sparse = rdm.Hamiltonian(2, 14, few).info()
+    assert sparse["transform"] == 0 and sparse["bath_transform"] == 0
+    forced = rdm.Hamiltonian(2, 14, few, apply="transform").info()
+    assert forced["transform"] == 1 and forced["transform_yy"] == 1
+    chain = rdm.Hamiltonian.from_instance(nn_xxz_chain(2, 14, 5)).info()   # 8 partner rows per row
+    assert chain["transform"] == 1 and chain["transform_yy"] == 1
+    hops = rdm.Hamiltonian.from_instance(cfg_long_range(0), apply="hops").info()
+    assert hops["transform"] == 0 and hops["bath_transform"] == 0
+    xonly = rdm.Hamiltonian.from_instance(cfg_long_range(0)).info()
+    assert xonly["transform_yy"] == 0
+    out = rdm.C.c_void_p()
+    assert rdm.LIB.rdm_hamiltonian_create_ex(1, 3, None, 0, None, None, 7, rdm.C.byref(out)) == -1
 
 
 @pytest.mark.parametrize("bad", [

@@ -80,7 +80,12 @@ APPLY_CASES = [
     lambda: random_sparse_xxz(3007, n_range=(12, 14)),
     lambda: long_range_xx_zz(2, 14, 1.0, 57),     # 16 bits, X-type only: transform apply
     lambda: tfim_request(7, n_range=(17, 17)),    # 17 bits, ZZ chain + x-field: transform apply
+    # transform apply with a YY part (T W D_Y W T)
+    lambda: random_dense_terms(2, 14, 59, density=0.3),  # 16 bits, every term type
+    lambda: long_range_xxz(2, 15, 60),            # 17 bits, J^x = J^y, x-field
+    lambda: nn_xxz_chain(2, 17, 61),              # 19 bits, XXZ chain, z-field
 ]
+YY_APPLY_CASES = (8, 9, 10)
 
 
 @pytest.mark.parametrize("case", range(len(APPLY_CASES)))
@@ -89,6 +94,8 @@ APPLY_CASES = [
 def test_apply_matches_oracle(case, prec, n_cols):
     inst = APPLY_CASES[case]()
     h = H(inst)
+    if case in YY_APPLY_CASES:
+        assert h.info()["transform_yy"] == 1
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
     rng = np.random.default_rng(case * 100 + n_cols)
     x = rng.normal(size=(inst.dim, n_cols))
@@ -149,13 +156,18 @@ def _cfg_large():
 
 @pytest.mark.parametrize("make,cols", [(lambda: cfg_long_range(2), 64), (lambda: tfim_request(3, n_range=(24, 24)), 32),
                                        (lambda: tfim_request(4, n_range=(21, 21)), 16),
-                                       (lambda: long_range_xx_zz(1, 21, 1.0, 6), 16), (_cfg_large, 32)])
+                                       (lambda: long_range_xx_zz(1, 21, 1.0, 6), 16), (_cfg_large, 32),
+                                       (lambda: long_range_xxz(1, 20, 7), 16),
+                                       (lambda: random_sparse_xxz(3001, n_range=(22, 22)), 32),
+                                       (lambda: long_range_xxz(1, 22, 8), 16)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_apply_full_size_sampled_rows(make, cols, prec):
     # full-size shapes (dim 2^20, 2^24 and the largest, 2^26 with all-pairs
     # XXZ) in the bench's launch configuration, checked on 300 sampled rows
     # computed one by one by the oracle; 2^21 and 2^22 run the transform apply
-    # with 9 and 10 high bits (2^22 with the XCD grouping of strided tiles)
+    # with 9 and 10 high bits (2^22 with the XCD grouping of strided tiles);
+    # 2^23, 2^24 and 2^26 split the high bits over three strided passes; the
+    # 2^21, 2^22 sparse, 2^23 and 2^26 operators have a YY part
     inst = make()
     h = H(inst)
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
@@ -233,6 +245,8 @@ SOLVE_CASES = {
     "sparse": lambda: random_sparse_xxz(3011, n_range=(12, 13)),
     # 16 bits, X-type hops only: the transform apply (H_t) next to hop tables (H_b)
     "xz_2+14": lambda: long_range_xx_zz(2, 14, 1.0, 75, betas=(0.5, 2.0), n_v=2, k=30),
+    # 16 bits with YY couplings: the transform apply with its YY part
+    "xxz_2+14": lambda: long_range_xxz(2, 14, 76, betas=(0.5, 2.0), n_v=2, k=30),
 }
 
 _ORACLE = {}
@@ -264,7 +278,7 @@ def test_solve_mixed_matches_oracle(name):
 # --------------------------------------------------------------------------
 # the paper's block variant (Algorithm 1 + block Gauss quadrature) against O4
 # --------------------------------------------------------------------------
-BLOCK_CASES = ["chain_1+9", "random_2+6", "random_3+5", "lr_2+9", "xz_2+14"]
+BLOCK_CASES = ["chain_1+9", "random_2+6", "random_3+5", "lr_2+9", "xz_2+14", "xxz_2+14"]
 _ORACLE_BLOCK = {}
 
 
@@ -573,18 +587,19 @@ def test_batch_waves_and_two_pass_equal_solo():
     # the batch into several waves: every item bitwise equal to its own solve
     # under the same budget, one item against O3
     insts = [long_range_xx_zz(2, 12, 1.0, 301, betas=(0.5, 2.0), n_v=4, k=40),
-             random_sparse_xxz(3012, n_range=(13, 13)),
-             random_sparse_xxz(3013, n_range=(12, 12)),
-             SOLVE_CASES["lr_2+9"](),
-             SOLVE_CASES["random_2+6"]()]
+             SOLVE_CASES["lr_2+9"](), SOLVE_CASES["random_2+6"](), SOLVE_CASES["random_3+5"](),
+             SOLVE_CASES["chain_1+9"]()]
     hs = [H(i) for i in insts]
-    big = insts[0]
-    stored = rdm.workspace_size(hs[0], len(big.betas), big.n_v, big.k, precision="mixed", mode="stored")
-    two = rdm.workspace_size(hs[0], len(big.betas), big.n_v, big.k, precision="mixed", mode="two_pass")
-    budget = (stored + two) // 2
-    assert two < budget < stored
     items = [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
     for prec in ("fp64", "mixed"):
+        size = lambda t, mode: rdm.workspace_size(hs[t], len(insts[t].betas), insts[t].n_v, insts[t].k,  # noqa: E731
+                                                   precision=prec, mode=mode)
+        stored0, two0 = size(0, "stored"), size(0, "two_pass")
+        others = max(size(t, "stored") for t in range(1, len(insts)))
+        total = sum(size(t, "stored") for t in range(1, len(insts))) + two0
+        budget = (max(two0, others) + min(stored0, total)) // 2
+        assert max(two0, others) < budget < stored0
+        assert total > budget  # so the batch runs in several waves
         got = rdm.solve_batch(items, precision=prec, hbm_budget=budget, library_alloc=True)
         solo = [rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision=prec, hbm_budget=budget) for h, i in
                 zip(hs, insts)]
@@ -594,10 +609,7 @@ def test_batch_waves_and_two_pass_equal_solo():
             assert b["status"] == 0
             for key in ("rho", "h_star", "log_z", "entropy"):
                 assert np.array_equal(a[key], b[key]), (prec, key)
-    total = sum(rdm.workspace_size(h, len(i.betas), i.n_v, i.k, precision="fp64", hbm_budget=budget)
-                for h, i in zip(hs, insts))
-    assert total > budget  # so the batch above ran in more than one wave
-    check_result(got[3], oracle_solve("lr_2+9"), 1e-5, "batched item vs O3")
+        check_result(got[1], oracle_solve("lr_2+9"), 1e-10 if prec == "fp64" else 1e-5, "batched item vs O3")
 
 
 def test_concurrent_solves_equal_solo():
@@ -783,19 +795,45 @@ def test_served_request_matches_oracle():
         check_result(got, want, tol, f"served request ({prec}) vs O3")
 
 
-def _with_hop_tables(inst):
-    # the same operator up to a YY part of 1e-13 on one pair (far below the
-    # FP64 bar): a YY term rules out the transform apply, so the library
-    # takes its hop tables
-    i, j, jx, _, jz = inst.couplings[0]
-    cps = [(i, j, jx, 1e-13, jz)] + list(inst.couplings[1:])
-    return Instance(inst.n_s, inst.n_b, cps, inst.hx, inst.hz, inst.betas, inst.n_v, inst.k, inst.seed)
+def test_serving_cancel_and_ticket_ownership():
+    # cancelled requests (one queued, one resident) complete with
+    # RDM_E_CANCELLED; every other request is bitwise its solo result; a
+    # retrieved ticket is gone
+    insts = [tfim_request(r, n_range=(16, 18), n_v=4, k=40) for r in range(6)]
+    hs = [H(i) for i in insts]
+    alone = [rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision="mixed") for h, i in zip(hs, insts)]
+    srv = rdm.Server(hbm_budget=4 << 30, max_active=2, precision="mixed")
+    try:
+        tickets = [srv.submit(h, i.betas, i.n_v, i.k, i.seed) for h, i in zip(hs, insts)]
+        srv.cancel(tickets[5])        # still queued behind two resident requests
+        srv.cancel(tickets[0])        # resident (or already done)
+        res = [srv.wait(t) for t in tickets]
+        with pytest.raises(rdm.RdmError):
+            srv.poll(tickets[1])      # retired by wait
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert res[5]["status"] == -6
+    assert res[0]["status"] in (0, -6)
+    assert st["completed"] == 6
+    for t in range(1, 5):
+        assert res[t]["status"] == 0
+        for key in ("rho", "h_star", "log_z", "entropy"):
+            assert np.array_equal(alone[t][key], res[t][key]), (t, key)
+
+
+def HH(inst):
+    # the same operator applied from hop tables
+    return rdm.Hamiltonian.from_instance(inst, apply="hops")
 
 
 DEEP_CASES = {
     "tfim_1+21": lambda: tfim_request(3, n_range=(22, 22), n_v=2, k=30),
     "lr_1+20": lambda: long_range_xx_zz(1, 20, 1.0, 81, betas=(0.5, 2.0), n_v=2, k=30),
     "lr_2+20": lambda: long_range_xx_zz(2, 20, 1.0, 82, betas=(1.0,), n_v=1, k=20),
+    # with a YY part: the deep strided pass on D_Y as well
+    "xxz_1+20": lambda: long_range_xxz(1, 20, 87, betas=(0.5, 2.0), n_v=2, k=30),
+    "sparse_22": lambda: random_sparse_xxz(3001, n_range=(22, 22), n_v=1, k=30),
 }
 
 
@@ -805,13 +843,16 @@ SHALLOW_CASES = {
     "lr_1+16": lambda: long_range_xx_zz(1, 16, 1.0, 83, betas=(0.5, 2.0), n_v=2, k=30),
     "lr_2+16": lambda: long_range_xx_zz(2, 16, 0.5, 84, betas=(1.0, 4.0), n_v=2, k=30),
     "tfim_2+17": lambda: tfim_request(11, n_range=(19, 19), n_v=2, k=30),
+    # with a YY part
+    "xxz_1+16": lambda: long_range_xxz(1, 16, 85, betas=(0.5, 2.0), n_v=2, k=30),
+    "chain_2+17": lambda: nn_xxz_chain(2, 17, 86, betas=(1.0,), n_v=2, k=30),
 }
 
 
 @pytest.mark.parametrize("name", list(SHALLOW_CASES))
 def test_transform_17_to_19_bits_matches_hop_tables(name):
     inst = SHALLOW_CASES[name]()
-    h, hh = H(inst), H(_with_hop_tables(inst))
+    h, hh = H(inst), HH(inst)
     assert h.info()["transform"] == 1 and hh.info()["transform"] == 0
     a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
     b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
@@ -820,17 +861,20 @@ def test_transform_17_to_19_bits_matches_hop_tables(name):
 
 
 def test_graph_cache_separates_strided_variants():
-    # two batches with the same launch counts (segments, tiles, columns, k) at
-    # one workspace address, one of them with a 21-bit segment (deep strided
-    # variant) and one without: each replay must record its own variants
-    def batch(ns):
-        insts = [long_range_xx_zz(3, n - 3, 1.0, 90 + n, betas=(1.0,), n_v=1, k=8) for n in ns]
+    # batches with the same launch counts (segments, tiles, columns, k) at one
+    # workspace address, one with a 21-bit segment (deep strided variant), one
+    # with YY parts (the YY passes) and one with neither: each replay must
+    # record its own variants
+    def batch(ns, yy=False):
+        insts = [long_range_xxz(3, n - 3, 90 + n, betas=(1.0,), n_v=1, k=8) if yy else
+                 long_range_xx_zz(3, n - 3, 1.0, 90 + n, betas=(1.0,), n_v=1, k=8) for n in ns]
         hs = [H(i) for i in insts]
         return [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
-    shallow, deep = batch([20, 20, 20]), batch([21, 19, 19])
-    assert all(it["h"].info()["transform"] == 1 for it in shallow + deep)
+    shallow, deep, yy = batch([20, 20, 20]), batch([21, 19, 19]), batch([20, 20, 20], yy=True)
+    assert all(it["h"].info()["transform"] == 1 for it in shallow + deep + yy)
+    assert all(it["h"].info()["transform_yy"] == 1 for it in yy)
     ws = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
-    for items in (shallow, deep, shallow):
+    for items in (shallow, deep, shallow, yy, shallow):
         eager = rdm.solve_batch(items, precision="mixed", eager=True, workspace=ws)
         graph = rdm.solve_batch(items, precision="mixed", workspace=ws)
         for x, y in zip(eager, graph):
@@ -846,7 +890,7 @@ def test_transform_beyond_20_bits_matches_hop_tables(name):
     # in the sampled-rows test); FP64 paths agree to rounding, the mixed path
     # to the mixed bar
     inst = DEEP_CASES[name]()
-    h, hh = H(inst), H(_with_hop_tables(inst))
+    h, hh = H(inst), HH(inst)
     assert h.info()["transform"] == 1 and hh.info()["transform"] == 0
     a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
     b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
@@ -856,11 +900,44 @@ def test_transform_beyond_20_bits_matches_hop_tables(name):
     check_result(m, want, 1e-5, "mixed transform vs FP64 hop tables " + name)
 
 
+SPLIT_CASES = {
+    # 23 and 24 bits: the high bits in two groups (5 + 6, 6 + 6), three
+    # strided passes per product, with and without a YY part
+    "tfim_2+21": lambda: tfim_request(17, n_range=(23, 23), n_v=1, k=20),
+    "xxz_1+22": lambda: long_range_xxz(1, 22, 88, betas=(0.5, 2.0), n_v=1, k=20),
+    "chain_1+23": lambda: nn_xxz_chain(1, 23, 89, betas=(1.0,), n_v=1, k=16),
+}
+
+
+@pytest.mark.parametrize("name", list(SPLIT_CASES))
+def test_transform_split_matches_hop_tables(name):
+    inst = SPLIT_CASES[name]()
+    h, hh = rdm.Hamiltonian.from_instance(inst, apply="transform"), HH(inst)
+    assert h.info()["transform"] == 1 and hh.info()["transform"] == 0
+    b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    want = [{key: b[key][t] for key in ("rho", "h_star", "log_z", "entropy")} for t in range(len(inst.betas))]
+    a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    check_result(a, want, 1e-10, "split transform vs hop tables " + name)
+    m = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed")
+    check_result(m, want, 1e-5, "mixed split transform vs FP64 hop tables " + name)
+    # the regeneration pass of the split variant repeats the first bit for bit
+    s1 = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="stored")
+    s2 = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", mode="two_pass")
+    assert s2["two_pass"] and not s1["two_pass"]
+    for key in ("rho", "h_star", "log_z", "entropy"):
+        assert np.array_equal(s1[key], s2[key]), key
+    # the block variant's plain split passes
+    blk = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    blh = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    want_b = [{key: blh[key][t] for key in ("rho", "h_star", "log_z", "entropy")} for t in range(len(inst.betas))]
+    check_result(blk, want_b, 1e-10, "block: split transform vs hop tables " + name)
+
+
 @pytest.mark.parametrize("name", ["tfim_1+21", "lr_1+20"])
 def test_block_beyond_20_bits_matches_hop_tables(name):
     # the block variant's plain transform passes with the deep strided kernel
     inst = DEEP_CASES[name]()
-    h, hh = H(inst), H(_with_hop_tables(inst))
+    h, hh = H(inst), HH(inst)
     a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
     b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
     want = [{key: b[key][t] for key in ("rho", "h_star", "log_z", "entropy")} for t in range(len(inst.betas))]
@@ -870,7 +947,7 @@ def test_block_beyond_20_bits_matches_hop_tables(name):
 def test_serving_alone_equals_in_mix_large_requests():
     # 21- and 22-spin requests (transform apply with more than 8 high bits)
     # next to small ones: every result bitwise equal to its solo run
-    insts = [tfim_request(r, n_range=(21, 22), n_v=2, k=20) for r in range(3)] + \
+    insts = [tfim_request(r, n_range=(21, 23), n_v=2, k=20) for r in range(3)] + \
             [tfim_request(r, n_range=(12, 16), n_v=2, k=20) for r in range(3, 6)]
     hs = [H(i) for i in insts]
     assert sum(h.info()["transform"] for h in hs[:3]) == 3
