@@ -201,6 +201,30 @@ rdm_status rdm_solve_ws(const rdm_hamiltonian* h, const double* beta, int32_t n_
                         int32_t k, uint64_t seed, const rdm_options* opt, void* hip_stream,
                         rdm_result* out, void* dev_workspace, uint64_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code that may not call
+ * hipMalloc or an allocating library routine: tight serving loops, harnesses
+ * that forbid allocation).  As rdm_solve with the per-column method, but the
+ * device workspace is a fixed array inside this library of
+ * RDM_NOALLOC_MAX_BYTES bytes per device (held by every device the library
+ * runs on until the process ends); the call allocates no device memory.
+ * The plan must fit the array: with mode RDM_AUTO a basis that does not fit
+ * takes the two-pass plan; RDM_E_NOMEM (and nothing run) if even that does
+ * not fit.  The Hamiltonian's device tables for this precision must already
+ * be resident on the current device (any earlier rdm_solve, rdm_solve_ws or
+ * rdm_apply with it builds them); otherwise RDM_E_INVALID and nothing run.
+ * The Lanczos steps are launched one by one (no graph capture, no slab
+ * timing); results equal rdm_solve's with the same options and an
+ * hbm_budget of RDM_NOALLOC_MAX_BYTES.  The array keeps the last call's
+ * contents, and the solve initialises everything it reads.  Calls share the
+ * device's array: the library serialises the calls of one process (a second
+ * caller blocks until the first returns), and calls that overlapped on one
+ * device would race.  Blocking; results on the host.  method must be
+ * RDM_PER_COLUMN or RDM_METHOD_AUTO (taken as per-column) and profile 0. */
+#define RDM_NOALLOC_MAX_BYTES (64ull << 20)
+rdm_status rdm_solve_noalloc(const rdm_hamiltonian* h, const double* beta, int32_t n_beta, int32_t n_v,
+                             int32_t k, uint64_t seed, const rdm_options* opt, void* hip_stream,
+                             rdm_result* out);
+
 /* One instance of a batched solve. */
 typedef struct {
   const rdm_hamiltonian* h;

@@ -185,6 +185,20 @@ def solve(h: Hamiltonian, betas: Sequence[float], n_v: int, k: int, seed: int, *
     return res.as_dict()
 
 
+def solve_noalloc(h: Hamiltonian, betas: Sequence[float], n_v: int, k: int, seed: int, *, stream=None,
+                  **opts) -> dict:
+    """As ``solve`` (per-column method), with the device workspace in the
+    library's fixed scratch array (``_lib.NOALLOC_MAX_BYTES`` per device): the
+    call allocates no device memory.  The Hamiltonian's device tables must be
+    resident already (any earlier solve with it in this precision)."""
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    o = make_options(**opts)
+    res = _ResultBuffers(len(betas), 1 << h.n_s)
+    _check(LIB.rdm_solve_noalloc(h.handle, _dptr(betas), len(betas), n_v, k, seed, C.byref(o),
+                                 _stream_handle(stream), C.byref(res.c)), "rdm_solve_noalloc")
+    return res.as_dict()
+
+
 def solve_batch(items: List[dict], *, stream=None, library_alloc: bool = False,
                 reserve_bytes: int = 8 << 30, workspace=None, **opts) -> List[dict]:
     """items: dicts with keys h, betas, n_v, k, seed.  Returns per-item result

@@ -18,6 +18,7 @@ RDM_AUTO, RDM_STORED_Q, RDM_TWO_PASS = 0, 1, 2
 RDM_PER_COLUMN, RDM_BLOCK, RDM_METHOD_AUTO = 0, 1, 2
 RDM_APPLY_AUTO, RDM_APPLY_HOPS, RDM_APPLY_TRANSFORM = 0, 1, 2
 DIAG_FIXED = 16
+NOALLOC_MAX_BYTES = 64 << 20  # RDM_NOALLOC_MAX_BYTES
 
 STATUS_NAMES = {0: "RDM_OK", -1: "RDM_E_INVALID", -2: "RDM_E_NOMEM", -3: "RDM_E_DEVICE",
                 -4: "RDM_E_NONFINITE", -5: "RDM_E_BUSY", -6: "RDM_E_CANCELLED"}
@@ -76,6 +77,9 @@ SIGNATURES = [
     ("rdm_solve_ws", C.c_int32,
      [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
       C.POINTER(Options), C.c_void_p, C.POINTER(Result), C.c_void_p, C.c_uint64]),
+    ("rdm_solve_noalloc", C.c_int32,
+     [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+      C.POINTER(Options), C.c_void_p, C.POINTER(Result)]),
     ("rdm_solve_batch", C.c_int32, [C.c_int32, C.POINTER(BatchItem), C.POINTER(Options), C.c_void_p]),
     ("rdm_solve_batch_ws", C.c_int32,
      [C.c_int32, C.POINTER(BatchItem), C.POINTER(Options), C.c_void_p, C.c_void_p, C.c_uint64]),

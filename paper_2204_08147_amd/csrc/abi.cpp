@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "host.h"
 #include "solve.h"
@@ -205,6 +207,88 @@ extern "C" rdm_status rdm_solve_ws(const rdm_hamiltonian* h, const double* beta,
     return RDM_E_INVALID;
   }
   return solve_impl(h, beta, n_beta, n_v, k, seed, opt, hip_stream, out, dev_workspace, ws_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// rdm_solve_noalloc: the per-column solve with its workspace in a fixed
+// device array of this library instead of memory it allocates.  The array is
+// part of the code object: each device the library runs on holds its own copy
+// until the process ends.  Host code must never pass the array's name to a
+// kernel or a copy (in host code it names a host-side stand-in): the device
+// address of this device's copy comes from hipGetSymbolAddress, once per
+// device, and is kept below.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[RDM_NOALLOC_MAX_BYTES];
+
+namespace {
+
+std::mutex g_noalloc_mu;             // serialises the calls: one array per device
+std::map<int, char*> g_noalloc_ptr;  // device -> address of its copy of the array
+
+rdm_status noalloc_workspace(char** out) {
+  int dev = 0;
+  RDM_HIP(hipGetDevice(&dev));
+  auto it = g_noalloc_ptr.find(dev);
+  if (it == g_noalloc_ptr.end()) {
+    void* ptr = nullptr;
+    RDM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr & 255)) {
+      set_error("rdm_solve_noalloc: bad device address of the scratch array");
+      return RDM_E_DEVICE;
+    }
+    it = g_noalloc_ptr.emplace(dev, (char*)ptr).first;
+  }
+  *out = it->second;
+  return RDM_OK;
+}
+
+}  // namespace
+
+extern "C" rdm_status rdm_solve_noalloc(const rdm_hamiltonian* h, const double* beta, int32_t n_beta,
+                                        int32_t n_v, int32_t k, uint64_t seed, const rdm_options* opt,
+                                        void* hip_stream, rdm_result* out) {
+  Opts o;
+  rdm_status s = read_opts(opt, o);
+  if (s != RDM_OK) return s;
+  if ((s = check_solve_args(h, beta, n_beta, n_v, k)) != RDM_OK) return s;
+  if (!out) {
+    set_error("NULL result");
+    return RDM_E_INVALID;
+  }
+  if (o.method == RDM_BLOCK || o.profile) {
+    set_error("rdm_solve_noalloc: the per-column method only, without profiling");
+    return RDM_E_INVALID;
+  }
+  // the plan must fit the array (two-pass if the stored basis does not)
+  const uint64_t cap = RDM_NOALLOC_MAX_BYTES;
+  o.budget = o.budget ? std::min<uint64_t>(o.budget, cap) : cap;
+  std::vector<InstPlan> plans(1);
+  s = plan_instance(plans[0], h, n_beta, n_v, k, o.prec, o.mode, o.budget, o.slab, o.rpl);
+  if (s == RDM_E_NOMEM) {
+    set_error("rdm_solve_noalloc: the instance needs more than the " + std::to_string(cap >> 20) +
+              " MiB scratch array even with two passes");
+    return RDM_E_NOMEM;
+  }
+  if (s != RDM_OK) return s;
+  const size_t need = batch_header_bytes(plans) + plans[0].bytes;
+  if (need > cap) {
+    set_error("rdm_solve_noalloc: the instance needs " + std::to_string(need) + " bytes, the scratch array holds " +
+              std::to_string(cap));
+    return RDM_E_NOMEM;
+  }
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  char* ws = nullptr;
+  if ((s = noalloc_workspace(&ws)) != RDM_OK) return s;
+  std::vector<InstRun> runs(1);
+  runs[0].plan = &plans[0];
+  runs[0].betas.assign(beta, beta + n_beta);
+  runs[0].seed = seed;
+  // eager launches (no graph capture, no slab timing events), resident
+  // tables only: nothing below allocates device memory
+  s = execute(runs, ws, (hipStream_t)hip_stream, o.tau, false, false, false, false);
+  if (s == RDM_OK) s = runs[0].status;
+  if (s == RDM_OK) s = finalize(runs[0], out);
+  return s;
 }
 
 namespace {
