@@ -170,6 +170,17 @@ void rdm_hamiltonian_destroy(rdm_hamiltonian* h);
  * internal-energy deviation tr(H* rho*) - tr(H_s rho_s). */
 rdm_status rdm_system_hamiltonian(const rdm_hamiltonian* h, double* out);
 
+/* The internal-energy deviation of Section "Deviation in internal energy"
+ * (formula:deviation_of_Hamiltonian): out[b] = tr(H*(beta_b) rho*(beta_b)) -
+ * tr(H_s rho_s(beta_b)), rho_s = exp(-beta H_s) / tr exp(-beta H_s) the bare
+ * system's thermal state (H_s as rdm_system_hamiltonian).  rho, h_star: host,
+ * n_beta x d_s x d_s row-major, the outputs of a solve at the n_beta inverse
+ * temperatures beta (host, each > 0 and finite); out: host, n_beta.  Zero
+ * when H_sb = 0, where H* = H_s.  RDM_E_INVALID for NULL or bad arguments,
+ * RDM_E_NONFINITE for a non-finite input. */
+rdm_status rdm_energy_deviation(const rdm_hamiltonian* h, int32_t n_beta, const double* beta, const double* rho,
+                                const double* h_star, double* out);
+
 /* Table sizes of a built Hamiltonian: out[0]=N, [1]=n_s, [2]=n_b,
  * [3]=uniform-coefficient hops, [4]=parity-dependent hops, [5]=diagonal terms,
  * [6..8] the same three counts for H_b, [9] / [10] partner-tile groups the

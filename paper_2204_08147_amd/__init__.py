@@ -121,6 +121,17 @@ class Hamiltonian:
         _check(LIB.rdm_system_hamiltonian(self.handle, _dptr(out)), "rdm_system_hamiltonian")
         return out
 
+    def energy_deviation(self, betas, rho, h_star) -> np.ndarray:
+        """tr(H* rho*) - tr(H_s rho_s) per temperature from a solve's rho* and
+        H* (Section "Deviation in internal energy"), computed by the library."""
+        bt = np.ascontiguousarray(np.atleast_1d(betas), dtype=np.float64)
+        r = np.ascontiguousarray(rho, dtype=np.float64)
+        hh = np.ascontiguousarray(h_star, dtype=np.float64)
+        out = np.zeros(len(bt))
+        _check(LIB.rdm_energy_deviation(self.handle, len(bt), _dptr(bt), _dptr(r), _dptr(hh), _dptr(out)),
+               "rdm_energy_deviation")
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             LIB.rdm_hamiltonian_destroy(self.handle)

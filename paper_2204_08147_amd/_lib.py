@@ -69,6 +69,9 @@ SIGNATURES = [
     ("rdm_hamiltonian_destroy", None, [C.c_void_p]),
     ("rdm_hamiltonian_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("rdm_system_hamiltonian", C.c_int32, [C.c_void_p, C.POINTER(C.c_double)]),
+    ("rdm_energy_deviation", C.c_int32,
+     [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+      C.POINTER(C.c_double)]),
     ("rdm_solve", C.c_int32,
      [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
       C.POINTER(Options), C.c_void_p, C.POINTER(Result)]),

@@ -1,9 +1,9 @@
 """Parameter scans and observables on top of the solver (the paper's
 numerical experiments on long-range chains): entropy over a grid of
 temperatures and fields, the internal-energy deviation tr(H* rho*) -
-tr(H_s rho_s), and the system-bath coupling sweep.  Every solve runs through
-the C ABI (batched: one Lanczos run per Hamiltonian serves all its
-temperatures); only d_s x d_s post-processing happens here.
+tr(H_s rho_s), and the system-bath coupling sweep.  Every solve and the
+deviation run through the C ABI (batched: one Lanczos run per Hamiltonian
+serves all its temperatures); this module only arranges the results.
 """
 from __future__ import annotations
 
@@ -14,36 +14,21 @@ import numpy as np
 from . import Hamiltonian, solve_batch
 
 
-def bare_system_rho(hs: np.ndarray, beta: float) -> np.ndarray:
-    """rho_s(beta) = exp(-beta H_s) / tr exp(-beta H_s) of the bare system."""
-    w, v = np.linalg.eigh(hs)
-    p = np.exp(-beta * (w - w.min()))
-    p /= p.sum()
-    return (v * p) @ v.T
-
-
-def energy_deviation(result: dict, hs: np.ndarray, betas: Sequence[float]) -> np.ndarray:
-    """tr(H*(beta) rho*(beta)) - tr(H_s rho_s(beta)) per temperature (Section
-    "Deviation in internal energy"): zero when the system-bath coupling
-    vanishes, where H* = H_s."""
-    out = []
-    for b, beta in enumerate(betas):
-        out.append(float(np.trace(result["h_star"][b] @ result["rho"][b])
-                         - np.trace(hs @ bare_system_rho(hs, beta))))
-    return np.array(out)
-
-
 def run(instances: Iterable, **opts) -> List[dict]:
     """One batched solve over the instances (each with its own temperatures,
     bath vectors, k and seed).  Returns per-instance result dicts with the
-    instance's H_s attached."""
+    instance's H_s and the internal-energy deviation tr(H* rho*) -
+    tr(H_s rho_s) per temperature (Section "Deviation in internal energy",
+    computed by the library) attached."""
     insts = list(instances)
     hs = [Hamiltonian.from_instance(i) for i in insts]
     try:
         items = [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
         out = solve_batch(items, **opts)
-        for o, h in zip(out, hs):
+        for o, h, i in zip(out, hs, insts):
             o["h_s"] = h.system_matrix()
+            if o["status"] == 0:
+                o["deviation"] = h.energy_deviation(i.betas, o["rho"], o["h_star"])
     finally:
         for h in hs:
             h.close()
@@ -71,5 +56,5 @@ def deviation_scan(make: Callable[[float], object], values: Sequence[float], **o
     for r, i in zip(res, insts):
         if r["status"] != 0:
             raise RuntimeError(f"solve failed with status {r['status']}")
-        rows.append(energy_deviation(r, r["h_s"], i.betas))
+        rows.append(r["deviation"])
     return np.array(rows)

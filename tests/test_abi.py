@@ -229,3 +229,33 @@ def test_auto_method_picks_block_when_the_basis_does_not_fit():
     two = rdm.workspace_size(h, 1, 4, 30, precision="fp64", mode="two_pass", hbm_budget=1 << 40)
     assert rdm.workspace_size(h, 1, 4, 30, precision="fp64", method="auto", mode="two_pass",
                               hbm_budget=1 << 40) == two
+
+
+def test_energy_deviation_host_routine():
+    # tr(H* rho*) - tr(H_s rho_s) from given rho*, H* (Section "Deviation in
+    # internal energy"): against the same formula written with eigh here, on
+    # random density matrices; zero when H* = H_s and rho* = rho_s
+    from oracle import spin
+    inst = random_dense_terms(3, 4, 27)
+    h = rdm.Hamiltonian.from_instance(inst)
+    hs, _, _ = spin.split_dense(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz)
+    rng = np.random.default_rng(4)
+    betas = np.array([0.3, 1.0, 5.0])
+    rho, hst = [], []
+    for _ in betas:
+        a = rng.normal(size=(8, 8))
+        r = a @ a.T
+        rho.append(r / np.trace(r))
+        b = rng.normal(size=(8, 8))
+        hst.append(b + b.T)
+    rho, hst = np.array(rho), np.array(hst)
+    got = h.energy_deviation(betas, rho, hst)
+    w, v = np.linalg.eigh(hs)
+    for t, beta in enumerate(betas):
+        p = np.exp(-beta * (w - w.min()))
+        rho_s = (v * (p / p.sum())) @ v.T
+        want = np.trace(hst[t] @ rho[t]) - np.trace(hs @ rho_s)
+        assert abs(got[t] - want) < 1e-12 * max(1.0, abs(want))
+        assert abs(h.energy_deviation([beta], rho_s[None], hs[None])[0]) < 1e-12
+    with pytest.raises(rdm.RdmError):
+        h.energy_deviation([0.0], rho[:1], hst[:1])
