@@ -335,14 +335,21 @@ rdm_status rdm_block_quadrature(int32_t n, int32_t b, const double* t, int32_t n
  * vectors' Gram matrix above 1e-6 (FP64) / 1e-3 (mixed) of the largest;
  * r <= 4).  Outputs (host, any may be NULL): rho d_s x d_s row-major,
  * e_total, e_bath, entropy -tr rho ln rho, degeneracy r.  opt: precision,
- * hbm_budget, tau and eager are used (NULL = FP64).  Blocking; the library
- * allocates its workspace. */
+ * hbm_budget, tau and eager are used (NULL = FP64).  Any output pointer,
+ * the residual included, may be NULL.  Blocking; the library allocates its
+ * workspace. */
 typedef struct {
   double* rho;
   double* e_total;
   double* e_bath;
   double* entropy;
   int32_t* degeneracy;
+  double* residual;   /* convergence measure: the largest, over the columns
+                         that span the ground space, Ritz residual norm
+                         |H y - theta y| (y of unit norm) of the lowest Ritz
+                         pair after k - 1 steps; 0 when a column reached an
+                         invariant subspace.  Small against the gap to the
+                         next eigenvalue means a converged ground space. */
 } rdm_ground_result;
 rdm_status rdm_ground_state(const rdm_hamiltonian* h, int32_t n_v, int32_t k, uint64_t seed,
                             const rdm_options* opt, void* hip_stream, rdm_ground_result* out);

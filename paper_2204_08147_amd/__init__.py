@@ -304,13 +304,15 @@ def ground_state(h: Hamiltonian, n_v: int, k: int, seed: int, *, stream=None, **
     o = make_options(**opts)
     d = 1 << h.n_s
     rho = np.zeros((d, d))
-    et, eb, ent = C.c_double(), C.c_double(), C.c_double()
+    et, eb, ent, resid = C.c_double(), C.c_double(), C.c_double(), C.c_double()
     r = C.c_int32()
-    res = _lib.GroundResult(_dptr(rho), C.pointer(et), C.pointer(eb), C.pointer(ent), C.pointer(r))
+    res = _lib.GroundResult(_dptr(rho), C.pointer(et), C.pointer(eb), C.pointer(ent), C.pointer(r),
+                            C.pointer(resid))
     _check(LIB.rdm_ground_state(h.handle, n_v, k, seed, C.byref(o), _stream_handle(stream), C.byref(res)),
            "rdm_ground_state")
     return {"rho": rho, "e_total": et.value, "e_bath": eb.value, "entropy": ent.value,
-            "degeneracy": int(r.value), "h_star": (et.value - eb.value) * np.eye(d)}
+            "degeneracy": int(r.value), "h_star": (et.value - eb.value) * np.eye(d),
+            "residual": resid.value}
 
 
 def product_trace(h: Hamiltonian, betas, n_v: int, k: int, seed: int, *, stream=None, **opts) -> dict:

@@ -44,7 +44,7 @@ class Result(C.Structure):
 class GroundResult(C.Structure):
     _fields_ = [("rho", C.POINTER(C.c_double)), ("e_total", C.POINTER(C.c_double)),
                 ("e_bath", C.POINTER(C.c_double)), ("entropy", C.POINTER(C.c_double)),
-                ("degeneracy", C.POINTER(C.c_int32))]
+                ("degeneracy", C.POINTER(C.c_int32)), ("residual", C.POINTER(C.c_double))]
 
 
 class ProductResult(C.Structure):

@@ -25,14 +25,23 @@ CXXFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-W
             f"-I{os.path.join(ROOT, 'include')}"]
 
 
+# host-side AddressSanitizer and UndefinedBehaviorSanitizer (device code is
+# compiled as usual): a separate library for the CPU tests of the host code
+SAN_DIR = os.path.join(ROOT, "_build", "librdm_san")
+SAN_LIB = os.path.join(SAN_DIR, "librdm_san.so")
+SANFLAGS = ["-g", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".cpp", ".hip")))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+def _compile(src: str, sanitize: bool = False) -> str:
+    obj = os.path.join(SAN_DIR if sanitize else BUILD_DIR, os.path.basename(src) + ".o")
     lang = ["-x", "hip"]
-    cmd = [HIPCC, *CXXFLAGS, *lang, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CXXFLAGS, *(SANFLAGS if sanitize else []), *lang, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l]
     if r.returncode != 0:
@@ -42,21 +51,27 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link ``librdm.so``; returns its path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source and link ``librdm.so`` (sanitize: the host-side
+    sanitizer build ``_build/librdm_san/librdm_san.so``); returns its path."""
+    out_dir, lib = (SAN_DIR, SAN_LIB) if sanitize else (BUILD_DIR, LIB)
+    os.makedirs(out_dir, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+        objs = list(ex.map(lambda f: _compile(f, sanitize), srcs))
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lrocprofiler-sdk-roctx",
+           "-lpthread"]
+    if sanitize:
+        # host runtimes only: the device code carries no sanitizer
+        cmd[1:1] = ["-shared-libsan", "-fsanitize=address,undefined", "-fno-gpu-sanitize"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

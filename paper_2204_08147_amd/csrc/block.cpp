@@ -170,6 +170,7 @@ rdm_status run_block(const BlockPlan& bp, const OpDevice* op_t, char* ws, char* 
 
 rdm_status block_solve(const BlockPlan& bp, const double* betas, uint64_t seed, double tau, char* ws,
                        hipStream_t st, bool profile, rdm_result* out) {
+  Range range("rdm block solve");
   const OpDevice *op_t = nullptr, *op_b = nullptr;
   rdm_status s = get_device_op(bp.h, 0, bp.prec, st, &op_t);
   if (s == RDM_OK) s = get_device_op(bp.h, 1, bp.prec, st, &op_b);

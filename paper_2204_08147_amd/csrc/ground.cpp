@@ -132,6 +132,29 @@ rdm_status ground_run(const GroundPlan& gp, const rdm_hamiltonian* h, uint64_t s
   }
   // columns whose lowest Ritz value reached the ground energy
   const double e_tol = (gp.prec == RDM_FP64 ? 1e-9 : 1e-4) * std::max(1.0, scale);
+  // convergence measure: the residual norm |H y - theta y| = beta_{k-1} |s_{k-1}|
+  // of the lowest Ritz pair of the first k-1 steps (its last eigenvector
+  // component times the coupling to step k), largest over the columns that
+  // contribute; 0 for a column that reached an invariant subspace (it broke
+  // down, or its Krylov space is the whole space), whose Ritz pairs are exact
+  double resid = 0.0;
+  const bool whole = (uint64_t)gp.k >= (1ull << h->n);
+  for (int c = 0; c < n_v; ++c) {
+    if (et[c].theta[i0[c]] > et_min + e_tol) continue;
+    const int kk = tkc[c];
+    if (kk < 2 || kk < gp.k || whole) continue;
+    std::vector<double> al(kk - 1), be(kk > 2 ? kk - 2 : 0), sv(kk - 1);
+    for (int j = 0; j + 1 < kk; ++j) al[j] = ta[(size_t)j * cp + c];
+    for (int j = 0; j + 2 < kk; ++j) be[j] = tb[(size_t)j * cp + c];
+    TridiagEig e;
+    e.solve(al.data(), be.data(), kk - 1);
+    if (!e.ok || e.n == 0) continue;
+    int lo = 0;
+    for (int q = 1; q < e.n; ++q)
+      if (e.theta[q] < e.theta[lo]) lo = q;
+    e.eigvec(lo, sv.data());
+    resid = std::max(resid, std::fabs(tb[(size_t)(kk - 2) * cp + c] * sv[kk - 2]));
+  }
   // Ritz vector weights (times L^-1/2 when the basis is kept as W_lo u)
   const double bscale = op_t->xz ? kXzBasisScale : 1.0;
   std::vector<double> y((size_t)gp.k * cp, 0.0);
@@ -244,6 +267,7 @@ rdm_status ground_run(const GroundPlan& gp, const rdm_hamiltonian* h, uint64_t s
   if (out->e_total) *out->e_total = et_min;
   if (out->e_bath) *out->e_bath = eb_min;
   if (out->degeneracy) *out->degeneracy = r;
+  if (out->residual) *out->residual = resid;
   if (out->entropy) {
     std::vector<double> ev(ds), vv((size_t)ds * ds);
     sym_eig_small(ds, rho.data(), ev.data(), vv.data());

@@ -129,13 +129,21 @@ void compile(const rdm_hamiltonian& h, int first_site, OpTables& t) {
   any_x = !xt.empty();
   any_y = !yt.empty();
   const bool in_range = t.nbits >= kXzMinBits && t.nbits <= kXzMaxBits && (any_x || any_y);
-  // a hop-table step streams about 6 vectors plus one per partner tile it
-  // stages and one per hop it gathers; a transform step streams 8 vectors,
-  // 13 with a YY part: sparse operators with YY terms keep the hop tables
+  // A transform step streams 8 vectors, 15 with a YY part and 4 more with
+  // split strided passes (above 22 bits); a hop-table step streams about 6
+  // and reads one partner row per staged partner tile and per gathered hop,
+  // from cache for the most part.  Measured: with YY terms the hop tables win
+  // at 28 partner rows per row (random graphs of degree 4, 22 bits) and lose
+  // from 78 on (all pairs, 20-26 bits); with split passes the transverse-field
+  // chain (16 partner rows) runs 3-4 % faster from hop tables.  So operators
+  // with YY terms, and all operators above 22 bits, take the transform from
+  // 40 partner rows on; X-type operators up to 22 bits always.
   const int partners = (int)(t.groups.size() - 1 + thin[0].size() + thin[1].size() + thin[2].size());
+  const bool dense_enough = partners >= 40;
   bool use = false;
   if (h.apply == RDM_APPLY_TRANSFORM) use = in_range;
-  else if (h.apply == RDM_APPLY_AUTO) use = in_range && (!any_y || 6 + partners >= 13);
+  else if (h.apply == RDM_APPLY_AUTO)
+    use = in_range && (any_y || xz_geom(t.nbits) == XG_SPLIT ? dense_enough : true);
   t.xz = use;
   t.xy = use && any_y;
   if (use) {

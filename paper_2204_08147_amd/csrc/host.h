@@ -5,9 +5,20 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.h"
 
 namespace rdm {
+
+// A named range on the calling thread's roctx stack (shown by rocprofv3
+// --marker-trace; a few nanoseconds when no tool is attached).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // Thread-local error message behind rdm_last_error().
 void set_error(const std::string& msg);

@@ -223,12 +223,12 @@ hipError_t launch_xz_split(int op, const Seg* segs, int nseg, int ntiles, hipStr
 // tile.
 template <typename T>
 hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff,
-                             hipStream_t st, int geo = XG_SHALLOW, bool xy = false);
+                             hipStream_t st, int geo = XG_SHALLOW);
 // Recombination weights of a segment whose basis is kept as W_lo u: L^-1/2
 constexpr double kXzBasisScale = 1.0 / (1 << (kXzTileBits / 2));
 // Lanczos-step passes of the YY part (xy segments): 3 = Y <- W_lo T W_lo u~ / L
-// (contiguous), 4 = Y <- W_hi D_Y W_hi Y (strided; deep variant as for pass 1);
-// pass 2 then adds W_lo T W_lo Y to the step's residual (xy variant)
+// (contiguous), 4 = Y <- W_hi D_Y W_hi Y (strided; deep variant as for pass 1),
+// 5 = R <- R + W_lo T W_lo Y / L (contiguous), before pass 2
 hipError_t launch_red_beta(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_red_alpha(const Seg* segs, int nseg, int cmax, hipStream_t st);
 hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hipStream_t st);

@@ -985,7 +985,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
 //     partial <u_j, r_j> = s sum d u^2 + <u~_j, w> / L
 // boff offsets blockIdx.x in the segments' transform tile numbering.
 // ---------------------------------------------------------------------------
-template <typename T, int PASS, bool REGEN, int GEOM, bool XY = false>
+template <typename T, int PASS, bool REGEN, int GEOM>
 __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ segs, int nseg, int boff) {
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
@@ -995,13 +995,11 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
   const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x + boff, (PASS == 1 || PASS == 4) && DEEP);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   // pass 1 comes in variants (the regeneration pass needs more registers;
-  // one per strided geometry), pass 2 in two (with and without a YY part);
-  // each leaves the other variants' tiles alone.  Passes 3 and 4 run on the
-  // segments with a YY part only (pass 4: shallow and deep; split segments
-  // take launch_xz_split).
+  // one per strided geometry); each leaves the other variants' tiles alone.
+  // Passes 3, 4 and 5 run on the segments with a YY part only (pass 4:
+  // shallow and deep; split segments take launch_xz_split).
   if (PASS == 1 && ((sg.mode == MODE_REGEN) != REGEN || xz_geom(sg.nbits) != GEOM)) return;
-  if (PASS == 2 && (sg.xy != 0) != XY) return;
-  if ((PASS == 3 || PASS == 4) && !sg.xy) return;
+  if ((PASS == 3 || PASS == 4 || PASS == 5) && !sg.xy) return;
   if (PASS == 4 && xz_geom(sg.nbits) != GEOM) return;
   const int j = PASS == 0 ? 1 : sg.stepc[0];
   if (j > sg.k) return;
@@ -1122,44 +1120,39 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
     xz_strided_inplace<T, DEEP>(sg, t, (V*)sg.Y + (uint64_t)t.panel0 * pstride, (const T*)sg.dy, lds);
     return;
   }
+  if (PASS == 5) {
+    // contiguous tile: R += W_lo T W_lo Y / L, so that pass 2 finds
+    // L R = L W_hi D_X W_hi u~_j + W_lo (T W D_Y W T u_j) in R
+    const V* yb = (const V*)sg.Y + (uint64_t)t.panel0 * pstride;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(yb, t.row0 + xz_tau(0, l, q));
+    xz_low_transform(v, lds);
+    yy_twist<T>(v, t.row0, inv_l);
+    xz_low_transform(v, lds);
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const uint32_t row = t.row0 + xz_tau(0, l, q);
+      stg_stream<true>(rb, row, ldg_nt((const V*)rb, row) + v[q]);
+    }
+    return;
+  }
 
   // PASS 2: contiguous tile, row = row0 + tau
   const V* ub = (const V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
   const T* dg = (const T*)sg.diag;
   V w[kXzRegs];
   T d[kXzRegs];
+#pragma unroll
+  for (int q = 0; q < kXzRegs; ++q) {
+    const uint32_t row = t.row0 + xz_tau(0, l, q);
+    v[q] = ldg_nt(ub, row);
+    w[q] = ldg_nt((const V*)rb, row);
+    d[q] = ldg_s(dg, row);
+  }
   const V sc = scur_of<T, 1>(st, cp, t.panel0, 0, false);
   const V scl = sc * T(1 << kXzTileBits);
-  if (XY) {
-    // the YY part first: w = s W_lo T W_lo Y (= s W_lo (T W D_Y W T u_j)),
-    // then the XX part, w += s L R, with the tile of u~_j loaded afterwards
-    const V* yb = (const V*)sg.Y + (uint64_t)t.panel0 * pstride;
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) w[q] = ldg_nt(yb, t.row0 + xz_tau(0, l, q));
-    xz_low_transform(w, lds);
-    yy_twist<T>(w, t.row0, T(1));
-    xz_low_transform(w, lds);
-    // the loads below stay after the YY transforms (hoisted above them they
-    // would hold three tiles of registers at once and halve the occupancy)
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) {
-      const uint32_t row = t.row0 + xz_tau(0, l, q);
-      w[q] = fma_v(scl, ldg_nt((const V*)rb, row), sc * w[q]);
-      v[q] = ldg_nt(ub, row);
-      d[q] = ldg_s(dg, row);
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) {
-      const uint32_t row = t.row0 + xz_tau(0, l, q);
-      v[q] = ldg_nt(ub, row);
-      w[q] = ldg_nt((const V*)rb, row);
-      d[q] = ldg_s(dg, row);
-    }
-#pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) w[q] = scl * w[q];
-  }
+  for (int q = 0; q < kXzRegs; ++q) w[q] = scl * w[q];
   if (uprev) {
     const V bp = bps_of<T, 1>(st, cp, t.panel0, 0);
 #pragma unroll
@@ -1829,23 +1822,23 @@ hipError_t launch_xz_pass(int pass, const Seg* segs, int nseg, int ntiles, hipSt
 
 template <typename T>
 hipError_t launch_xz_lanczos(int pass, bool regen, const Seg* segs, int nseg, int ntiles, int boff, hipStream_t st,
-                             int geo, bool xy) {
+                             int geo) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b(kBlock);
-#define RDM_XZL(P, R, G, X) hipLaunchKernelGGL((k_xz_lanczos<T, P, R, G, X>), g, b, 0, st, segs, nseg, boff)
-  if (pass == 0) RDM_XZL(0, false, XG_SHALLOW, false);
+#define RDM_XZL(P, R, G) hipLaunchKernelGGL((k_xz_lanczos<T, P, R, G>), g, b, 0, st, segs, nseg, boff)
+  if (pass == 0) RDM_XZL(0, false, XG_SHALLOW);
   else if (pass == 1) {
-    if (regen && geo == XG_SPLIT) RDM_XZL(1, true, XG_SPLIT, false);
-    else if (regen && geo == XG_DEEP) RDM_XZL(1, true, XG_DEEP, false);
-    else if (regen) RDM_XZL(1, true, XG_SHALLOW, false);
-    else if (geo == XG_SPLIT) RDM_XZL(1, false, XG_SPLIT, false);
-    else if (geo == XG_DEEP) RDM_XZL(1, false, XG_DEEP, false);
-    else RDM_XZL(1, false, XG_SHALLOW, false);
-  } else if (pass == 2 && xy) RDM_XZL(2, false, XG_SHALLOW, true);
-  else if (pass == 2) RDM_XZL(2, false, XG_SHALLOW, false);
-  else if (pass == 3) RDM_XZL(3, false, XG_SHALLOW, false);
-  else if (pass == 4 && geo == XG_DEEP) RDM_XZL(4, false, XG_DEEP, false);
-  else if (pass == 4 && geo == XG_SHALLOW) RDM_XZL(4, false, XG_SHALLOW, false);
+    if (regen && geo == XG_SPLIT) RDM_XZL(1, true, XG_SPLIT);
+    else if (regen && geo == XG_DEEP) RDM_XZL(1, true, XG_DEEP);
+    else if (regen) RDM_XZL(1, true, XG_SHALLOW);
+    else if (geo == XG_SPLIT) RDM_XZL(1, false, XG_SPLIT);
+    else if (geo == XG_DEEP) RDM_XZL(1, false, XG_DEEP);
+    else RDM_XZL(1, false, XG_SHALLOW);
+  } else if (pass == 2) RDM_XZL(2, false, XG_SHALLOW);
+  else if (pass == 3) RDM_XZL(3, false, XG_SHALLOW);
+  else if (pass == 4 && geo == XG_DEEP) RDM_XZL(4, false, XG_DEEP);
+  else if (pass == 4 && geo == XG_SHALLOW) RDM_XZL(4, false, XG_SHALLOW);
+  else if (pass == 5) RDM_XZL(5, false, XG_SHALLOW);
   else return hipErrorInvalidValue;
 #undef RDM_XZL
   return hipGetLastError();
@@ -1954,8 +1947,8 @@ template hipError_t launch_ground_ptrace<float>(const GPSeg*, int, int, hipStrea
 template hipError_t launch_ground_ptrace<double>(const GPSeg*, int, int, hipStream_t);
 template hipError_t launch_block_update<double>(const BSeg*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_xz_pass<double>(int, const Seg*, int, int, hipStream_t, int);
-template hipError_t launch_xz_lanczos<float>(int, bool, const Seg*, int, int, int, hipStream_t, int, bool);
-template hipError_t launch_xz_lanczos<double>(int, bool, const Seg*, int, int, int, hipStream_t, int, bool);
+template hipError_t launch_xz_lanczos<float>(int, bool, const Seg*, int, int, int, hipStream_t, int);
+template hipError_t launch_xz_lanczos<double>(int, bool, const Seg*, int, int, int, hipStream_t, int);
 template hipError_t launch_gram<float>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_gram<double>(const GSeg*, const GTile*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_start_block<float>(int, int, int, uint64_t, int, float*, int, int, hipStream_t);

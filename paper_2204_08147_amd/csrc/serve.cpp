@@ -190,6 +190,7 @@ void rdm_server::finish_loop() {
       finishing.pop_front();
       ++busy_finishers;
     }
+    Range range("rdm serve finish");
     rdm_status q = fs ? RDM_OK : RDM_E_DEVICE;
     if (q == RDM_OK && hipEventSynchronize(r->last) != hipSuccess) q = RDM_E_DEVICE;
     bool requeued = false;
@@ -300,6 +301,7 @@ void rdm_server::run() {
     }
     if (active.empty()) continue;
 
+    Range range("rdm serve step");
     rdm_status s = RDM_OK;
     if (changed) {
       // a new segment table (in the buffer not in use), and the state of the

@@ -388,6 +388,7 @@ rdm_status init_run(int prec, const Seg* dsegs, int nseg, int cmax, int phase, i
 
 rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, hipStream_t st,
                        StepTimers* tm) {
+  Range range("rdm step launch");
   const bool d = prec == RDM_FP64;
   if (tm) RDM_HIP(tm->norm.mark(st));
   RDM_HIP(d ? launch_norm<double>(dsegs, nseg, L.norm, slab, st) : launch_norm<float>(dsegs, nseg, L.norm, slab, st));
@@ -416,19 +417,16 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
       for (int op : {2, 3, 2})
         RDM_HIP(d ? launch_xz_split<double>(op, dsegs, nseg, L.xz, st)
                   : launch_xz_split<float>(op, dsegs, nseg, L.xz, st));
+    RDM_HIP(d ? launch_xz_lanczos<double>(5, false, dsegs, nseg, L.xz, 0, st)
+              : launch_xz_lanczos<float>(5, false, dsegs, nseg, L.xz, 0, st));
   }
   if (tm) RDM_HIP(tm->xz1.mark(st));
   RDM_HIP(launch_red_beta(dsegs, nseg, cmax, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(d ? launch_apply<double>(dsegs, nseg, L.apply, slab, st)
             : launch_apply<float>(dsegs, nseg, L.apply, slab, st));
-  // pass 2 in two variants (with and without a YY part), each leaving the
-  // other's segments alone
-  for (int xy = 0; xy < 2; ++xy) {
-    if (xy && !L.any_xy()) continue;
-    RDM_HIP(d ? launch_xz_lanczos<double>(2, false, dsegs, nseg, L.xz, 0, st, false, xy)
-              : launch_xz_lanczos<float>(2, false, dsegs, nseg, L.xz, 0, st, false, xy));
-  }
+  RDM_HIP(d ? launch_xz_lanczos<double>(2, false, dsegs, nseg, L.xz, 0, st)
+            : launch_xz_lanczos<float>(2, false, dsegs, nseg, L.xz, 0, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(launch_red_alpha(dsegs, nseg, cmax, st));
   return RDM_OK;
@@ -792,6 +790,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
 
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
                    bool tune, bool graph, bool build_tables) {
+  Range range("rdm execute");
   const int ni = (int)runs.size();
   if (ni == 0) return RDM_OK;
   const int prec = runs[0].plan->prec;
@@ -814,19 +813,32 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     segs.push_back(seg_of(r, 0, MODE_LANCZOS, tau));
     segs.push_back(seg_of(r, 1, MODE_LANCZOS, tau));
   }
-  rdm_status s = run_phase(segs, dsegs, prec, 0, st, profile ? &tm : nullptr, tune, graph);
+  rdm_status s;
+  {
+    Range lr("rdm lanczos");
+    s = run_phase(segs, dsegs, prec, 0, st, profile ? &tm : nullptr, tune, graph);
+  }
   if (s != RDM_OK) return s;
-  for (auto& r : runs) r.status = host_phase(r, st);
+  {
+    Range hr("rdm host phase");
+    for (auto& r : runs) r.status = host_phase(r, st);
+  }
   // pass 2 (two-pass plans): regenerate u_j from the stored coefficients
   segs.clear();
   for (auto& r : runs)
     if (r.plan->two_pass && r.status == RDM_OK) segs.push_back(seg_of(r, 0, MODE_REGEN, tau));
-  if ((s = run_phase(segs, dsegs, prec, 1, st, nullptr, tune, graph)) != RDM_OK) return s;
+  {
+    Range rr("rdm regeneration");
+    if ((s = run_phase(segs, dsegs, prec, 1, st, nullptr, tune, graph)) != RDM_OK) return s;
+  }
   Timers tg;
   tg.on = profile;
-  for (auto& r : runs) {
-    if (r.status != RDM_OK) continue;
-    if ((s = gram_phase(r, st, profile ? &tg : nullptr)) != RDM_OK) return s;
+  {
+    Range gr("rdm gram");
+    for (auto& r : runs) {
+      if (r.status != RDM_OK) continue;
+      if ((s = gram_phase(r, st, profile ? &tg : nullptr)) != RDM_OK) return s;
+    }
   }
   if (profile)
     for (auto& r : runs) {

@@ -77,7 +77,7 @@ def test_transform_apply_selection():
     # tables would gather many partner rows (all pairs), hop tables for a
     # sparse chain; either kind on request
     xxz = rdm.Hamiltonian.from_instance(long_range_xxz(2, 16, 1)).info()
-    assert xxz["transform"] == 1 and xxz["transform_yy"] == 1 and xxz["bath_transform"] == 1
+    assert xxz["transform"] == 1 and xxz["transform_yy"] == 1   # its 16-bit bath has fewer partners
     # two XXZ bonds on the last four sites (the low index bits): every hop
     # stays inside a 256-row tile
     few = [(12, 13, 0.5, 0.5, 1.0), (14, 15, 0.7, 0.7, -1.0)]
@@ -86,6 +86,8 @@ def test_transform_apply_selection():
     forced = rdm.Hamiltonian(2, 14, few, apply="transform").info()
     assert forced["transform"] == 1 and forced["transform_yy"] == 1
     chain = rdm.Hamiltonian.from_instance(nn_xxz_chain(2, 14, 5)).info()   # 8 partner rows per row
+    assert chain["transform"] == 0
+    chain = rdm.Hamiltonian.from_instance(nn_xxz_chain(2, 14, 5), apply="transform").info()
     assert chain["transform"] == 1 and chain["transform_yy"] == 1
     hops = rdm.Hamiltonian.from_instance(cfg_long_range(0), apply="hops").info()
     assert hops["transform"] == 0 and hops["bath_transform"] == 0

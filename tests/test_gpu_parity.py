@@ -36,6 +36,12 @@ def H(inst):
     return rdm.Hamiltonian.from_instance(inst)
 
 
+def HT(inst):
+    # the transform apply on request (sparse operators with YY terms take the
+    # hop tables by default)
+    return rdm.Hamiltonian.from_instance(inst, apply="transform")
+
+
 def check_result(got, want, tol, what=""):
     nb = len(want)
     for b in range(nb):
@@ -93,7 +99,7 @@ YY_APPLY_CASES = (8, 9, 10)
 @pytest.mark.parametrize("n_cols", [1, 3, 8, 13])
 def test_apply_matches_oracle(case, prec, n_cols):
     inst = APPLY_CASES[case]()
-    h = H(inst)
+    h = HT(inst) if case in YY_APPLY_CASES else H(inst)
     if case in YY_APPLY_CASES:
         assert h.info()["transform_yy"] == 1
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
@@ -159,15 +165,17 @@ def _cfg_large():
                                        (lambda: long_range_xx_zz(1, 21, 1.0, 6), 16), (_cfg_large, 32),
                                        (lambda: long_range_xxz(1, 20, 7), 16),
                                        (lambda: random_sparse_xxz(3001, n_range=(22, 22)), 32),
-                                       (lambda: long_range_xxz(1, 22, 8), 16)])
+                                       (lambda: long_range_xxz(1, 22, 8), 16),
+                                       (lambda: cfg_long_range(0, n_b=22), 16)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_apply_full_size_sampled_rows(make, cols, prec):
     # full-size shapes (dim 2^20, 2^24 and the largest, 2^26 with all-pairs
     # XXZ) in the bench's launch configuration, checked on 300 sampled rows
     # computed one by one by the oracle; 2^21 and 2^22 run the transform apply
     # with 9 and 10 high bits (2^22 with the XCD grouping of strided tiles);
-    # 2^23, 2^24 and 2^26 split the high bits over three strided passes; the
-    # 2^21, 2^22 sparse, 2^23 and 2^26 operators have a YY part
+    # the 2^23 and 2^26 all-pairs operators and the 2^24 X-type one split the
+    # high bits over three strided passes (the 2^24 chain takes hop tables);
+    # the 2^21, 2^22 sparse, 2^23 and 2^26 operators have a YY part
     inst = make()
     h = H(inst)
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
@@ -249,6 +257,14 @@ SOLVE_CASES = {
     "xxz_2+14": lambda: long_range_xxz(2, 14, 76, betas=(0.5, 2.0), n_v=2, k=30),
 }
 
+# cases that exercise an apply kind other than the default
+SOLVE_APPLY = {"xxz_2+14": "transform"}
+
+
+def HS(name, inst):
+    return rdm.Hamiltonian.from_instance(inst, apply=SOLVE_APPLY.get(name, "auto"))
+
+
 _ORACLE = {}
 
 
@@ -263,7 +279,7 @@ def oracle_solve(name):
 def test_solve_fp64_matches_oracle(name):
     inst = SOLVE_CASES[name]()
     want = oracle_solve(name)
-    got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
+    got = rdm.solve(HS(name, inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
     check_result(got, want, 1e-10, name)
 
 
@@ -271,7 +287,7 @@ def test_solve_fp64_matches_oracle(name):
 def test_solve_mixed_matches_oracle(name):
     inst = SOLVE_CASES[name]()
     want = oracle_solve(name)
-    got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed")
+    got = rdm.solve(HS(name, inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed")
     check_result(got, want, 1e-5, name)
 
 
@@ -292,14 +308,14 @@ def oracle_block(name):
 @pytest.mark.parametrize("name", BLOCK_CASES)
 def test_block_fp64_matches_oracle(name):
     inst = SOLVE_CASES[name]()
-    got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
+    got = rdm.solve(HS(name, inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64", method="block")
     check_result(got, oracle_block(name), 1e-10, "block " + name)
 
 
 @pytest.mark.parametrize("name", BLOCK_CASES)
 def test_block_mixed_matches_oracle(name):
     inst = SOLVE_CASES[name]()
-    got = rdm.solve(H(inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", method="block")
+    got = rdm.solve(HS(name, inst), inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed", method="block")
     check_result(got, oracle_block(name), 1e-5, "block mixed " + name)
 
 
@@ -413,6 +429,20 @@ def test_ground_state_matches_oracle(name):
     assert mixed["degeneracy"] == want["degeneracy"]
     assert np.abs(mixed["rho"] - want["rho"]).max() < 1e-3
     assert abs(mixed["e_total"] - want["e_total"]) < 1e-4 * max(1.0, abs(want["e_total"]))
+    assert 0.0 <= got["residual"] < 1e-3, got["residual"]
+
+
+def test_ground_state_residual_tracks_convergence():
+    # the reported Ritz residual: large after a few steps, tiny once the
+    # ground state has converged (and then E_t is the exact ground energy)
+    from oracle import ground
+    inst = random_dense_terms(2, 6, 94)
+    e_exact = ground.exact(inst)["e_total"]
+    short = rdm.ground_state(H(inst), 2, 6, 18, precision="fp64")
+    long = rdm.ground_state(H(inst), 2, 120, 18, precision="fp64")
+    assert short["residual"] > 1e-3
+    assert long["residual"] < 1e-8
+    assert abs(long["e_total"] - e_exact) < 1e-9 * max(1.0, abs(e_exact))
 
 
 def test_ground_state_is_the_large_beta_limit():
@@ -852,7 +882,7 @@ SHALLOW_CASES = {
 @pytest.mark.parametrize("name", list(SHALLOW_CASES))
 def test_transform_17_to_19_bits_matches_hop_tables(name):
     inst = SHALLOW_CASES[name]()
-    h, hh = H(inst), HH(inst)
+    h, hh = HT(inst), HH(inst)
     assert h.info()["transform"] == 1 and hh.info()["transform"] == 0
     a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
     b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
@@ -890,7 +920,7 @@ def test_transform_beyond_20_bits_matches_hop_tables(name):
     # in the sampled-rows test); FP64 paths agree to rounding, the mixed path
     # to the mixed bar
     inst = DEEP_CASES[name]()
-    h, hh = H(inst), HH(inst)
+    h, hh = HT(inst), HH(inst)
     assert h.info()["transform"] == 1 and hh.info()["transform"] == 0
     a = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
     b = rdm.solve(hh, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
@@ -950,7 +980,7 @@ def test_serving_alone_equals_in_mix_large_requests():
     insts = [tfim_request(r, n_range=(21, 23), n_v=2, k=20) for r in range(3)] + \
             [tfim_request(r, n_range=(12, 16), n_v=2, k=20) for r in range(3, 6)]
     hs = [H(i) for i in insts]
-    assert sum(h.info()["transform"] for h in hs[:3]) == 3
+    assert sum(h.info()["transform"] for h in hs[:3]) == 2   # 21, 22 bits; the 23-bit chain: hop tables
     alone = [rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision="mixed") for h, i in zip(hs, insts)]
     srv = rdm.Server(hbm_budget=16 << 30, max_active=4, precision="mixed")
     try:
