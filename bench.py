@@ -818,7 +818,9 @@ def main():
         n_d = len(lat_d)
         fp64 = {"solves_per_s": n_d / wall_d, "p50_ms": 1e3 * float(np.percentile(lat_d, 50)),
                 "p99_ms": 1e3 * float(np.percentile(lat_d, 99)),
-                "step_kernels_ms": float(np.mean(ap_d) + np.mean(no_d) + np.mean(x0_d))}
+                "step_kernels_ms": float(np.mean(ap_d) + np.mean(no_d) + np.mean(x0_d)),
+                "transform_pass1_ms": round(float(np.mean(x0_d)), 4),
+                "apply_kernel_ms": round(float(np.mean(ap_d)), 4)}
         # error of the mixed path against the FP64 path, same instances and
         # bath vectors (the largest over the fields and temperatures)
         errs = [result_errors(a, b) for a, b in zip(res_m, res_d)]

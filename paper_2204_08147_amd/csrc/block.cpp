@@ -66,7 +66,7 @@ rdm_status block_plan(BlockPlan& bp, const rdm_hamiltonian* h, int n_beta, int n
   // geometry of the plain apply segments (no storage of their own)
   size_t dummy = 0;
   plan_seg(bp.apply, h->n, bp.cpad, 1, prec, 1, 0, 1, dummy);
-  plan_seg(bp.bath, h->n_b, n_v, bp.kb, prec, 0, 0, 2, off, needs_ybuf(h, 1));
+  plan_seg(bp.bath, h->n_b, n_v, bp.kb, prec, 0, 0, 2, off, lanczos_needs_ybuf(h, 1, prec));
   bp.bytes = bp.header + off;
   if (budget != 0 && bp.bytes > budget) {
     set_error("block solve needs " + std::to_string(bp.bytes) + " device bytes, budget " +

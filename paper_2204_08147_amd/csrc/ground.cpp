@@ -56,8 +56,8 @@ rdm_status ground_plan(GroundPlan& gp, const rdm_hamiltonian* h, int n_v, int k,
   }
   gp.header = align_up(2 * sizeof(Seg));
   size_t off = 0;
-  plan_seg(gp.tot, h->n, cpad, gp.k, prec, 0, 0, gp.k, off, needs_ybuf(h, 0));
-  plan_seg(gp.bath, h->n_b, n_v, gp.kb, prec, 0, 0, 2, off, needs_ybuf(h, 1));
+  plan_seg(gp.tot, h->n, cpad, gp.k, prec, 0, 0, gp.k, off, lanczos_needs_ybuf(h, 0, prec));
+  plan_seg(gp.bath, h->n_b, n_v, gp.kb, prec, 0, 0, 2, off, lanczos_needs_ybuf(h, 1, prec));
   gp.n_cblocks = cpad / cb;
   const uint64_t r = (dim * gp.n_cblocks) / (kBlock * 4096ull);
   gp.g_rpl = (int)std::max<uint64_t>(1, std::min<uint64_t>(r, 16));

@@ -26,6 +26,20 @@ enum {
 };
 
 enum { MODE_LANCZOS = 0, MODE_REGEN = 1, MODE_PLAIN = 2 };
+
+// Partial-sum planes of the FP64 transform Lanczos step (Seg::xdots): plane p
+// is rows [p * x_tiles, (p + 1) * x_tiles) of part, one row per tile.  The
+// step's <u_j, r_j> = s_j (A + QX + QY) - (beta s)_{j-1} C is assembled from
+//   XP_A:  sum d u^2, the diagonal part (contiguous pass; before it the
+//          plane holds |u~_j|^2 / L for the norm)
+//   XP_QX: <u~_j, W_hi D_X W_hi u~_j> as sum D_X z^2, z = W_hi u~_j (strided
+//          pass of the X part)
+//   XP_C:  <u~_j, u~_{j-1}> / L (strided pass, where u~_j is formed)
+//   XP_QY: <u~_j, (W_lo T W_lo) Y / L> = <Y_in, W_hi D_Y W_hi Y_in> (strided
+//          pass of the YY part)
+// so that the contiguous pass needs neither R nor u~_{j-1} before its
+// transforms (FP32 steps keep the fused form of the contiguous pass).
+enum { XP_A = 0, XP_QX = 1, XP_C = 2, XP_QY = 3, XP_COUNT = 4 };
 enum { START_SYSBATH = 0, START_BATH = 1, START_PRODUCT = 2 };
 
 constexpr int kTileBits = 8;       // the apply stages 2^8 = kBlock-row partner tiles in LDS
@@ -109,7 +123,7 @@ struct Seg {
   int32_t x_tiles;     // transform apply: tiles of 2^kXzTileBits rows
   int32_t x_base;      // transform apply: first workgroup of this segment
   int32_t xy;          // transform apply with a YY part (D_Y, the block Y)
-  int32_t pad_xy;
+  int32_t xdots;       // FP64 transform Lanczos: <u_j, r_j> from the XP_* planes
   const void* dx;      // transform apply: D_X / 2^N in T (tile order above 20 bits)
   const void* dy;      // transform apply: D_Y / 2^N in T, same order (xy segments)
   void* Y;             // xy segments: one block of dim x cpad for the YY part

@@ -168,6 +168,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* 
   }
 }
 
+// Sum the lane values v over the workgroup and store them at plane `plane`
+// (XP_*), row tile rt, columns panel0 * W .. + W - 1, times scale.
+template <int W>
+__device__ __forceinline__ void put_plane(const CONST_AS Seg& sg, int plane, int rt, int panel0, double (&v)[W],
+                                          double* red, double scale = 1.0) {
+  double tot;
+  block_sum<W>(v, red, &tot);
+  if (threadIdx.x < W)
+    sg.part[((uint64_t)plane * sg.x_tiles + rt) * sg.cpad + panel0 * W + threadIdx.x] = tot * scale;
+}
+
 // per-column scalars of the recurrence for panel s of a tile (uniform loads)
 template <typename T, int S>
 __device__ __forceinline__ typename PanelT<T>::V scur_of(const CONST_AS double* st, int cp, int panel0,
@@ -612,15 +623,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
 // of them in registers q.  Three arrangements: 0: tau = q*256 + l (q = bits
 // 8..11); 1: tau = l*16 + q (q = bits 0..3); 2: q = bits 4..7, l = bits 0..3
 // and 8..11.  Butterflies act on register bits; an LDS round trip changes the
-// arrangement.  The LDS slot of tau is tau ^ ((tau >> 4) & 15), which keeps
-// every 16-lane group of a 16-byte access on distinct banks.
+// arrangement.  The LDS slot of tau is tau + (tau >> 4) (one 16-byte pad per
+// 16 slots): in every arrangement it is a per-lane base plus a constant per
+// register (an instruction offset), and the 16 lanes of each group of a
+// 16-byte access fall on distinct banks (slot mod 16 = lane + const).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t xz_tau(int arr, uint32_t l, int q) {
   return arr == 0 ? (uint32_t)q * 256u + l
        : arr == 1 ? (l << 4) | (uint32_t)q
                   : (l & 15u) | ((uint32_t)q << 4) | ((l >> 4) << 8);
 }
-__device__ __forceinline__ uint32_t xz_slot(uint32_t tau) { return tau ^ ((tau >> 4) & 15u); }
+// tau + (tau >> 4) for tau = xz_tau(arr, l, q), as base(l) + const(q)
+__device__ __forceinline__ uint32_t xz_slot(int arr, uint32_t l, int q) {
+  return arr == 0 ? (l + (l >> 4)) + (uint32_t)q * 272u
+       : arr == 1 ? l * 17u + (uint32_t)q
+                  : ((l & 15u) + (l >> 4) * 272u) + (uint32_t)q * 17u;
+}
+constexpr int kXzLdsSlots = (1 << kXzTileBits) + (1 << (kXzTileBits - 4));
 
 // butterflies (a, b) -> (a + b, a - b) over the register bits set in mask
 template <typename V>
@@ -642,10 +661,10 @@ template <typename V>
 __device__ __forceinline__ void xz_rearrange(V (&v)[kXzRegs], V* lds, int from, int to) {
   const uint32_t l = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < kXzRegs; ++q) lds[xz_slot(xz_tau(from, l, q))] = v[q];
+  for (int q = 0; q < kXzRegs; ++q) lds[xz_slot(from, l, q)] = v[q];
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kXzRegs; ++q) v[q] = lds[xz_slot(xz_tau(to, l, q))];
+  for (int q = 0; q < kXzRegs; ++q) v[q] = lds[xz_slot(to, l, q)];
   __syncthreads();
 }
 
@@ -689,9 +708,21 @@ __device__ __forceinline__ void xz_low_transform(V (&v)[kXzRegs], V* lds) {
 // those of 0..3 at or above lrb (arrangement 1).  D_X is stored in row order
 // for shallow operators (read through row_of) and in the strided tiles' own
 // order for deep ones (tile rt's 4096 entries in tau order from rt * 4096).
-template <bool DEEP, typename T, typename V, typename RowOf>
+// QUAD: qf[e] += sum over the tile of D z^2 (z = W_hi v, column e), the
+// lane's share of <v, W_hi D W_hi v>.
+template <typename T, typename V>
+__device__ __forceinline__ V xz_scale_quad(T d, V z, double* qf, bool quad) {
+  constexpr int W = sizeof(V) / sizeof(T);
+  if (quad) {
+#pragma unroll
+    for (int e = 0; e < W; ++e) qf[e] += (double)d * ((double)z[e] * (double)z[e]);
+  }
+  return d * z;
+}
+
+template <bool DEEP, bool QUAD = false, typename T, typename V, typename RowOf>
 __device__ __forceinline__ void xz_high_transform(V (&v)[kXzRegs], V* lds, const T* dx, uint32_t rt, int lrb,
-                                                  RowOf row_of) {
+                                                  RowOf row_of, double* qf = nullptr) {
   constexpr int W = sizeof(V) / sizeof(T);
   const uint32_t l = threadIdx.x;
   xz_bfly(v, 0xF);
@@ -700,7 +731,7 @@ __device__ __forceinline__ void xz_high_transform(V (&v)[kXzRegs], V* lds, const
     const int m2 = 0xF & ~((1 << (lrb - 4)) - 1);
     xz_bfly(v, m2);
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dx, row_of(xz_tau(2, l, q))) * v[q];
+    for (int q = 0; q < kXzRegs; ++q) v[q] = xz_scale_quad(ldg_s(dx, row_of(xz_tau(2, l, q))), v[q], qf, QUAD);
     xz_bfly(v, m2);
   } else {
     const int m1 = 0xF & ~((1 << lrb) - 1);
@@ -713,7 +744,7 @@ __device__ __forceinline__ void xz_high_transform(V (&v)[kXzRegs], V* lds, const
     for (int g = 0; g < kXzRegs / W; ++g) {
       const V dd = ldg(dv, (uint32_t)g);
 #pragma unroll
-      for (int e = 0; e < W; ++e) v[g * W + e] = dd[e] * v[g * W + e];
+      for (int e = 0; e < W; ++e) v[g * W + e] = xz_scale_quad(dd[e], v[g * W + e], qf, QUAD);
     }
     xz_bfly(v, m1);
     xz_rearrange(v, lds, 1, 2);
@@ -738,10 +769,11 @@ __device__ __forceinline__ void yy_twist(V (&v)[kXzRegs], uint32_t row0, T scale
 }
 
 // In-place strided pass buf = W_hi D W_hi buf on the strided tile t of a
-// segment (the row map and cache hints of the strided passes below).
-template <typename T, bool DEEP>
+// segment (the row map and cache hints of the strided passes below); QUAD as
+// in xz_high_transform.
+template <typename T, bool DEEP, bool QUAD = false>
 __device__ __forceinline__ void xz_strided_inplace(const CONST_AS CSeg& sg, const Tile& t, typename PanelT<T>::V* buf,
-                                                   const T* dd, typename PanelT<T>::V* lds) {
+                                                   const T* dd, typename PanelT<T>::V* lds, double* qf = nullptr) {
   using V = typename PanelT<T>::V;
   const uint32_t l = threadIdx.x;
   const int hb = sg.nbits - kXzTileBits;
@@ -756,7 +788,7 @@ __device__ __forceinline__ void xz_strided_inplace(const CONST_AS CSeg& sg, cons
     constexpr bool NT = decltype(nt_tag)::value;
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_sel<NT>((const V*)buf, row_of(xz_tau(0, l, q)));
-    xz_high_transform<DEEP>(v, lds, dd, t.rtile, lrb, row_of);
+    xz_high_transform<DEEP, QUAD>(v, lds, dd, t.rtile, lrb, row_of, qf);
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) stg_sel<NT>(buf, row_of(xz_tau(0, l, q)), v[q]);
   };
@@ -769,8 +801,10 @@ __device__ __forceinline__ void xz_strided_inplace(const CONST_AS CSeg& sg, cons
 // butterflies act on arrangement 0 (tau bits 8..11) and on the bits of 4..7
 // at or above lrb (arrangement 2), as in shallow tiles.  WITH_D: the sandwich
 // W_G D W_G with D read in row order through row_of; otherwise W_G alone.
-template <bool WITH_D, typename T, typename V, typename RowOf>
-__device__ __forceinline__ void xz_group_transform(V (&v)[kXzRegs], V* lds, const T* dd, int lrb, RowOf row_of) {
+// QUAD (with WITH_D) as in xz_high_transform.
+template <bool WITH_D, bool QUAD = false, typename T, typename V, typename RowOf>
+__device__ __forceinline__ void xz_group_transform(V (&v)[kXzRegs], V* lds, const T* dd, int lrb, RowOf row_of,
+                                                   double* qf = nullptr) {
   const uint32_t l = threadIdx.x;
   const int m2 = 0xF & ~((1 << (lrb - 4)) - 1);
   xz_bfly(v, 0xF);
@@ -778,7 +812,7 @@ __device__ __forceinline__ void xz_group_transform(V (&v)[kXzRegs], V* lds, cons
   xz_bfly(v, m2);
   if (WITH_D) {
 #pragma unroll
-    for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_s(dd, row_of(xz_tau(2, l, q))) * v[q];
+    for (int q = 0; q < kXzRegs; ++q) v[q] = xz_scale_quad(ldg_s(dd, row_of(xz_tau(2, l, q))), v[q], qf, QUAD);
     xz_bfly(v, m2);
   }
   xz_rearrange(v, lds, 2, 0);
@@ -810,7 +844,11 @@ struct SplitRows {
 template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_xz_split(const Seg* __restrict__ segs, int nseg) {
   using V = typename PanelT<T>::V;
-  __shared__ V lds[1 << kXzTileBits];
+  constexpr int W = PanelT<T>::W;
+  // FP64 Lanczos steps: the D_X / D_Y sandwiches give the XP_QX / XP_QY planes
+  constexpr bool QUAD = sizeof(T) == 8 && (OP == 1 || OP == 3);
+  __shared__ V lds[kXzLdsSlots];
+  __shared__ double red[4 * W];
   const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   if (xz_geom(sg.nbits) != XG_SPLIT) return;
@@ -825,7 +863,11 @@ __global__ __launch_bounds__(kBlock) void k_xz_split(const Seg* __restrict__ seg
   V v[kXzRegs];
 #pragma unroll
   for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_nt(src, row_of(xz_tau(0, l, q)));
-  xz_group_transform<B>(v, lds, (const T*)(OP == 3 ? sg.dy : sg.dx), row_of.lrb, row_of);
+  double qf[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) qf[e] = 0.0;
+  xz_group_transform<B, QUAD>(v, lds, (const T*)(OP == 3 ? sg.dy : sg.dx), row_of.lrb, row_of, qf);
+  if (QUAD && sg.mode == MODE_LANCZOS) put_plane<W>(sg, OP == 1 ? XP_QX : XP_QY, t.rtile, t.panel0, qf, red);
   if (OP == 4) {
 #pragma unroll
     for (int q = 0; q < kXzRegs; ++q) v[q] = T(1 << kXzTileBits) * v[q];
@@ -848,7 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_xz_split(const Seg* __restrict__ seg
 template <typename T, int PHASE, bool DEEP>
 __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ segs, int nseg) {
   using V = typename PanelT<T>::V;
-  __shared__ V lds[1 << kXzTileBits];
+  __shared__ V lds[kXzLdsSlots];
   const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x, DEEP);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   const uint64_t pstride = (uint64_t)1 << sg.nbits;
@@ -990,8 +1032,16 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
   using V = typename PanelT<T>::V;
   constexpr int W = PanelT<T>::W;
   constexpr bool DEEP = GEOM == XG_DEEP;
-  __shared__ V lds[1 << kXzTileBits];
-  __shared__ double red[4 * W];
+  // FP64 steps split the recurrence differently (the contiguous pass then
+  // reads one vector and writes one, in 210 VGPRs at two waves per SIMD):
+  // ZR: the contiguous pass leaves Z = W_lo D_Z u_j in the block Y and the
+  // next strided pass forms s Z + s L R - (beta s) u~_{j-1} there; XD: the
+  // step's <u_j, r_j> from the XP_* planes.  FP32 steps keep the whole
+  // recurrence and the dot product in the contiguous pass.
+  constexpr bool ZR = sizeof(T) == 8;
+  constexpr bool XD = ZR && !REGEN;
+  __shared__ V lds[kXzLdsSlots];
+  __shared__ double red[4 * 2 * W];
   const Tile t = xz_tile_of(segs, nseg, (int)blockIdx.x + boff, (PASS == 1 || PASS == 4) && DEEP);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
   // pass 1 comes in variants (the regeneration pass needs more registers;
@@ -1047,17 +1097,43 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
       for (int e = 0; e < W; ++e) acur[e] = (T)st[ST_ACUR * cp + t.panel0 * W + e];
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q) v[q] = ldg_sel<NT>((const V*)rb, row_of(xz_tau(0, l, q)));
+      // dsum: |u~_j|^2; XD: dsum[W + e] = <u~_j, u~_{j-1}>
+      double dsum[XD ? 2 * W : W];
+#pragma unroll
+      for (int e = 0; e < (XD ? 2 * W : W); ++e) dsum[e] = 0.0;
+      if (ZR && uprev) {
+        // W_lo r_{j-1} = s L R + s Z - (beta s) u~_{j-2}, with the scalars of
+        // step j-1 (still in st), in the FP32 path's rounding order
+        const V sc = scur_of<T, 1>(st, cp, t.panel0, 0, false);
+        const V scl = sc * T(1 << kXzTileBits);
+        const V bp = bps_of<T, 1>(st, cp, t.panel0, 0);
+        const V* zb = (const V*)sg.Y + (uint64_t)t.panel0 * pstride;
+        const V* upp = j > 2 ? (const V*)slot_ptr<T>(sg, j - 2) + (uint64_t)t.panel0 * pstride : nullptr;
+#pragma unroll
+        for (int q = 0; q < kXzRegs; ++q) {
+          const uint32_t row = row_of(xz_tau(0, l, q));
+          V w = scl * v[q];
+          if (upp) {
+            const V u2 = ldg_sel<NT>(upp, row);
+#pragma unroll
+            for (int e = 0; e < W; ++e) w[e] = fma_s(-bp[e], u2[e], w[e]);
+          }
+          const V z = ldg_sel<NT>(zb, row);
+#pragma unroll
+          for (int e = 0; e < W; ++e) v[q][e] = fma_s(sc[e], z[e], w[e]);
+        }
+      }
       if (uprev) {
 #pragma unroll
         for (int q = 0; q < kXzRegs; ++q) {
           const V up = ldg_sel<NT>(uprev, row_of(xz_tau(0, l, q)));
 #pragma unroll
-          for (int e = 0; e < W; ++e) v[q][e] = fma_s(-acur[e], up[e], v[q][e]);
+          for (int e = 0; e < W; ++e) {
+            v[q][e] = fma_s(-acur[e], up[e], v[q][e]);
+            if (XD) dsum[W + e] += (double)v[q][e] * (double)up[e];
+          }
         }
       }
-      double dsum[W];
-#pragma unroll
-      for (int e = 0; e < W; ++e) dsum[e] = 0.0;
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q) {
         stg(ucur, row_of(xz_tau(0, l, q)), v[q]);
@@ -1089,11 +1165,22 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
         }
       }
       double tot;
-      block_sum<W>(dsum, red, &tot);
-      if (threadIdx.x < W)
+      block_sum<XD ? 2 * W : W>(dsum, red, &tot);
+      if (threadIdx.x < W) {
         sg.part[(uint64_t)t.rtile * cp + t.panel0 * W + threadIdx.x] = tot * (double)inv_l;
-      if constexpr (GEOM == XG_SPLIT) xz_group_transform<false>(v, lds, (const T*)nullptr, lrb, row_of);
-      else xz_high_transform<DEEP>(v, lds, (const T*)sg.dx, t.rtile, lrb, row_of);
+      } else if (XD && threadIdx.x < 2 * W) {
+        sg.part[((uint64_t)XP_C * sg.x_tiles + t.rtile) * cp + t.panel0 * W + threadIdx.x - W] =
+            tot * (double)inv_l;
+      }
+      if constexpr (GEOM == XG_SPLIT) {
+        xz_group_transform<false>(v, lds, (const T*)nullptr, lrb, row_of);
+      } else {
+        double qf[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) qf[e] = 0.0;
+        xz_high_transform<DEEP, XD>(v, lds, (const T*)sg.dx, t.rtile, lrb, row_of, qf);
+        if (XD) put_plane<W>(sg, XP_QX, t.rtile, t.panel0, qf, red);
+      }
 #pragma unroll
       for (int q = 0; q < kXzRegs; ++q) stg_sel<NT>(rb, row_of(xz_tau(0, l, q)), v[q]);
     };
@@ -1116,8 +1203,13 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
     return;
   }
   if (PASS == 4) {
-    // strided tile: Y = W_hi D_Y W_hi Y
-    xz_strided_inplace<T, DEEP>(sg, t, (V*)sg.Y + (uint64_t)t.panel0 * pstride, (const T*)sg.dy, lds);
+    // strided tile: Y = W_hi D_Y W_hi Y (FP64: and the XP_QY plane)
+    constexpr bool QY = sizeof(T) == 8;
+    double qf[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) qf[e] = 0.0;
+    xz_strided_inplace<T, DEEP, QY>(sg, t, (V*)sg.Y + (uint64_t)t.panel0 * pstride, (const T*)sg.dy, lds, qf);
+    if (QY && sg.mode == MODE_LANCZOS) put_plane<W>(sg, XP_QY, t.rtile, t.panel0, qf, red);
     return;
   }
   if (PASS == 5) {
@@ -1140,6 +1232,34 @@ __global__ __launch_bounds__(kBlock) void k_xz_lanczos(const Seg* __restrict__ s
   // PASS 2: contiguous tile, row = row0 + tau
   const V* ub = (const V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel0 * pstride;
   const T* dg = (const T*)sg.diag;
+  if constexpr (ZR) {
+    // FP64: Z = W_lo D_Z u_j into Y (the next strided pass completes the
+    // recurrence) and the diagonal part of <u_j, r_j> (plane XP_A)
+    T d[kXzRegs];
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const uint32_t row = t.row0 + xz_tau(0, l, q);
+      v[q] = ldg_nt(ub, row);
+      d[q] = ldg_s(dg, row);
+    }
+    double d2[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) d2[e] = 0.0;
+    xz_low_transform(v, lds);      // L u
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) {
+      const V u = v[q] * inv_l;
+      v[q] = d[q] * u;             // D_Z u
+#pragma unroll
+      for (int e = 0; e < W; ++e) d2[e] += (double)u[e] * (double)v[q][e];
+    }
+    xz_low_transform(v, lds);      // W_lo D_Z u
+    V* zb = (V*)sg.Y + (uint64_t)t.panel0 * pstride;
+#pragma unroll
+    for (int q = 0; q < kXzRegs; ++q) stg_stream<true>(zb, t.row0 + xz_tau(0, l, q), v[q]);
+    if (XD && sg.mode == MODE_LANCZOS) put_plane<W>(sg, XP_A, t.rtile, t.panel0, d2, red);
+    return;
+  }
   V w[kXzRegs];
   T d[kXzRegs];
 #pragma unroll
@@ -1571,13 +1691,37 @@ __global__ __launch_bounds__(kBlock) void k_red_beta(const Seg* __restrict__ seg
   st[ST_SCUR * cp + c] = s;
 }
 
+// <u_j, r_j> of an FP64 transform step from its partial-sum planes (XP_*):
+// per tile s_j (A + QX [+ QY]) - (beta s)_{j-1} C, then the fixed tree.
+__device__ __forceinline__ double xdots_total(const Seg& sg, int c, double* lds) {
+  const int cp = sg.cpad;
+  const double sc = sg.st[ST_SCUR * cp + c], bp = sg.st[ST_BPS * cp + c];
+  const uint64_t ps = (uint64_t)sg.x_tiles * cp;
+  double s = 0.0;
+  for (int t = threadIdx.x; t < sg.x_tiles; t += kBlock) {
+    const double* p = sg.part + (uint64_t)t * cp + c;
+    double q = p[XP_A * ps] + p[XP_QX * ps];
+    if (sg.xy) q += p[XP_QY * ps];
+    s += sc * q - bp * p[XP_C * ps];
+  }
+  lds[threadIdx.x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  return lds[0];
+}
+
 // alpha_j = s_j <u_j, r>; weight alpha_j s_j for the next step; advance.
 __global__ __launch_bounds__(kBlock) void k_red_alpha(const Seg* __restrict__ segs) {
   const Seg& sg = segs[blockIdx.x];
   const int c = blockIdx.y;
   if (c >= sg.cpad) return;
   __shared__ double lds[kBlock];
-  const double tot = column_total(sg, sg.ap_rows, c, lds);
+  const double tot = sg.xdots && sg.mode == MODE_LANCZOS ? xdots_total(sg, c, lds)
+                                                         : column_total(sg, sg.ap_rows, c, lds);
   if (threadIdx.x != 0) return;
   const int j = sg.stepc[c];
   if (j > sg.k) return;

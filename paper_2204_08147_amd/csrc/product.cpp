@@ -39,8 +39,8 @@ rdm_status product_plan(ProductPlan& pp, const rdm_hamiltonian* h, int n_v, int 
   pp.header = align_up(2 * sizeof(Seg));
   size_t off = 0;
   // only the coefficients are needed: two basis slots per segment
-  plan_seg(pp.tot, h->n, n_v, pp.k, prec, 0, 0, 2, off, needs_ybuf(h, 0));
-  plan_seg(pp.bath, h->n_b, n_v, pp.kb, prec, 0, 0, 2, off, needs_ybuf(h, 1));
+  plan_seg(pp.tot, h->n, n_v, pp.k, prec, 0, 0, 2, off, lanczos_needs_ybuf(h, 0, prec));
+  plan_seg(pp.bath, h->n_b, n_v, pp.kb, prec, 0, 0, 2, off, lanczos_needs_ybuf(h, 1, prec));
   pp.bytes = pp.header + off;
   if (budget != 0 && pp.bytes > budget) {
     set_error("product-state estimate needs " + std::to_string(pp.bytes) + " device bytes, budget " +

@@ -102,12 +102,16 @@ void parallel_for(int n, const std::function<void(int)>& fn) {
 // planning
 // ---------------------------------------------------------------------------
 bool needs_ybuf(const rdm_hamiltonian* h, int which) { return h->op[which].xz && h->op[which].xy; }
+bool lanczos_needs_ybuf(const rdm_hamiltonian* h, int which, int prec) {
+  return h->op[which].xz && (h->op[which].xy || prec == RDM_FP64);
+}
 
 void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
               size_t& off, bool ybuf) {
   const int W = panel_width(prec);
   const size_t sb = scalar_bytes(prec);
   g.nbits = nbits;
+  g.prec = prec;
   g.dim = 1ull << nbits;
   g.C = C;
   g.P = (C + W - 1) / W;
@@ -173,8 +177,9 @@ rdm_status plan_instance(InstPlan& p, const rdm_hamiltonian* h, int n_beta, int 
   }
   auto layout = [&](bool two_pass) {
     size_t off = 0;
-    plan_seg(p.tot, h->n, p.ds * n_v, p.k, prec, slab_opt, rpl_opt, two_pass ? 2 : p.k, off, needs_ybuf(h, 0));
-    plan_seg(p.bath, h->n_b, n_v, p.kb, prec, slab_opt, rpl_opt, 2, off, needs_ybuf(h, 1));
+    plan_seg(p.tot, h->n, p.ds * n_v, p.k, prec, slab_opt, rpl_opt, two_pass ? 2 : p.k, off,
+             lanczos_needs_ybuf(h, 0, prec));
+    plan_seg(p.bath, h->n_b, n_v, p.kb, prec, slab_opt, rpl_opt, 2, off, lanczos_needs_ybuf(h, 1, prec));
     p.o_psi = off;
     if (two_pass) off = al(off + (size_t)n_beta * p.tot.blk * sb);
     p.o_y = off; off = al(off + (size_t)n_beta * p.k * p.tot.cpad * sb);
@@ -218,6 +223,10 @@ Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int sta
   s.nbits = g.nbits;
   s.n_row_tiles = g.n_row_tiles;
   bind_apply(s, op);
+  // FP64 transform steps assemble <u_j, r_j> from XP_COUNT planes of x_tiles
+  // rows each (n_row_tiles = dim / 256 rows leave room for them)
+  static_assert(XP_COUNT * kBlock <= (1 << kXzTileBits), "partial-sum planes exceed the part buffer");
+  s.xdots = op->xz && g.prec == RDM_FP64 ? 1 : 0;
   s.P = g.P;
   s.S = g.S;
   s.rpl = g.rpl;
@@ -699,8 +708,8 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
                      StepTimers* tm, bool tune, bool graph) {
   if (hsegs.empty()) return RDM_OK;
   for (const auto& sg : hsegs)
-    if (sg.xy && !sg.Y) {
-      set_error("internal: a segment with a YY transform part has no Y block");
+    if ((sg.xy || (sg.xz && prec == RDM_FP64)) && !sg.Y) {
+      set_error("internal: a transform segment that needs the Y block has none");
       return RDM_E_INVALID;
     }
   int kmax = 0, cmax = 0;
@@ -938,7 +947,7 @@ rdm_status lanczos_only(const rdm_hamiltonian* h, int which, int n_v, int k, uin
   const int kk = (int)std::min<uint64_t>((uint64_t)k, 1ull << nbits);
   const size_t base_off = al(sizeof(Seg));
   size_t off = base_off;
-  plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, off, needs_ybuf(h, which));
+  plan_seg(g, nbits, C, kk, prec, slab, rpl, 2, off, lanczos_needs_ybuf(h, which, prec));
   char* ws = nullptr;
   RDM_HIP(hipMalloc(&ws, off));
   const OpDevice* op = nullptr;

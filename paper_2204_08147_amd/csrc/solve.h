@@ -15,12 +15,18 @@ struct SegPlan {
   int nbits = 0, C = 0, cpad = 0, P = 0, S = 1, rpl = 1, n_row_tiles = 0, k = 0, nslots = 0;
   uint64_t dim = 0, blk = 0;
   size_t o_Q = 0, o_R = 0, o_st = 0, o_ha = 0, o_hb = 0, o_hs = 0, o_part = 0, o_step = 0, o_kc = 0;
+  int prec = 0;       // RDM_FP64 / RDM_MIXED
   bool ybuf = false;  // one more block (the YY part of a transform operator) at o_Y
   size_t o_Y = 0;
 };
 // Whether operator `which` of h (0: H_t, 1: H_b) is applied by the transform
 // with a YY part, which needs the scratch block Y.
 bool needs_ybuf(const rdm_hamiltonian* h, int which);
+// Whether a Lanczos segment of operator `which` in precision prec needs the
+// block Y: the YY part, and every FP64 transform step (Z = W_lo D_Z u_j
+// between the contiguous pass and the next strided pass; the YY part uses Y
+// only between those two, so one block serves both).
+bool lanczos_needs_ybuf(const rdm_hamiltonian* h, int which, int prec);
 
 struct InstPlan {
   const rdm_hamiltonian* h = nullptr;
