@@ -374,7 +374,8 @@ def bench_large(args):
             "higher_is_better": False, "dtype": "f32 vectors + f64 reductions",
             "config": {"workload": "long-range XXZ 3+23 spins (dim 2^26), alpha=1.2, Delta=0.8, "
                                    "x-field 1.0, beta=2, n_v=4 (32 columns), k=80, two-pass"},
-            "apply_kernel_ms": round(res["t_apply_ms"], 3), "norm_kernel_ms": round(res["t_norm_ms"], 3),
+            "step_kernels_ms": round(t_step * 1e3, 3), "apply_kernel_ms": round(res["t_apply_ms"], 3),
+            "norm_kernel_ms": round(res["t_norm_ms"], 3),
             "roofline_step": roofline(*plan_work([inst], 4), t_step),
             "roofline_step_implementation": roofline(by, fl, t_step), "two_pass": res["two_pass"],
             "device_bytes": res["device_bytes"],
@@ -391,11 +392,16 @@ def bench_serve(args):
     queue, and so the latency, grows with the run's length), and Poisson
     arrivals at 0.7x the measured capacity (steady state)."""
     import threading
+    import torch
     import paper_2204_08147_amd as rdm
     from workloads import poisson_arrivals, tfim_request
-    srv = rdm.Server(hbm_budget=int(200e9), max_active=64, precision="mixed")
+    # the engine's arena: the device's free memory less 16 GiB for the
+    # Hamiltonians' own tables (at most max_active requests' worth resident)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free - (16 << 30))
+    srv = rdm.Server(hbm_budget=budget, max_active=64, precision="mixed")
     next_req = [0]
-    keep = []  # Hamiltonians stay alive (and their device tables resident) until the end
+    keep = []  # Hamiltonians of requests not yet finished (released as they finish)
 
     def new_request():
         inst = tfim_request(next_req[0])
@@ -405,7 +411,7 @@ def bench_serve(args):
     def open_loop(n, rate):
         """n Poisson arrivals at rate/s; returns (solves/s, latencies in s)."""
         arr = poisson_arrivals(n, rate, seed=int(rate * 1000) + n)
-        done, pending = {}, {}
+        done, pending, hams = {}, {}, {}
         lock = threading.Lock()
         stop = [False]
 
@@ -419,6 +425,7 @@ def bench_serve(args):
                         done[i] = (time.perf_counter(), r["status"])
                         with lock:
                             del pending[t]
+                        hams.pop(i).close()
                 time.sleep(0.0005)
 
         th = threading.Thread(target=poller)
@@ -433,7 +440,7 @@ def bench_serve(args):
                 print(f"[serve] rate {rate:.1f}/s: submitted {i} of {n}, {len(done)} done", file=sys.stderr,
                       flush=True)
             inst, h = new_request()
-            keep.append(h)
+            hams[i] = h
             sub[i] = time.perf_counter()
             t = srv.submit(h, inst.betas, inst.n_v, inst.k, inst.seed)
             with lock:
@@ -457,11 +464,14 @@ def bench_serve(args):
         # closed loop: everything submitted at once -> saturated capacity
         batch = [new_request() for _ in range(200)]
         t0 = time.perf_counter()
+        keep.extend(h for _, h in batch)
         tk = [srv.submit(h, i.betas, i.n_v, i.k, i.seed) for i, h in batch]
         for t in tk:
             assert srv.wait(t)["status"] == 0
         capacity = 200 / (time.perf_counter() - t0)
-        keep.extend(h for _, h in batch)
+        for h in keep:
+            h.close()
+        keep.clear()
         print(f"[serve] closed-loop capacity {capacity:.2f} solves/s", file=sys.stderr, flush=True)
         rate_a, lat_a = open_loop(args.requests, args.rate)
         steady = 0.7 * capacity
@@ -492,7 +502,7 @@ def bench_serve(args):
             "steady": {"offered_rate": round(steady, 3), "requests": args.steady_requests,
                        "solves_per_s": round(rate_b, 3), "p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99)},
             "peak_active": stats["peak_active"], "engine_steps": stats["steps"],
-            "peak_device_bytes": stats["peak_bytes"]}
+            "peak_device_bytes": stats["peak_bytes"], "arena_bytes": budget}
 
 
 def bench_scan(args):
