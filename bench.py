@@ -476,6 +476,9 @@ def bench_serve(args):
         rate_a, lat_a = open_loop(args.requests, args.rate)
         steady = 0.7 * capacity
         rate_b, lat_b = open_loop(args.steady_requests, steady)
+        # the same number of arrivals at a fixed 12.6/s (0.7 x the capacity of
+        # an earlier engine), for comparisons at equal offered load
+        rate_c, lat_c = open_loop(args.steady_requests, 12.6)
         stats = srv.stats()
     finally:
         srv.close()
@@ -501,6 +504,8 @@ def bench_serve(args):
             "p50_ms": pct(lat_a, 50), "p99_ms": pct(lat_a, 99), "offered_rate": args.rate,
             "steady": {"offered_rate": round(steady, 3), "requests": args.steady_requests,
                        "solves_per_s": round(rate_b, 3), "p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99)},
+            "fixed_12_6": {"offered_rate": 12.6, "requests": args.steady_requests, "solves_per_s": round(rate_c, 3),
+                           "p50_ms": pct(lat_c, 50), "p99_ms": pct(lat_c, 99)},
             "peak_active": stats["peak_active"], "engine_steps": stats["steps"],
             "peak_device_bytes": stats["peak_bytes"], "arena_bytes": budget}
 
@@ -594,6 +599,19 @@ def bench_small(args):
     wall = time.perf_counter() - t0
     ex = exact.exact_rdm(inst, float(inst.betas[0]))
     err = float(np.linalg.norm(r["rho"][0] - ex["rho"]) / np.linalg.norm(ex["rho"]))
+    # the same solves as one batched call per step (50 bath-vector seeds):
+    # every kernel of a step launches once for all of them
+    items = [dict(h=h, betas=inst.betas, n_v=inst.n_v, k=inst.k, seed=inst.seed + s_) for s_ in range(50)]
+    rdm.solve_batch(items, precision="fp64")
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(args.steps):
+        outs = rdm.solve_batch(items, precision="fp64")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - tb
+    assert all(o["status"] == 0 for o in outs)
+    batched = {"solves_per_s": round(50 * args.steps / tb, 3), "ms_per_call": round(1e3 * tb / args.steps, 3),
+               "solves_per_call": 50}
     cpu = None
     if not args.no_cpu_baseline:
         stage("oracle on the host (whole O3 solves and the dense answer)")
@@ -608,7 +626,7 @@ def bench_small(args):
                                    "z-field h=0.5, beta=1, n_v=4, k=30, FP64; 50 solves per step"},
             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
-            "rho_rel_err_vs_exact": err,
+            "rho_rel_err_vs_exact": err, "batched": batched,
             "note": "the estimate's error against the exact partial trace is the stochastic error of "
                     "n_v = 4 bath vectors, not a parity figure"}
 

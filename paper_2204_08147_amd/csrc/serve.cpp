@@ -88,6 +88,7 @@ struct Req {
   int phase = 0;       // 0: pass 1 (H_t and H_b), 1: regeneration pass
   int steps = 0;       // steps launched in the current phase
   bool need_init = true;
+  bool light = false;  // takes 1 + kExtra steps per engine step (see run())
   hipEvent_t last = nullptr;  // recorded after the request's last launched step
 };
 
@@ -101,6 +102,7 @@ struct Req {
 struct rdm_server {
   static constexpr int kAhead = 4;        // steps in flight at most
   static constexpr int kFinishers = 2;
+  static constexpr int kExtra = 3;        // extra steps per engine step of a light request
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_fin;
   std::deque<Req*> queue;        // submitted, not admitted
@@ -122,11 +124,12 @@ struct rdm_server {
   hipStream_t stream = nullptr;
   Arena arena;                   // guarded by mu
   char* arena_mem = nullptr;
-  // two segment tables, each with the event after the last step that read it
-  Seg* dsegs[2] = {nullptr, nullptr};
-  size_t segs_cap[2] = {0, 0};
-  std::vector<Seg> hsegs[2];
-  hipEvent_t seg_done[2] = {nullptr, nullptr};
+  // segment tables, each with the event after the last step that read it:
+  // 0 and 1 alternate for all resident requests, 2 and 3 for the light ones
+  Seg* dsegs[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t segs_cap[4] = {0, 0, 0, 0};
+  std::vector<Seg> hsegs[4];
+  hipEvent_t seg_done[4] = {nullptr, nullptr, nullptr, nullptr};
   std::deque<hipEvent_t> ahead, spare;  // events after the steps in flight
   int64_t n_submitted = 0, n_completed = 0, n_steps = 0, peak_active = 0, peak_bytes = 0, used = 0;
   int64_t n_active = 0;  // active.size() as last published by the worker (under mu)
@@ -221,11 +224,11 @@ void rdm_server::finish_loop() {
 
 void rdm_server::run() {
   (void)hipSetDevice(device);
-  std::vector<Seg> segs;
-  int cur = 0;
+  std::vector<Seg> segs, lsegs;
+  int cur = 0, lcur = 2;
   bool changed = true;
-  Launch ntiles;
-  int slab = 1, cmax = 0;
+  Launch ntiles, ltiles;
+  int slab = 1, cmax = 0, lslab = 1, lcmax = 0;
   while (true) {
     std::vector<Req*> admitted;
     {
@@ -308,14 +311,17 @@ void rdm_server::run() {
       // requests that start a phase
       segs.clear();
       std::vector<std::pair<int, int>> init_ranges;  // (first seg, phase)
+      auto add_segs = [&](std::vector<Seg>& v, Req* r) {
+        if (r->phase == 0) {
+          v.push_back(seg_of(r->run, 0, MODE_LANCZOS, tau));
+          v.push_back(seg_of(r->run, 1, MODE_LANCZOS, tau));
+        } else {
+          v.push_back(seg_of(r->run, 0, MODE_REGEN, tau));
+        }
+      };
       for (Req* r : active) {
         const int first = (int)segs.size();
-        if (r->phase == 0) {
-          segs.push_back(seg_of(r->run, 0, MODE_LANCZOS, tau));
-          segs.push_back(seg_of(r->run, 1, MODE_LANCZOS, tau));
-        } else {
-          segs.push_back(seg_of(r->run, 0, MODE_REGEN, tau));
-        }
+        add_segs(segs, r);
         if (r->need_init) {
           for (int q = first; q < (int)segs.size(); ++q) init_ranges.push_back({q, r->phase});
           r->need_init = false;
@@ -333,10 +339,53 @@ void rdm_server::run() {
           s = init_run(prec, dsegs[cur] + ir.first, 1, cmax, ir.second, sg.xz ? sg.x_tiles * sg.P : 0,
                        sg.x_base, stream);
       }
+      // Light requests take 1 + kExtra steps per engine step, so that a
+      // small request is not held to the pace of the largest resident one
+      // (every request otherwise advances one step per engine step): the
+      // cheapest requests by rows x columns, as long as their extra steps add
+      // at most a quarter of the engine step's work.  The extra launches run
+      // on a table of their segments only; a segment past its last step is
+      // left alone by every kernel, so a request may overrun its k there.
+      std::vector<std::pair<double, Req*>> cost;
+      double total = 0.0;
+      for (Req* r : active) {
+        double c = 0.0;
+        for (int w = 0; w < (r->phase == 0 ? 2 : 1); ++w) {
+          const SegPlan& g = w == 0 ? r->plan.tot : r->plan.bath;
+          c += (double)g.dim * g.cpad * (r->phase == 0 ? 1.0 : 1.0 + r->run.betas.size());
+        }
+        total += c;
+        cost.push_back({c, r});
+        r->light = false;
+      }
+      std::sort(cost.begin(), cost.end(),
+                [](const std::pair<double, Req*>& a, const std::pair<double, Req*>& b) { return a.first < b.first; });
+      double extra = 0.0;
+      for (auto& cr : cost) {
+        if (extra + kExtra * cr.first > 0.25 * total) break;
+        cr.second->light = true;
+        extra += kExtra * cr.first;
+      }
+      lsegs.clear();
+      for (Req* r : active)
+        if (r->light) add_segs(lsegs, r);
+      if (s == RDM_OK && !lsegs.empty()) {
+        lslab = tuned_slab(prec, lsegs);
+        ltiles = assign_tiles(lsegs);
+        lcmax = 0;
+        for (const auto& sg : lsegs) lcmax = std::max(lcmax, sg.cpad);
+        lcur ^= 1;
+        s = upload_table(lcur, lsegs);
+      }
       changed = false;
     }
     if (s == RDM_OK) s = launch_step(prec, dsegs[cur], (int)segs.size(), ntiles, slab, cmax, stream, nullptr);
     if (s == RDM_OK && hipEventRecord(seg_done[cur], stream) != hipSuccess) s = RDM_E_DEVICE;
+    if (!lsegs.empty()) {
+      for (int e = 0; e < kExtra && s == RDM_OK; ++e)
+        s = launch_step(prec, dsegs[lcur], (int)lsegs.size(), ltiles, lslab, lcmax, stream, nullptr);
+      if (s == RDM_OK && hipEventRecord(seg_done[lcur], stream) != hipSuccess) s = RDM_E_DEVICE;
+    }
     // bound how far the launches run ahead of the device
     if (s == RDM_OK) {
       hipEvent_t e = nullptr;
@@ -366,7 +415,7 @@ void rdm_server::run() {
     // requests whose recurrences are complete leave for a finisher
     for (size_t i = 0; i < active.size();) {
       Req* r = active[i];
-      ++r->steps;
+      r->steps += r->light ? 1 + kExtra : 1;
       const int need = r->phase == 0 ? std::max(r->plan.k, r->plan.kb) : r->plan.k;
       if (r->steps < need) {
         ++i;
@@ -419,9 +468,9 @@ extern "C" rdm_status rdm_server_create(uint64_t hbm_budget, int32_t max_active,
     return RDM_E_NOMEM;
   }
   s->arena.init(s->arena_mem, hbm_budget);
-  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&s->seg_done[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&s->seg_done[1], hipEventDisableTiming) != hipSuccess) {
+  bool ev_ok = true;
+  for (auto& e : s->seg_done) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess || !ev_ok) {
     for (auto e : s->seg_done)
       if (e) (void)hipEventDestroy(e);
     if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -584,7 +633,7 @@ extern "C" void rdm_server_destroy(rdm_server* s) {
   }
   for (auto e : s->ahead) (void)hipEventDestroy(e);
   for (auto e : s->spare) (void)hipEventDestroy(e);
-  for (int b = 0; b < 2; ++b) {
+  for (int b = 0; b < 4; ++b) {
     if (s->dsegs[b]) (void)hipFree(s->dsegs[b]);
     if (s->seg_done[b]) (void)hipEventDestroy(s->seg_done[b]);
   }
