@@ -409,9 +409,10 @@ def bench_serve(args):
         return inst, rdm.Hamiltonian.from_instance(inst)
 
     def open_loop(n, rate):
-        """n Poisson arrivals at rate/s; returns (solves/s, latencies in s)."""
+        """n Poisson arrivals at rate/s; returns (solves/s, latencies in s,
+        spin counts of the requests)."""
         arr = poisson_arrivals(n, rate, seed=int(rate * 1000) + n)
-        done, pending, hams = {}, {}, {}
+        done, pending, hams, sizes = {}, {}, {}, {}
         lock = threading.Lock()
         stop = [False]
 
@@ -440,6 +441,7 @@ def bench_serve(args):
                 print(f"[serve] rate {rate:.1f}/s: submitted {i} of {n}, {len(done)} done", file=sys.stderr,
                       flush=True)
             inst, h = new_request()
+            sizes[i] = inst.n
             hams[i] = h
             sub[i] = time.perf_counter()
             t = srv.submit(h, inst.betas, inst.n_v, inst.k, inst.seed)
@@ -458,7 +460,8 @@ def bench_serve(args):
         th.join()
         total = time.perf_counter() - start
         assert all(done[i][1] == 0 for i in range(n))
-        return n / total, np.array([done[i][0] - sub[i] for i in range(n)])
+        return (n / total, np.array([done[i][0] - sub[i] for i in range(n)]),
+                np.array([sizes[i] for i in range(n)]))
 
     try:
         # closed loop: everything submitted at once -> saturated capacity
@@ -473,12 +476,12 @@ def bench_serve(args):
             h.close()
         keep.clear()
         print(f"[serve] closed-loop capacity {capacity:.2f} solves/s", file=sys.stderr, flush=True)
-        rate_a, lat_a = open_loop(args.requests, args.rate)
+        rate_a, lat_a, _ = open_loop(args.requests, args.rate)
         steady = 0.7 * capacity
-        rate_b, lat_b = open_loop(args.steady_requests, steady)
+        rate_b, lat_b, n_b = open_loop(args.steady_requests, steady)
         # the same number of arrivals at a fixed 12.6/s (0.7 x the capacity of
         # an earlier engine), for comparisons at equal offered load
-        rate_c, lat_c = open_loop(args.steady_requests, 12.6)
+        rate_c, lat_c, _ = open_loop(args.steady_requests, 12.6)
         stats = srv.stats()
     finally:
         srv.close()
@@ -504,6 +507,10 @@ def bench_serve(args):
             "p50_ms": pct(lat_a, 50), "p99_ms": pct(lat_a, 99), "offered_rate": args.rate,
             "steady": {"offered_rate": round(steady, 3), "requests": args.steady_requests,
                        "solves_per_s": round(rate_b, 3), "p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99)},
+            "steady_by_spins": {f"{lo}-{hi}": {"requests": int(((n_b >= lo) & (n_b <= hi)).sum()),
+                                               "p50_ms": pct(lat_b[(n_b >= lo) & (n_b <= hi)], 50),
+                                               "p99_ms": pct(lat_b[(n_b >= lo) & (n_b <= hi)], 99)}
+                                for lo, hi in ((14, 20), (21, 22), (23, 24))},
             "fixed_12_6": {"offered_rate": 12.6, "requests": args.steady_requests, "solves_per_s": round(rate_c, 3),
                            "p50_ms": pct(lat_c, 50), "p99_ms": pct(lat_c, 99)},
             "peak_active": stats["peak_active"], "engine_steps": stats["steps"],
