@@ -14,6 +14,7 @@
 // reductions run over its own tiles in a fixed order, so its result does not
 // depend on what else is resident.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -103,6 +104,8 @@ struct rdm_server {
   static constexpr int kAhead = 4;        // steps in flight at most
   static constexpr int kFinishers = 2;
   static constexpr int kExtra = 3;        // extra steps per engine step of a light request
+  static constexpr int kScan = 64;        // queued requests looked at per admission
+  static constexpr double kBypassSec = 0.5;  // longest a blocked head of the queue is passed
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_fin;
   std::deque<Req*> queue;        // submitted, not admitted
@@ -133,6 +136,8 @@ struct rdm_server {
   std::deque<hipEvent_t> ahead, spare;  // events after the steps in flight
   int64_t n_submitted = 0, n_completed = 0, n_steps = 0, peak_active = 0, peak_bytes = 0, used = 0;
   int64_t n_active = 0;  // active.size() as last published by the worker (under mu)
+  uint64_t blocked_ticket = 0;  // head of the queue that did not fit, and since when (worker, under mu)
+  std::chrono::steady_clock::time_point blocked_since{};
 
   void run();
   bool cancelled(const Req* r) {
@@ -246,22 +251,38 @@ void rdm_server::run() {
         admitted.push_back(regen_ready.front());
         regen_ready.pop_front();
       }
-      while (!queue.empty() && (int)active.size() + (int)admitted.size() < max_active) {
-        Req* r = queue.front();
+      // In arrival order; a request that does not fit yet may be passed by
+      // later ones that do (among the first kScan queued) for at most
+      // kBypassSec after it first failed to fit at the head of the queue;
+      // after that the queue waits until enough memory drains for it.
+      const auto now = std::chrono::steady_clock::now();
+      int scanned = 0;
+      for (auto it = queue.begin(); it != queue.end() && scanned < kScan &&
+                                    (int)active.size() + (int)admitted.size() < max_active;) {
+        Req* r = *it;
+        ++scanned;
         char* m = arena.alloc(r->plan.bytes);
         if (!m) {
           if (used == 0) {
             // cannot fit even in an empty arena: fail it rather than block the queue
-            queue.pop_front();
+            it = queue.erase(it);
             r->status = RDM_E_NOMEM;
             r->done = true;
             ++n_completed;
             cv_done.notify_all();
             continue;
           }
-          break;
+          if (it == queue.begin()) {
+            if (blocked_ticket != r->ticket) {
+              blocked_ticket = r->ticket;
+              blocked_since = now;
+            }
+            if (std::chrono::duration<double>(now - blocked_since).count() > kBypassSec) break;
+          }
+          ++it;
+          continue;
         }
-        queue.pop_front();
+        it = queue.erase(it);
         r->mem = m;
         used += (int64_t)r->plan.bytes;
         peak_bytes = std::max(peak_bytes, used);

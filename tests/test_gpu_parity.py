@@ -767,6 +767,54 @@ def test_serving_alone_equals_in_mix():
             assert np.array_equal(a[key], b[key]), key
 
 
+def test_serving_admission_passes_a_blocked_request():
+    """A queued request that does not fit next to the resident ones is passed
+    by a later one that fits (the small request finishes before the one
+    admitted ahead of both), and every result equals its solo run."""
+    import dataclasses
+    import time
+
+    def with_ns(n, n_s, k):
+        for r in range(200):
+            i = tfim_request(r, n_range=(n, n))
+            if i.n_s == n_s:
+                return dataclasses.replace(i, k=k)
+        raise AssertionError("no such request")
+
+    filler, big, small = with_ns(16, 2, 60), with_ns(21, 1, 60), with_ns(14, 1, 10)
+    hs = [H(i) for i in (filler, big, small)]
+    fp = lambda h, i, mode: rdm.workspace_size(h, 1, i.n_v, i.k, precision="mixed", mode=mode,  # noqa: E731
+                                               hbm_budget=1 << 40)
+    f_st, b_st, b_tp = fp(hs[0], filler, "stored"), fp(hs[1], big, "stored"), fp(hs[1], big, "two_pass")
+    s_st = fp(hs[2], small, "stored")
+    margin = 16 << 20
+    budget = 2 * f_st + margin
+    # the filler keeps its basis (at most half the arena), the big request
+    # runs two-pass and cannot sit next to the filler, the small one can
+    assert b_st > budget // 2 and f_st + margin < b_tp <= budget - margin and f_st + s_st < budget
+    alone = [rdm.solve(h, i.betas, i.n_v, i.k, i.seed, precision="mixed") for h, i in zip(hs, (filler, big, small))]
+    srv = rdm.Server(hbm_budget=budget, max_active=8, precision="mixed")
+    try:
+        tickets = [srv.submit(h, i.betas, i.n_v, i.k, i.seed) for h, i in zip(hs, (filler, big, small))]
+        done, res = {}, {}
+        t0 = time.perf_counter()
+        while len(done) < 3 and time.perf_counter() - t0 < 120:
+            for q, t in enumerate(tickets):
+                if q not in done:
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[q], res[q] = time.perf_counter(), r
+            time.sleep(0.0005)
+    finally:
+        srv.close()
+    assert len(done) == 3
+    assert done[2] < done[0], "the small request waited behind the blocked one"
+    for q, a in enumerate(alone):
+        assert res[q]["status"] == 0
+        for key in ("rho", "h_star", "log_z", "entropy"):
+            assert np.array_equal(a[key], res[q][key]), (q, key)
+
+
 # --------------------------------------------------------------------------
 # stored oracle results at full size (tests/golden/make_golden.py, O3 in
 # FP64): the benchmark's own 2 + 18 workload in the benchmark's launch
