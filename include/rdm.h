@@ -139,8 +139,9 @@ typedef struct {
 
 /* Build a Hamiltonian (eqn:Ht) and its bath part.  hx, hz: host arrays of
  * length n_s + n_b, coefficients of sx_i and sz_i; NULL means all zero.
- * Validation: 1 <= n_s <= 3, 1 <= n_b, n_s + n_b <= 28, every coefficient
- * finite, 0 <= i,j < N, i != j.  The library copies all inputs; device tables
+ * Validation: 1 <= n_s <= 3, 1 <= n_b, n_s + n_b <= 28 (a 16-byte panel of
+ * one vector is addressed with 32-bit byte offsets: at most 2^28 rows),
+ * every coefficient finite, 0 <= i,j < N, i != j.  The library copies all inputs; device tables
  * are built lazily on first use on the current device. */
 rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm_coupling* couplings,
                                   int64_t n_couplings, const double* hx, const double* hz,

@@ -1025,6 +1025,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_xz(const Seg* __restrict__ seg
 //   PASS 2 (contiguous tiles): w = s L R - (beta s)_{j-1} u~_{j-1};
 //     u = W_lo u~_j / L; R = s W_lo (D_Z u) + w  (= W_lo r_j);
 //     partial <u_j, r_j> = s sum d u^2 + <u~_j, w> / L
+// FP64 steps move the recurrence (ZR below): pass 2 only leaves
+// Z = W_lo D_Z u_j in Y, pass 1 of the next step starts from
+// s L R + s Z - (beta s) u~_{j-1}, and <u_j, r_j> comes from the XP_* planes.
+// Passes 3-5: the YY part (below).
 // boff offsets blockIdx.x in the segments' transform tile numbering.
 // ---------------------------------------------------------------------------
 template <typename T, int PASS, bool REGEN, int GEOM>

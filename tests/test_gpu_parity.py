@@ -166,7 +166,8 @@ def _cfg_large():
                                        (lambda: long_range_xxz(1, 20, 7), 16),
                                        (lambda: random_sparse_xxz(3001, n_range=(22, 22)), 32),
                                        (lambda: long_range_xxz(1, 22, 8), 16),
-                                       (lambda: cfg_long_range(0, n_b=22), 16)])
+                                       (lambda: cfg_long_range(0, n_b=22), 16),
+                                       (lambda: tfim_request(5, n_range=(28, 28)), 1)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_apply_full_size_sampled_rows(make, cols, prec):
     # full-size shapes (dim 2^20, 2^24 and the largest, 2^26 with all-pairs
@@ -175,7 +176,8 @@ def test_apply_full_size_sampled_rows(make, cols, prec):
     # with 9 and 10 high bits (2^22 with the XCD grouping of strided tiles);
     # the 2^23 and 2^26 all-pairs operators and the 2^24 X-type one split the
     # high bits over three strided passes (the 2^24 chain takes hop tables);
-    # the 2^21, 2^22 sparse, 2^23 and 2^26 operators have a YY part
+    # the 2^21, 2^22 sparse, 2^23 and 2^26 operators have a YY part; 2^28
+    # (the largest size, one column) runs hop tables
     inst = make()
     h = H(inst)
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
@@ -1189,21 +1191,23 @@ def _spin_state(hx, hz, beta):
     return 0.5 * (np.eye(2) - np.tanh(beta * e) * (hx * sx + hz * sz) / e)
 
 
-@pytest.mark.parametrize("n_b", [6, 14, 20])
-def test_fields_only_is_the_bare_product_state(n_b):
+@pytest.mark.parametrize("n_s,n_b,n_v", [(2, 6, 2), (2, 14, 2), (2, 20, 2), (1, 27, 1)])
+def test_fields_only_is_the_bare_product_state(n_s, n_b, n_v):
     # no couplings: H_sb = 0, so rho* is the bare system's thermal state, a
     # product of single-spin states, whatever the bath vectors (n_b = 14 and
-    # 20 run on the transform apply, 20 with 10 high bits)
-    n_s = 2
+    # 20 run on the transform apply, 20 with 10 high bits; 28 spins, the
+    # largest size, on hop tables with the two-pass plan)
     n = n_s + n_b
     rng = np.random.default_rng(n_b)
     hx, hz = rng.uniform(0.2, 0.8, n), rng.uniform(-0.5, 0.5, n)
-    inst = Instance(n_s, n_b, [], hx, hz, np.array([0.4, 1.5]), 2, 40, 9)
+    inst = Instance(n_s, n_b, [], hx, hz, np.array([0.4, 1.5]), n_v, 40, 9)
     h = H(inst)
     assert h.info()["transform"] == (16 <= n <= 22)
     r = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="fp64")
     for b, beta in enumerate(inst.betas):
-        want = np.kron(_spin_state(hx[0], hz[0], beta), _spin_state(hx[1], hz[1], beta))
+        want = _spin_state(hx[0], hz[0], beta)
+        for s_ in range(1, n_s):
+            want = np.kron(want, _spin_state(hx[s_], hz[s_], beta))
         assert np.abs(r["rho"][b] - want).max() < 1e-10
         hs = rdm.Hamiltonian.from_instance(inst).system_matrix()
         assert np.abs(r["h_star"][b] - hs).max() < 1e-8
