@@ -986,6 +986,9 @@ SPLIT_CASES = {
     "tfim_2+21": lambda: tfim_request(17, n_range=(23, 23), n_v=1, k=20),
     "xxz_1+22": lambda: long_range_xxz(1, 22, 88, betas=(0.5, 2.0), n_v=1, k=20),
     "chain_1+23": lambda: nn_xxz_chain(1, 23, 89, betas=(1.0,), n_v=1, k=16),
+    # the largest workload's operator (all-pairs XXZ, 3 + 23 spins, 7 + 7 high
+    # bits) with one bath vector and a short Krylov space
+    "large_3+23": lambda: __import__("dataclasses").replace(_cfg_large(), n_v=1, k=12),
 }
 
 
