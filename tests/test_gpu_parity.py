@@ -257,6 +257,11 @@ SOLVE_CASES = {
     "xz_2+14": lambda: long_range_xx_zz(2, 14, 1.0, 75, betas=(0.5, 2.0), n_v=2, k=30),
     # 16 bits with YY couplings: the transform apply with its YY part
     "xxz_2+14": lambda: long_range_xxz(2, 14, 76, betas=(0.5, 2.0), n_v=2, k=30),
+    # the shortest Krylov spaces: one and two steps (T_k of size 1 and 2), one
+    # bath vector, on hop tables and on the transform apply
+    "k1_2+6": lambda: random_dense_terms(2, 6, 91, k=1, n_v=1, betas=(0.3, 3.0)),
+    "k2_1+9": lambda: random_dense_terms(1, 9, 92, k=2, n_v=3, betas=(1.0,)),
+    "k1_xz_2+14": lambda: long_range_xx_zz(2, 14, 1.0, 77, betas=(0.5, 2.0), n_v=1, k=1),
 }
 
 # cases that exercise an apply kind other than the default
