@@ -94,7 +94,9 @@ typedef struct {
   double tau;          /* breakdown threshold (0 = 1e-12 FP64, 1e-5 mixed)    */
   int32_t profile;      /* 1: time the step kernels with HIP events on
                            hip_stream (results in rdm_result.diag; the steps
-                           are then launched one by one)                      */
+                           are then launched one by one).  2: keep the graph
+                           replay and time each replayed phase with HIP
+                           events on the replay stream (diag[11..12])        */
   int32_t eager;        /* 1: launch every Lanczos step's kernels one by one;
                            by default the steps of a solve or batch run as one
                            captured hipGraph, replayed by later calls with
@@ -134,7 +136,11 @@ typedef struct {
                        (ms), [10] mean transform pass 1 time (ms; norm step
                        and high-bit transform) -- [7..10] only when
                        rdm_options.profile = 1 (event timing), else 0 --
-                       [11..15] zero; then per beta {ln Z_t, ln Z_b}.        */
+                       [11] mean time of a replayed Lanczos step (ms: all
+                       its kernels, as they ran), [12] steps replayed --
+                       only when rdm_options.profile = 2 (for a batch:
+                       the steps of all its instances together) --
+                       [13..15] zero; then per beta {ln Z_t, ln Z_b}.        */
 } rdm_result;
 
 /* Build a Hamiltonian (eqn:Ht) and its bath part.  hx, hz: host arrays of

@@ -65,7 +65,9 @@ def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_l
     o.slab = int(slab)
     o.rows_per_lane = int(rows_per_lane)
     o.tau = float(tau)
-    o.profile = 1 if profile else 0
+    # profile: False, True (event-timed kernels, launched one by one) or
+    # "replay" (the graph replay kept and each replayed phase timed)
+    o.profile = 2 if profile == "replay" else int(profile)
     o.eager = 1 if eager else 0
     o.method = METHODS[method] if isinstance(method, str) else int(method)
     return o
@@ -162,6 +164,7 @@ class _ResultBuffers:
                 "breakdown_total": int(d[2]), "breakdown_bath": int(d[3]),
                 "two_pass": bool(d[4]), "device_bytes": int(d[5]), "mu_ratio": d[6],
                 "t_apply_ms": d[7], "t_norm_ms": d[8], "t_gram_ms": d[9], "t_xz1_ms": d[10],
+                "t_replay_step_ms": d[11], "replay_steps": int(d[12]),
                 "log_z_t": d[DIAG_FIXED::2][:nb].copy(), "log_z_b": d[DIAG_FIXED + 1::2][:nb].copy()}
 
 

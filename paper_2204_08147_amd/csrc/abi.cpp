@@ -16,7 +16,7 @@ struct Opts {
   int prec = RDM_FP64, mode = RDM_AUTO, slab = 0, rpl = 0;
   uint64_t budget = 0;
   double tau = 0;
-  bool profile = false;
+  int profile = 0;     // 1: event-timed kernels (eager), 2: timed graph replays
   bool eager = false;  // no hipGraph replay of the Lanczos steps
   int method = RDM_PER_COLUMN;
 };
@@ -29,7 +29,7 @@ rdm_status read_opts(const rdm_options* o, Opts& r) {
     r.slab = o->slab;
     r.rpl = o->rows_per_lane;
     r.tau = o->tau;
-    r.profile = o->profile != 0;
+    r.profile = o->profile;
     r.eager = o->eager != 0;
     r.method = o->method;
     if (o->reserved != 0) {
@@ -51,6 +51,10 @@ rdm_status read_opts(const rdm_options* o, Opts& r) {
   }
   if (!(r.tau >= 0.0) || !std::isfinite(r.tau)) {
     set_error("options: tau must be finite and >= 0");
+    return RDM_E_INVALID;
+  }
+  if (r.profile < 0 || r.profile > 2) {
+    set_error("options: profile must be 0, 1 or 2");
     return RDM_E_INVALID;
   }
   if (r.method != RDM_PER_COLUMN && r.method != RDM_BLOCK && r.method != RDM_METHOD_AUTO) {
@@ -162,7 +166,7 @@ static rdm_status solve_impl(const rdm_hamiltonian* h, const double* beta, int32
       RDM_HIP(hipMalloc(&ws, bp.bytes));
       owned = true;
     }
-    s = block_solve(bp, beta, seed, o.tau, ws, st, o.profile, out);
+    s = block_solve(bp, beta, seed, o.tau, ws, st, o.profile == 1, out);
     if (owned) (void)hipFree(ws);
     return s;
   }
@@ -185,7 +189,7 @@ static rdm_status solve_impl(const rdm_hamiltonian* h, const double* beta, int32
   runs[0].plan = &plans[0];
   runs[0].betas.assign(beta, beta + n_beta);
   runs[0].seed = seed;
-  s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0, !o.eager);
+  s = execute(runs, ws, st, o.tau, o.profile == 1, o.slab == 0, !o.eager, true, o.profile == 2);
   if (s == RDM_OK) s = runs[0].status;
   if (s == RDM_OK) s = finalize(runs[0], out);
   if (owned) (void)hipFree(ws);
@@ -384,7 +388,7 @@ rdm_status batch_impl(int32_t n_items, rdm_batch_item* items, const rdm_options*
       runs[w].betas.assign(items[wave[w]].beta, items[wave[w]].beta + items[wave[w]].n_beta);
       runs[w].seed = items[wave[w]].seed;
     }
-    s = execute(runs, ws, st, o.tau, o.profile, o.slab == 0, !o.eager);
+    s = execute(runs, ws, st, o.tau, o.profile == 1, o.slab == 0, !o.eager, true, o.profile == 2);
     for (size_t w = 0; w < wave.size(); ++w) {
       rdm_batch_item& it = items[wave[w]];
       it.status = s != RDM_OK ? s : runs[w].status;

@@ -644,10 +644,45 @@ std::map<GraphKey, hipGraphExec_t> g_graphs;
 std::vector<GraphKey> g_graph_order;  // insertion order, for eviction
 std::map<int, hipStream_t> g_graph_stream;
 
+rdm_status graph_steps_locked(int prec, Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, int nsteps,
+                              hipStream_t st, int dev, hipEvent_t t0, hipEvent_t t1);
+
 rdm_status graph_steps(int prec, Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, int nsteps,
-                       hipStream_t st) {
+                       hipStream_t st, ReplayTimer* rt) {
   int dev = 0;
   RDM_HIP(hipGetDevice(&dev));
+  // rt: timing events around the replay on the replay stream, read after
+  // the lock is released
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (rt) {
+    RDM_HIP(hipEventCreate(&t0));
+    if (hipEventCreate(&t1) != hipSuccess) {
+      (void)hipEventDestroy(t0);
+      set_error("hipEventCreate failed");
+      return RDM_E_DEVICE;
+    }
+  }
+  auto drop_timers = [&]() {
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  };
+  rdm_status ls = graph_steps_locked(prec, dsegs, nseg, L, slab, cmax, nsteps, st, dev, t0, t1);
+  if (ls == RDM_OK && rt) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+      drop_timers();
+      set_error("replay timing failed");
+      return RDM_E_DEVICE;
+    }
+    rt->ms += ms;
+    rt->steps += nsteps;
+  }
+  drop_timers();
+  return ls;
+}
+
+rdm_status graph_steps_locked(int prec, Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, int nsteps,
+                              hipStream_t st, int dev, hipEvent_t t0, hipEvent_t t1) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   hipStream_t gs;
   auto its = g_graph_stream.find(dev);
@@ -693,7 +728,9 @@ rdm_status graph_steps(int prec, Seg* dsegs, int nseg, const Launch& L, int slab
   }
   hipError_t e = hipEventRecord(before, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(gs, before, 0);
+  if (e == hipSuccess && t0) e = hipEventRecord(t0, gs);
   if (e == hipSuccess) e = hipGraphLaunch(exec, gs);
+  if (e == hipSuccess && t1) e = hipEventRecord(t1, gs);
   if (e == hipSuccess) e = hipEventRecord(after, gs);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, after, 0);
   (void)hipEventDestroy(before);
@@ -705,7 +742,7 @@ rdm_status graph_steps(int prec, Seg* dsegs, int nseg, const Launch& L, int slab
 }  // namespace
 
 rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
-                     StepTimers* tm, bool tune, bool graph) {
+                     StepTimers* tm, bool tune, bool graph, ReplayTimer* rt) {
   if (hsegs.empty()) return RDM_OK;
   for (const auto& sg : hsegs)
     if ((sg.xy || (sg.xz && prec == RDM_FP64)) && !sg.Y) {
@@ -784,7 +821,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
     if (s != RDM_OK) return s;
   }
   if (graph && !tm && kmax - j + 1 >= 2) {
-    rdm_status s = graph_steps(prec, dsegs, nseg, ntiles, slab, cmax, kmax - j + 1, st);
+    rdm_status s = graph_steps(prec, dsegs, nseg, ntiles, slab, cmax, kmax - j + 1, st, rt);
     if (s != RDM_OK) return s;
     j = kmax + 1;
   }
@@ -798,7 +835,7 @@ rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, h
 }
 
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
-                   bool tune, bool graph, bool build_tables) {
+                   bool tune, bool graph, bool build_tables, bool replay_timing) {
   Range range("rdm execute");
   const int ni = (int)runs.size();
   if (ni == 0) return RDM_OK;
@@ -816,6 +853,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
   }
   StepTimers tm;
   tm.apply.on = tm.norm.on = tm.xz1.on = profile;
+  ReplayTimer rt;
   // pass 1: every total and bath segment in the same launches
   std::vector<Seg> segs;
   for (auto& r : runs) {
@@ -825,7 +863,7 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
   rdm_status s;
   {
     Range lr("rdm lanczos");
-    s = run_phase(segs, dsegs, prec, 0, st, profile ? &tm : nullptr, tune, graph);
+    s = run_phase(segs, dsegs, prec, 0, st, profile ? &tm : nullptr, tune, graph, replay_timing ? &rt : nullptr);
   }
   if (s != RDM_OK) return s;
   {
@@ -838,7 +876,8 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
     if (r.plan->two_pass && r.status == RDM_OK) segs.push_back(seg_of(r, 0, MODE_REGEN, tau));
   {
     Range rr("rdm regeneration");
-    if ((s = run_phase(segs, dsegs, prec, 1, st, nullptr, tune, graph)) != RDM_OK) return s;
+    if ((s = run_phase(segs, dsegs, prec, 1, st, nullptr, tune, graph, replay_timing ? &rt : nullptr)) != RDM_OK)
+      return s;
   }
   Timers tg;
   tg.on = profile;
@@ -848,6 +887,10 @@ rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double 
       if (r.status != RDM_OK) continue;
       if ((s = gram_phase(r, st, profile ? &tg : nullptr)) != RDM_OK) return s;
     }
+  }
+  for (auto& r : runs) {
+    r.replay_steps = rt.steps;
+    r.t_replay_ms = rt.steps ? rt.ms / rt.steps : 0.0;
   }
   if (profile)
     for (auto& r : runs) {
@@ -933,7 +976,9 @@ rdm_status finalize(const InstRun& r, rdm_result* out) {
     d[8] = r.t_norm_ms;
     d[9] = r.t_gram_ms;
     d[10] = r.t_xz1_ms;
-    for (int t = 11; t < kDiagFixed; ++t) d[t] = 0.0;
+    d[11] = r.t_replay_ms;
+    d[12] = r.replay_steps;
+    for (int t = 13; t < kDiagFixed; ++t) d[t] = 0.0;
   }
   return RDM_OK;
 }

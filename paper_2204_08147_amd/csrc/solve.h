@@ -77,6 +77,12 @@ struct Timers {
 struct StepTimers {
   Timers apply, norm, xz1;
 };
+// Replayed Lanczos steps timed as they run (rdm_options.profile = 2): HIP
+// events around each graph replay on the replay stream.
+struct ReplayTimer {
+  double ms = 0.0;
+  int steps = 0;
+};
 
 struct InstRun {
   const InstPlan* plan = nullptr;
@@ -90,6 +96,8 @@ struct InstRun {
   int n_break_t = 0, n_break_b = 0;
   std::vector<double> mb, gsum;
   double t_apply_ms = 0, t_norm_ms = 0, t_gram_ms = 0, t_xz1_ms = 0;
+  double t_replay_ms = 0;  // mean replayed step (ms) and steps replayed (profile = 2)
+  int replay_steps = 0;
 };
 
 void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int rpl_opt, int nslots,
@@ -100,8 +108,9 @@ size_t batch_header_bytes(const std::vector<InstPlan>& plans);
 // graph: replay the Lanczos steps as a captured hipGraph (unless profiling)
 // build_tables = false: the operators' device tables must be resident
 // already (nothing is allocated)
+// replay_timing: time the replayed steps with HIP events (graphs kept)
 rdm_status execute(std::vector<InstRun>& runs, char* ws, hipStream_t st, double tau, bool profile,
-                   bool tune, bool graph, bool build_tables = true);
+                   bool tune, bool graph, bool build_tables = true, bool replay_timing = false);
 
 // Phases (used by execute and by the serving engine).
 rdm_status bind_ops(InstRun& r, hipStream_t st, bool build_tables = true);
@@ -133,7 +142,7 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
 rdm_status init_run(int prec, const Seg* dsegs, int nseg, int cmax, int phase, int xz_tiles, int xz_boff,
                     hipStream_t st);
 rdm_status run_phase(std::vector<Seg>& hsegs, Seg* dsegs, int prec, int phase, hipStream_t st,
-                     StepTimers* tm, bool tune, bool graph);
+                     StepTimers* tm, bool tune, bool graph, ReplayTimer* rt = nullptr);
 // Panels per lane for a launch over these segments: the cached measurement
 // for the shape of the largest one, else one panel.
 int tuned_slab(int prec, std::vector<Seg>& segs);

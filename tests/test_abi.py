@@ -173,6 +173,11 @@ def test_block_method_validation():
     with pytest.raises(rdm.RdmError) as e:
         rdm.workspace_size(h, 1, 4, 30, precision="fp64", method=3, hbm_budget=1 << 40)
     assert e.value.status == -1
+    # profile: 0 off, 1 event-timed kernels, 2 timed graph replays
+    with pytest.raises(rdm.RdmError) as e:
+        rdm.workspace_size(h, 1, 4, 30, precision="fp64", profile=3, hbm_budget=1 << 40)
+    assert e.value.status == -1
+    assert rdm.make_options(profile="replay").profile == 2 and rdm.make_options(profile=True).profile == 1
     # the block method plans a few vector blocks, no Lanczos basis (an explicit
     # budget keeps the planner off the device)
     wb = rdm.workspace_size(h, 1, 4, 30, precision="fp64", method="block", hbm_budget=1 << 40)

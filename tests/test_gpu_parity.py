@@ -550,6 +550,14 @@ def test_graph_replay_equals_eager(prec):
         again = rdm.solve(hs[names[0]], insts[names[0]].betas, insts[names[0]].n_v, insts[names[0]].k,
                           insts[names[0]].seed, precision=prec, workspace=ws[names[0]], eager=True)
         assert np.array_equal(again["rho"], eager[names[0]]["rho"])
+    # timed replays (profile = 2) are the same replays: same results, and
+    # every step after the slab tuner's is timed
+    for n, i in insts.items():
+        t = rdm.solve(hs[n], i.betas, i.n_v, i.k, i.seed, precision=prec, workspace=ws[n], profile="replay")
+        for key in ("rho", "h_star", "log_z", "entropy"):
+            assert np.array_equal(t[key], eager[n][key]), ("replay timing", n, key)
+        assert 0 < t["replay_steps"] <= i.k and t["t_replay_step_ms"] > 0.0
+        assert t["t_apply_ms"] == 0.0  # no per-kernel event timing in this mode
     # a batch (one graph over all segments) equals the eager batch
     items = [dict(h=hs[n], betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for n, i in insts.items()]
     b1 = rdm.solve_batch(items, precision=prec, eager=True)
