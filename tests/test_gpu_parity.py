@@ -26,6 +26,11 @@ def _announce(request):
     sys.__stderr__.write(f"\n[gpu-test] {request.node.nodeid}\n")
     sys.__stderr__.flush()
     yield
+    # the full-size tests take tens of GB: hand the caching allocator's
+    # blocks back so that later plans see the device's memory as free
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
 
 
 def rel(a, b):
