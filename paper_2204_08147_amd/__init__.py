@@ -191,7 +191,15 @@ def solve(h: Hamiltonian, betas: Sequence[float], n_v: int, k: int, seed: int, *
                              C.byref(res.c)), "rdm_solve")
     else:
         if workspace is None:
-            nbytes = workspace_size(h, len(betas), n_v, k, **opts)
+            wopts = dict(opts)
+            if not wopts.get("hbm_budget"):
+                # torch allocates the workspace and may reuse its cached
+                # blocks: the budget is the free memory plus that cache, less
+                # the library's 2 GiB reserve
+                free, _ = torch.cuda.mem_get_info()
+                cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
+                wopts["hbm_budget"] = max(1, free + cached - (2 << 30))
+            nbytes = workspace_size(h, len(betas), n_v, k, **wopts)
             workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         _check(LIB.rdm_solve_ws(h.handle, _dptr(betas), len(betas), n_v, k, seed, C.byref(o), st,
                                 C.byref(res.c), C.c_void_p(workspace.data_ptr()),
