@@ -109,7 +109,7 @@ typedef struct {
                            each bath vector's d_s start columns and the block
                            Gauss quadrature E_1^T exp(-beta T) E_1 (eqn:fT,
                            eqn:trB_est); single solves only (rdm_solve,
-                           rdm_solve_ws), no Lanczos basis is kept.
+                           rdm_solve_ws), no Lanczos basis is kept; n_s <= 3.
                            RDM_METHOD_AUTO (2): per-column when its plan
                            keeps the Lanczos basis within the budget, block
                            when the basis would not fit (with mode RDM_AUTO;
@@ -145,7 +145,7 @@ typedef struct {
 
 /* Build a Hamiltonian (eqn:Ht) and its bath part.  hx, hz: host arrays of
  * length n_s + n_b, coefficients of sx_i and sz_i; NULL means all zero.
- * Validation: 1 <= n_s <= 3, 1 <= n_b, n_s + n_b <= 28 (a 16-byte panel of
+ * Validation: 1 <= n_s <= 4, 1 <= n_b, n_s + n_b <= 28 (a 16-byte panel of
  * one vector is addressed with 32-bit byte offsets: at most 2^28 rows),
  * every coefficient finite, 0 <= i,j < N, i != j.  The library copies all inputs; device tables
  * are built lazily on first use on the current device. */
@@ -358,6 +358,7 @@ typedef struct {
                          invariant subspace.  Small against the gap to the
                          next eigenvalue means a converged ground space. */
 } rdm_ground_result;
+/* (n_s <= 3: RDM_E_INVALID otherwise.) */
 rdm_status rdm_ground_state(const rdm_hamiltonian* h, int32_t n_v, int32_t k, uint64_t seed,
                             const rdm_options* opt, void* hip_stream, rdm_ground_result* out);
 

@@ -105,7 +105,7 @@ rdm_status default_budget(uint64_t& budget) {
 static rdm_status resolve_method(Opts& o, const rdm_hamiltonian* h, int n_beta, int n_v, int k) {
   if (o.method != RDM_METHOD_AUTO) return RDM_OK;
   o.method = RDM_PER_COLUMN;
-  if (o.mode != RDM_AUTO) return RDM_OK;
+  if (o.mode != RDM_AUTO || h->n_s > 3) return RDM_OK;  // the block variant takes d_s <= 8
   std::vector<InstPlan> plans(1);
   const rdm_status s = plan_instance(plans[0], h, n_beta, n_v, k, o.prec, o.mode, o.budget, o.slab, o.rpl);
   if (s == RDM_E_NOMEM || (s == RDM_OK && plans[0].two_pass)) o.method = RDM_BLOCK;

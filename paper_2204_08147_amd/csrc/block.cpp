@@ -26,6 +26,10 @@ size_t sbytes(int prec) { return prec == RDM_FP64 ? 8 : 4; }
 rdm_status block_plan(BlockPlan& bp, const rdm_hamiltonian* h, int n_beta, int n_v, int k, int prec,
                       uint64_t budget) {
   bp = BlockPlan{};
+  if (h->n_s > 3) {
+    set_error("the block variant takes n_s <= 3 (d_s <= 8)");
+    return RDM_E_INVALID;
+  }
   bp.h = h;
   bp.prec = prec;
   bp.n_beta = n_beta;

@@ -37,6 +37,10 @@ struct GroundPlan {
 
 rdm_status ground_plan(GroundPlan& gp, const rdm_hamiltonian* h, int n_v, int k, int prec, uint64_t budget) {
   gp = GroundPlan{};
+  if (h->n_s > 3) {
+    set_error("rdm_ground_state takes n_s <= 3 (d_s <= 8)");
+    return RDM_E_INVALID;
+  }
   gp.prec = prec;
   gp.n_v = n_v;
   gp.ds = 1 << h->n_s;

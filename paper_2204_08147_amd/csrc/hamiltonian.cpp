@@ -286,8 +286,8 @@ extern "C" rdm_status rdm_hamiltonian_create_ex(int32_t n_s, int32_t n_b, const 
     set_error("rdm_hamiltonian_create_ex: apply must be RDM_APPLY_AUTO, RDM_APPLY_HOPS or RDM_APPLY_TRANSFORM");
     return RDM_E_INVALID;
   }
-  if (n_s < 1 || n_s > 3 || n_b < 1 || n_s + n_b > 28) {
-    set_error("rdm_hamiltonian_create: need 1 <= n_s <= 3, n_b >= 1, n_s + n_b <= 28");
+  if (n_s < 1 || n_s > 4 || n_b < 1 || n_s + n_b > 28) {
+    set_error("rdm_hamiltonian_create: need 1 <= n_s <= 4, n_b >= 1, n_s + n_b <= 28");
     return RDM_E_INVALID;
   }
   if (n_couplings < 0 || (n_couplings > 0 && !couplings)) {

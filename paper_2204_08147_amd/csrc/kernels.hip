@@ -1749,15 +1749,31 @@ __global__ __launch_bounds__(kBlock) void k_red_alpha(const Seg* __restrict__ se
 // d_s x d_s Gram blocks, accumulated per lane over its rows in T and summed
 // across lanes / tiles in FP64.
 // ---------------------------------------------------------------------------
-template <typename T, int DS, int NB>
+// PART 0: the whole d_s x d_s Gram (d_s <= 8).  d_s = 16 takes three
+// launches over the column halves A = 0..7 and B = 8..15 of each bath
+// vector: PART 1 the block AA, 2 the block AB, 3 the block BB (each block's
+// products in registers; only the panels a block needs are read).
+template <int DS, int PART> struct GramBlock {
+  static constexpr int M0 = PART == 3 ? DS / 2 : 0;
+  static constexpr int M1 = PART == 0 ? DS : (PART == 3 ? DS : DS / 2);
+  static constexpr int N0 = PART == 2 || PART == 3 ? DS / 2 : 0;
+  static constexpr int N1 = PART == 1 ? DS / 2 : DS;
+  static constexpr bool TRI = PART != 2;  // a diagonal block: n >= m only
+  static constexpr int NE = TRI ? (M1 - M0) * (M1 - M0 + 1) / 2 : (M1 - M0) * (N1 - N0);
+  static constexpr int C0 = M0 < N0 ? M0 : N0, C1 = M1 > N1 ? M1 : N1;  // columns read
+};
+
+template <typename T, int DS, int NB, int PART>
 __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
                                                  const GTile* __restrict__ tiles, int beta0) {
   using V = typename PanelT<T>::V;
+  using GB = GramBlock<DS, PART>;
   constexpr int W = PanelT<T>::W;
   constexpr int CB = DS > W ? DS : W;
   constexpr int NPAN = CB / W;
+  constexpr int Q0 = GB::C0 / W, Q1 = (GB::C1 + W - 1) / W;  // panels read
   constexpr int NG = CB / DS;
-  constexpr int NE = DS * (DS + 1) / 2;
+  constexpr int NE = GB::NE;
   constexpr int NV = NB * NG * NE;
   extern __shared__ double smem[];
   double* lds = smem;                       // 4 * NV doubles
@@ -1789,7 +1805,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int q = 0; q < NPAN; ++q) {
+        for (int q = Q0; q < Q1; ++q) {
           if (b < nb) {
             const V* pb = (const V*)g.Q + (uint64_t)(beta0 + b) * (g.blk / W) +
                           (uint64_t)(t.cblock * NPAN + q) * pstride;
@@ -1810,11 +1826,11 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
         const V* sb = (const V*)g.Q + (uint64_t)jj * (g.blk / W);
         V qv[NPAN];
 #pragma unroll
-        for (int q = 0; q < NPAN; ++q) qv[q] = ldg_nt(sb + (uint64_t)(t.cblock * NPAN + q) * pstride, row);
+        for (int q = Q0; q < Q1; ++q) qv[q] = ldg_nt(sb + (uint64_t)(t.cblock * NPAN + q) * pstride, row);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int q = 0; q < NPAN; ++q)
+          for (int q = Q0; q < Q1; ++q)
 #pragma unroll
             for (int e = 0; e < W; ++e)
               psi[b][q][e] = fma_s(ys[(jj * NB + b) * CB + q * W + e], qv[q][e], psi[b][q][e]);
@@ -1826,9 +1842,9 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
       for (int gg = 0; gg < NG; ++gg) {
         int e = 0;
 #pragma unroll
-        for (int m = 0; m < DS; ++m)
+        for (int m = GB::M0; m < GB::M1; ++m)
 #pragma unroll
-          for (int n = m; n < DS; ++n) {
+          for (int n = GB::TRI ? m : GB::N0; n < GB::N1; ++n) {
             const int cm = gg * DS + m, cn = gg * DS + n;
             const T pm = psi[b][cm / W][cm % W], pn = psi[b][cn / W][cn % W];
             gacc[(b * NG + gg) * NE + e] = fma_s(pm, pn, gacc[(b * NG + gg) * NE + e]);
@@ -1846,9 +1862,16 @@ __global__ __launch_bounds__(kBlock) void k_gram(const GSeg* __restrict__ gsegs,
     const int b = i / (NG * NE), gg = (i / NE) % NG, e = i % NE;
     const int jv = t.cblock * NG + gg;
     if (b < nb && jv < g.n_v) {
-      int m = 0, rem = e;
-      while (rem >= DS - m) { rem -= DS - m; ++m; }
-      const int n = m + rem;
+      int m, n;
+      if (GB::TRI) {
+        int rem = e;
+        m = GB::M0;
+        while (rem >= GB::M1 - m) { rem -= GB::M1 - m; ++m; }
+        n = m + rem;
+      } else {
+        m = GB::M0 + e / (GB::N1 - GB::N0);
+        n = GB::N0 + e % (GB::N1 - GB::N0);
+      }
       double* o = g.gpart + ((((uint64_t)t.rtile * g.n_beta + beta0 + b) * g.n_v + jv) * DS) * DS;
       o[m * DS + n] = tot;
       o[n * DS + m] = tot;
@@ -2040,16 +2063,16 @@ hipError_t launch_init_state(const Seg* segs, int nseg, int cmax, int phase, hip
   return hipGetLastError();
 }
 
-template <typename T, int DS, int NB>
+template <typename T, int DS, int NB, int PART = 0>
 static hipError_t launch_gram_t(const GSeg* gs, const GTile* tiles, int ntiles, int beta0, int k,
                                 hipStream_t st) {
   constexpr int W = PanelT<T>::W;
   constexpr int CB = DS > W ? DS : W;
   constexpr int NG = CB / DS;
-  constexpr int NE = DS * (DS + 1) / 2;
+  constexpr int NE = GramBlock<DS, PART>::NE;
   constexpr int NV = NB * NG * NE;
   const size_t shm = 4 * NV * sizeof(double) + (size_t)k * NB * CB * sizeof(T);
-  hipLaunchKernelGGL((k_gram<T, DS, NB>), dim3(ntiles), dim3(kBlock), shm, st, gs, tiles, beta0);
+  hipLaunchKernelGGL((k_gram<T, DS, NB, PART>), dim3(ntiles), dim3(kBlock), shm, st, gs, tiles, beta0);
   return hipGetLastError();
 }
 
@@ -2062,6 +2085,12 @@ hipError_t launch_gram(const GSeg* gs, const GTile* tiles, int ntiles, int ds, i
   RDM_G(2, 1) RDM_G(2, 2) RDM_G(2, 4) RDM_G(4, 1) RDM_G(4, 2) RDM_G(4, 4)
   RDM_G(8, 1) RDM_G(8, 2)
 #undef RDM_G
+  if (ds == 16 && nb_chunk == 1) {
+    hipError_t e = launch_gram_t<T, 16, 1, 1>(gs, tiles, ntiles, beta0, k, st);
+    if (e == hipSuccess) e = launch_gram_t<T, 16, 1, 2>(gs, tiles, ntiles, beta0, k, st);
+    if (e == hipSuccess) e = launch_gram_t<T, 16, 1, 3>(gs, tiles, ntiles, beta0, k, st);
+    return e;
+  }
   return hipErrorInvalidValue;
 }
 

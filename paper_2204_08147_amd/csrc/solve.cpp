@@ -146,6 +146,7 @@ void plan_seg(SegPlan& g, int nbits, int C, int k, int prec, int slab_opt, int r
 }
 
 int max_nb_chunk(int prec, int ds) {
+  if (ds >= 16) return 1;  // the Gram in three column blocks, one temperature at a time
   if (ds >= 8) return prec == RDM_FP64 ? 1 : 2;
   return 4;
 }

@@ -99,7 +99,7 @@ def test_transform_apply_selection():
 
 @pytest.mark.parametrize("bad", [
     dict(n_s=0, n_b=4, couplings=[]),
-    dict(n_s=4, n_b=4, couplings=[]),
+    dict(n_s=5, n_b=4, couplings=[]),
     dict(n_s=2, n_b=27, couplings=[]),
     dict(n_s=1, n_b=3, couplings=[(0, 0, 1.0, 0, 0)]),
     dict(n_s=1, n_b=3, couplings=[(0, 4, 1.0, 0, 0)]),
@@ -166,6 +166,18 @@ def test_block_quadrature_matches_oracle():
         for q, bt in enumerate([0.3, 1.7]):
             want = block.block_quadrature(t, b, bt, e0)
             assert np.abs(f[q] - want).max() < 1e-12 * np.abs(want).max(), (t.shape, b, bt)
+
+
+def test_four_system_spins_take_the_per_column_path():
+    # d_s = 16: the per-column solve (its Gram in three column blocks); the
+    # block variant and the ground-state path keep d_s <= 8
+    inst = random_dense_terms(4, 6, 93, n_v=2, k=30)
+    h = rdm.Hamiltonian.from_instance(inst)
+    with pytest.raises(rdm.RdmError) as e:
+        rdm.workspace_size(h, 1, 2, 30, precision="fp64", method="block", hbm_budget=1 << 40)
+    assert e.value.status == -1
+    auto = rdm.workspace_size(h, 1, 2, 30, precision="fp64", method="auto", hbm_budget=1 << 40)
+    assert auto == rdm.workspace_size(h, 1, 2, 30, precision="fp64", mode="stored", hbm_budget=1 << 40)
 
 
 def test_block_method_validation():

@@ -267,6 +267,10 @@ SOLVE_CASES = {
     "k1_2+6": lambda: random_dense_terms(2, 6, 91, k=1, n_v=1, betas=(0.3, 3.0)),
     "k2_1+9": lambda: random_dense_terms(1, 9, 92, k=2, n_v=3, betas=(1.0,)),
     "k1_xz_2+14": lambda: long_range_xx_zz(2, 14, 1.0, 77, betas=(0.5, 2.0), n_v=1, k=1),
+    # four system spins (d_s = 16: the Gram in three column blocks), on hop
+    # tables and on the transform apply
+    "random_4+6": lambda: random_dense_terms(4, 6, 93, betas=(0.4, 2.0), n_v=2, k=30),
+    "xz_4+12": lambda: long_range_xx_zz(4, 12, 1.0, 95, betas=(1.0,), n_v=1, k=30),
 }
 
 # cases that exercise an apply kind other than the default
@@ -442,6 +446,12 @@ def test_ground_state_matches_oracle(name):
     assert np.abs(mixed["rho"] - want["rho"]).max() < 1e-3
     assert abs(mixed["e_total"] - want["e_total"]) < 1e-4 * max(1.0, abs(want["e_total"]))
     assert 0.0 <= got["residual"] < 1e-3, got["residual"]
+
+
+def test_ground_state_takes_at_most_three_system_spins():
+    with pytest.raises(rdm.RdmError) as e:
+        rdm.ground_state(H(random_dense_terms(4, 6, 93)), 2, 20, 5, precision="fp64")
+    assert e.value.status == -1
 
 
 def test_ground_state_residual_tracks_convergence():
@@ -621,7 +631,7 @@ def test_k_capped_at_dimension():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_equals_solo(prec):
     insts = [SOLVE_CASES[n]() for n in ("chain_1+9", "random_2+6", "xz_2+14", "random_3+5", "lr_2+9",
-                                        "sparse")]
+                                        "sparse", "random_4+6")]
     hs = [H(i) for i in insts]
     items = [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
     batch = rdm.solve_batch(items, precision=prec)

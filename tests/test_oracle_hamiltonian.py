@@ -43,7 +43,7 @@ def test_xx_chain_free_fermion_spectrum(n, J, h):
     assert np.allclose(np.sort(np.linalg.eigvalsh(H)), np.sort(many), atol=1e-12)
 
 
-@pytest.mark.parametrize("n_s,n_b,seed", [(1, 4, 1), (2, 4, 2), (3, 3, 3)])
+@pytest.mark.parametrize("n_s,n_b,seed", [(1, 4, 1), (2, 4, 2), (3, 3, 3), (4, 3, 4)])
 def test_matrix_free_equals_dense(n_s, n_b, seed):
     inst = random_dense_terms(n_s, n_b, seed)
     H = spin.dense_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)

@@ -54,7 +54,9 @@ def test_function_approximation_exact_for_low_degree():
 
 @pytest.mark.parametrize("make", [cfg_small_chain,
                                   lambda: random_dense_terms(2, 5, 33, betas=(0.3, 1.0, 2.5), k=40),
-                                  lambda: long_range_xx_zz(2, 6, 1.0, 34, n_v=3, k=40)])
+                                  lambda: long_range_xx_zz(2, 6, 1.0, 34, n_v=3, k=40),
+                                  # four system spins (d_s = 16), the Krylov space the whole space
+                                  lambda: random_dense_terms(4, 3, 35, betas=(0.5, 2.0), n_v=2, k=128)])
 def test_lanczos_path_equals_exact_typicality(make):
     inst = make()
     o2 = exact.exact_typicality(inst)
