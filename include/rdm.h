@@ -62,7 +62,7 @@ typedef enum {
 enum { RDM_FP64 = 0, RDM_MIXED = 1 };                 /* rdm_options.precision */
 enum { RDM_AUTO = 0, RDM_STORED_Q = 1, RDM_TWO_PASS = 2 };  /* rdm_options.mode */
 enum { RDM_PER_COLUMN = 0, RDM_BLOCK = 1, RDM_METHOD_AUTO = 2 };  /* rdm_options.method */
-enum { RDM_APPLY_AUTO = 0, RDM_APPLY_HOPS = 1, RDM_APPLY_TRANSFORM = 2 };  /* rdm_hamiltonian_create_ex */
+enum { RDM_APPLY_AUTO = 0, RDM_APPLY_HOPS = 1, RDM_APPLY_TRANSFORM = 2, RDM_APPLY_HOPS_ROWS = 3 };  /* rdm_hamiltonian_create_ex */
 
 /* One two-site term: jx sx_i sx_j + jy sy_i sy_j + jz sz_i sz_j (Pauli),
  * eqn:Ht.  0 <= i, j < N, i != j; (i, j) and (j, i) denote the same pair. */
@@ -154,15 +154,22 @@ rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm_coupling* 
                                   rdm_hamiltonian** out);
 /* As rdm_hamiltonian_create, choosing how products with H_t and H_b are
  * computed (the results agree to rounding either way):
- *   RDM_APPLY_HOPS: gathers of the partner rows idx ^ f from hop tables;
- *   RDM_APPLY_TRANSFORM: on 16..22 sites, H = D_Z + W D_X W + T W D_Y W T
+ *   RDM_APPLY_HOPS: gathers of the partner rows idx ^ f from hop tables.
+ *     Tiles of 256 consecutive rows, or, for the Lanczos steps on 12 sites
+ *     and more, tiles of the 4096 rows that differ only in 12 row bits chosen
+ *     per operator (the 4 lowest and those that leave the fewest distinct
+ *     partner tiles), when that form reads fewer partner tiles per tile
+ *     than the other reads partner rows per row;
+ *   RDM_APPLY_HOPS_ROWS: hop tables with 256-row tiles only;
+ *   RDM_APPLY_TRANSFORM: on 16..28 sites, H = D_Z + W D_X W + T W D_Y W T
  *     (W the Walsh-Hadamard transform, in whose basis XX couplings and
  *     x-fields are diagonal, D_X; YY couplings are T (XX) T with
  *     T = diag((-1)^floor(popcount(idx)/2)), D_Y), streamed in tiles;
  *     other sizes use hop tables;
  *   RDM_APPLY_AUTO (what rdm_hamiltonian_create does): the transform where
  *     available, unless a hop table would read fewer partner rows per row
- *     than the transform streams vectors (sparse operators with YY terms).
+ *     than the transform streams vectors (sparse operators with YY terms);
+ *     hop tables as under RDM_APPLY_HOPS otherwise.
  * rdm_hamiltonian_info reports the choice for H_t and H_b.  RDM_E_INVALID
  * for another value of apply. */
 rdm_status rdm_hamiltonian_create_ex(int32_t n_s, int32_t n_b, const rdm_coupling* couplings,
@@ -195,8 +202,11 @@ rdm_status rdm_energy_deviation(const rdm_hamiltonian* h, int32_t n_beta, const 
  * above a 256-row tile; the own tile plus every tile read by at least three
  * hops), [11] / [12] hops it gathers directly from memory instead, [13] /
  * [14] 1 when H_t / H_b is applied by the transform (rdm_hamiltonian_create_ex)
- * instead, [15] / [16] 1 when that transform has a YY part.
- * out: host array of 17 int64. */
+ * instead, [15] / [16] 1 when that transform has a YY part, [17] / [18] 1
+ * when the Lanczos steps with H_t / H_b take the 4096-row tiles of chosen
+ * row bits, [19] / [20] partner tiles one such tile reads (staged tiles other
+ * than its own plus hops gathered directly; 0 under 12 sites).
+ * out: host array of 21 int64. */
 rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* out);
 
 /* Full solve (blocking; results on the host).  beta: host array of n_beta

@@ -73,7 +73,7 @@ def make_options(precision="fp64", mode="auto", hbm_budget=0, slab=0, rows_per_l
     return o
 
 
-APPLY_KINDS = {"auto": 0, "hops": 1, "transform": 2}
+APPLY_KINDS = {"auto": 0, "hops": 1, "transform": 2, "hops_rows": 3}
 
 
 class Hamiltonian:
@@ -81,8 +81,10 @@ class Hamiltonian:
 
     couplings: iterable of (i, j, jx, jy, jz); hx, hz: coefficients of the
     one-site Pauli terms (length n_s + n_b).  apply: how products with H are
-    computed -- "auto", "hops" (hop-table gathers) or "transform" (the
-    Walsh-Hadamard form on 16..22 sites)."""
+    computed -- "auto", "hops" (hop-table gathers; the Lanczos steps take
+    4096-row tiles of chosen row bits where those read fewer partner tiles),
+    "hops_rows" (hop tables with 256-row tiles only) or "transform" (the
+    Walsh-Hadamard form on 16..28 sites)."""
 
     def __init__(self, n_s: int, n_b: int, couplings: Iterable, hx=None, hz=None, apply: str = "auto"):
         cps = list(couplings)
@@ -108,12 +110,13 @@ class Hamiltonian:
         return cls(inst.n_s, inst.n_b, inst.couplings, inst.hx, inst.hz, apply=apply)
 
     def info(self) -> dict:
-        out = (C.c_int64 * 17)()
+        out = (C.c_int64 * 21)()
         _check(LIB.rdm_hamiltonian_info(self.handle, out), "rdm_hamiltonian_info")
         keys = ["n", "n_s", "n_b", "hops_uniform", "hops_parity", "diag_terms",
                 "bath_hops_uniform", "bath_hops_parity", "bath_diag_terms", "tile_groups",
                 "bath_tile_groups", "direct_hops", "bath_direct_hops", "transform", "bath_transform",
-                "transform_yy", "bath_transform_yy"]
+                "transform_yy", "bath_transform_yy", "bitset_tiles", "bath_bitset_tiles",
+                "bitset_partners", "bath_bitset_partners"]
         return dict(zip(keys, list(out)))
 
     def system_matrix(self) -> np.ndarray:

@@ -16,7 +16,7 @@ RDM_E_CANCELLED = -6
 RDM_FP64, RDM_MIXED = 0, 1
 RDM_AUTO, RDM_STORED_Q, RDM_TWO_PASS = 0, 1, 2
 RDM_PER_COLUMN, RDM_BLOCK, RDM_METHOD_AUTO = 0, 1, 2
-RDM_APPLY_AUTO, RDM_APPLY_HOPS, RDM_APPLY_TRANSFORM = 0, 1, 2
+RDM_APPLY_AUTO, RDM_APPLY_HOPS, RDM_APPLY_TRANSFORM, RDM_APPLY_HOPS_ROWS = 0, 1, 2, 3
 DIAG_FIXED = 16
 NOALLOC_MAX_BYTES = 64 << 20  # RDM_NOALLOC_MAX_BYTES
 

@@ -15,6 +15,47 @@ thread_local std::string g_err;
 
 bool is_fin(double x) { return std::isfinite(x); }
 
+// the bits of x at the set bits of mask, packed to the low end (lowest first)
+uint32_t compress_bits(uint32_t x, uint32_t mask) {
+  uint32_t r = 0;
+  int k = 0;
+  for (int b = 0; b < 32; ++b)
+    if ((mask >> b) & 1u) {
+      if ((x >> b) & 1u) r |= 1u << k;
+      ++k;
+    }
+  return r;
+}
+
+// distinct nonzero partner-tile offsets f & ~B over the flip masks
+int distinct_partners(const std::vector<uint32_t>& flips, uint32_t B) {
+  std::vector<uint32_t> o;
+  for (uint32_t f : flips)
+    if (f & ~B) o.push_back(f & ~B);
+  std::sort(o.begin(), o.end());
+  return (int)(std::unique(o.begin(), o.end()) - o.begin());
+}
+
+// Tile bits B of the bit-set tiles: the kWideLowBits lowest row bits (256-byte
+// runs per 16 lanes), then one bit at a time the one that leaves the fewest
+// distinct partner tiles (the lowest such bit on ties), kWideBits in all.
+uint32_t choose_tile_bits(const std::vector<uint32_t>& flips, int nbits) {
+  uint32_t B = (1u << kWideLowBits) - 1u;
+  while (__builtin_popcount(B) < kWideBits) {
+    int best = -1, best_n = 0;
+    for (int b = kWideLowBits; b < nbits; ++b) {
+      if ((B >> b) & 1u) continue;
+      const int n = distinct_partners(flips, B | (1u << b));
+      if (best < 0 || n < best_n) {
+        best = b;
+        best_n = n;
+      }
+    }
+    B |= 1u << best;
+  }
+  return B;
+}
+
 // Compile the terms acting only on sites >= first_site (bath: first_site =
 // n_s) or all sites (first_site = 0).  Site s is bit (n-1-s) of the full
 // index; the bath operator uses the same bits (they are the low n_b bits).
@@ -146,6 +187,59 @@ void compile(const rdm_hamiltonian& h, int first_site, OpTables& t) {
     use = in_range && (any_y || xz_geom(t.nbits) == XG_SPLIT ? dense_enough : true);
   t.xz = use;
   t.xy = use && any_y;
+  // Bit-set tile form of the same hops (kWideBits sites and more): grouped by
+  // partner tile f & ~B; tiles read by at least kWideFat hops (and the own
+  // tile) are staged in LDS, the other hops gathered directly.  The Lanczos
+  // steps use it when it reads fewer partner tiles per tile than the 256-row
+  // form reads partner rows per row.
+  if (t.nbits >= kWideBits) {
+    std::vector<uint32_t> flips;
+    for (const H& x : all) flips.push_back(x.f);
+    const uint32_t B = choose_tile_bits(flips, t.nbits);
+    t.wbits = B;
+    std::vector<H> w = all;
+    for (H& x : w) x.kind = x.m == 0u ? 0 : ((x.m & B) == 0u ? 1 : 2);
+    std::stable_sort(w.begin(), w.end(), [&](const H& a, const H& b) {
+      const uint32_t ha = a.f & ~B, hb = b.f & ~B;
+      if (ha != hb) return ha < hb;
+      return a.kind < b.kind;
+    });
+    std::map<uint32_t, int> wuses;
+    for (const H& x : w) wuses[x.f & ~B] += 1;
+    t.wgroups.clear();
+    t.wgroups.push_back(HopGroup{0u, 0, 0, 0, 0, 0, {0, 0}});
+    std::vector<H> wthin[3];
+    for (const H& x : w) {
+      const uint32_t fo = x.f & ~B;
+      if (fo != 0u && wuses[fo] < kWideFat) {
+        wthin[x.kind].push_back(x);
+        continue;
+      }
+      if (fo != t.wgroups.back().fhi)
+        t.wgroups.push_back(HopGroup{fo, (int32_t)t.w_flo.size(), 0, 0, 0, 0, {0, 0}});
+      HopGroup& g = t.wgroups.back();
+      (x.kind == 0 ? g.n0 : x.kind == 1 ? g.n1 : g.n2) += 1;
+      t.w_flo.push_back(compress_bits(x.f & B, B));
+      t.w_m.push_back(x.m);
+      t.w_cs.push_back(x.cs);
+      t.w_cd.push_back(x.cd);
+    }
+    for (size_t g = 1; g < t.wgroups.size(); ++g) {
+      HopGroup& gr = t.wgroups[g];
+      gr.tile_uniform = gr.n0 == 0 && gr.n2 == 0 && gr.n1 > 0 ? 1 : 0;
+    }
+    for (int k = 0; k < 3; ++k) {
+      t.wnt[k] = (int)wthin[k].size();
+      for (const H& x : wthin[k]) {
+        t.wt_f.push_back(x.f);
+        t.wt_m.push_back(x.m);
+        t.wt_cs.push_back(x.cs);
+        t.wt_cd.push_back(x.cd);
+      }
+    }
+    const int wpartners = (int)(t.wgroups.size() - 1 + t.wt_f.size());
+    t.wide = !use && h.apply != RDM_APPLY_HOPS_ROWS && wpartners < partners;
+  }
   if (use) {
     t.xterms = xt;
     t.yterms = yt;
@@ -206,6 +300,26 @@ rdm_status upload(const OpTables& t, OpDevice& d, hipStream_t st) {
     RDM_HIP(launch_diag<T>((const DiagTerm*)d.yterms, (int)t.yterms.size(), (T*)d.dy, t.nbits, st,
                            xz_geom(t.nbits) == XG_DEEP));
   }
+  if (t.wide) {
+    std::vector<GHop<T>> wh(t.w_flo.size()), wt(t.wt_f.size());
+    for (size_t i = 0; i < wh.size(); ++i) wh[i] = GHop<T>{t.w_flo[i], t.w_m[i], (T)t.w_cs[i], (T)t.w_cd[i]};
+    for (size_t i = 0; i < wt.size(); ++i) wt[i] = GHop<T>{t.wt_f[i], t.wt_m[i], (T)t.wt_cs[i], (T)t.wt_cd[i]};
+    RDM_HIP(hipMalloc(&d.whops, std::max<size_t>(16, wh.size() * sizeof(GHop<T>))));
+    RDM_HIP(hipMalloc(&d.wgroups, std::max<size_t>(16, t.wgroups.size() * sizeof(HopGroup))));
+    RDM_HIP(hipMalloc(&d.wthin, std::max<size_t>(16, wt.size() * sizeof(GHop<T>))));
+    if (!wh.empty())
+      RDM_HIP(hipMemcpyAsync(d.whops, wh.data(), wh.size() * sizeof(GHop<T>), hipMemcpyHostToDevice, st));
+    RDM_HIP(hipMemcpyAsync(d.wgroups, t.wgroups.data(), t.wgroups.size() * sizeof(HopGroup),
+                           hipMemcpyHostToDevice, st));
+    if (!wt.empty())
+      RDM_HIP(hipMemcpyAsync(d.wthin, wt.data(), wt.size() * sizeof(GHop<T>), hipMemcpyHostToDevice, st));
+    // the host vectors above must outlive the copies
+    RDM_HIP(hipStreamSynchronize(st));
+    d.wngroups = (int)t.wgroups.size();
+    for (int k = 0; k < 3; ++k) d.wnt[k] = t.wnt[k];
+  }
+  d.wide = t.wide;
+  d.wbits = t.wbits;
   RDM_HIP(hipStreamSynchronize(st));
   d.ngroups = (int)t.groups.size();
   d.ready = true;
@@ -216,6 +330,9 @@ void free_dev(rdm::OpDevice& d) {
   if (d.hops) (void)hipFree(d.hops);
   if (d.groups) (void)hipFree(d.groups);
   if (d.thin) (void)hipFree(d.thin);
+  if (d.whops) (void)hipFree(d.whops);
+  if (d.wgroups) (void)hipFree(d.wgroups);
+  if (d.wthin) (void)hipFree(d.wthin);
   if (d.diag) (void)hipFree(d.diag);
   if (d.dx) (void)hipFree(d.dx);
   if (d.xterms) (void)hipFree(d.xterms);
@@ -282,8 +399,10 @@ extern "C" rdm_status rdm_hamiltonian_create_ex(int32_t n_s, int32_t n_b, const 
     return RDM_E_INVALID;
   }
   *out = nullptr;
-  if (apply != RDM_APPLY_AUTO && apply != RDM_APPLY_HOPS && apply != RDM_APPLY_TRANSFORM) {
-    set_error("rdm_hamiltonian_create_ex: apply must be RDM_APPLY_AUTO, RDM_APPLY_HOPS or RDM_APPLY_TRANSFORM");
+  if (apply != RDM_APPLY_AUTO && apply != RDM_APPLY_HOPS && apply != RDM_APPLY_TRANSFORM &&
+      apply != RDM_APPLY_HOPS_ROWS) {
+    set_error("rdm_hamiltonian_create_ex: apply must be RDM_APPLY_AUTO, RDM_APPLY_HOPS, RDM_APPLY_TRANSFORM "
+              "or RDM_APPLY_HOPS_ROWS");
     return RDM_E_INVALID;
   }
   if (n_s < 1 || n_s > 4 || n_b < 1 || n_s + n_b > 28) {
@@ -353,6 +472,9 @@ extern "C" rdm_status rdm_hamiltonian_info(const rdm_hamiltonian* h, int64_t* ou
     out[11 + w] = (int64_t)h->op[w].t_f.size();
     out[13 + w] = h->op[w].xz ? 1 : 0;
     out[15 + w] = h->op[w].xy ? 1 : 0;
+    out[17 + w] = h->op[w].wide ? 1 : 0;
+    out[19 + w] = h->op[w].wgroups.empty() ? 0
+                                            : (int64_t)(h->op[w].wgroups.size() - 1 + h->op[w].wt_f.size());
   }
   return RDM_OK;
 }

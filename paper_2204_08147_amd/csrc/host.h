@@ -49,6 +49,16 @@ struct OpTables {
   std::vector<uint32_t> t_f, t_m;
   std::vector<double> t_cs, t_cd;
   int nt[3] = {0, 0, 0};
+  // the same two forms for bit-set tiles (kWideBits sites and more): tile bits
+  // wbits; wide when the per-column Lanczos steps use them
+  bool wide = false;
+  uint32_t wbits = 0;
+  std::vector<uint32_t> w_flo, w_m;
+  std::vector<double> w_cs, w_cd;
+  std::vector<HopGroup> wgroups;
+  std::vector<uint32_t> wt_f, wt_m;
+  std::vector<double> wt_cs, wt_cd;
+  int wnt[3] = {0, 0, 0};
   // transform apply (kXzMinBits..kXzMaxBits bits): D_X terms (XX couplings
   // and x-fields) and D_Y terms (YY couplings), coefficients already scaled
   // by 2^-nbits; xy when there are D_Y terms
@@ -67,6 +77,14 @@ struct OpDevice {
   void* diag = nullptr;
   void* dterms = nullptr;
   int ngroups = 0;
+  // bit-set tile tables (wide operators)
+  bool wide = false;
+  uint32_t wbits = 0;
+  void* whops = nullptr;
+  void* wgroups = nullptr;
+  void* wthin = nullptr;
+  int wngroups = 0;
+  int wnt[3] = {0, 0, 0};
   bool xz = false, xy = false;
   void* dx = nullptr;      // D_X / 2^N (transform apply); strided-tile order above 20 bits
   void* dy = nullptr;      // D_Y / 2^N, same order (operators with YY couplings)

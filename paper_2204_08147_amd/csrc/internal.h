@@ -62,6 +62,17 @@ __host__ __device__ inline int xz_geom(int nbits) {
 }
 __host__ __device__ inline int xz_split_a(int nbits) { return (nbits - 12) / 2; }  // bits in group A
 constexpr int kFatGroup = 3;       // partner tiles read by at least this many hops go through LDS
+// Bit-set tiles (per-column Lanczos steps on hop-table operators of at least
+// kWideBits sites): a tile is the 2^kWideBits rows that differ only in a
+// chosen set B of row bits -- the four lowest always among them, so every 16
+// lanes read 256 contiguous bytes -- and agree with the tile's base in all
+// others.  A hop with flip bits f reads the partner tile base ^ (f & ~B); B is
+// chosen per operator so that few distinct partner tiles remain.
+constexpr int kWideBits = 12;
+constexpr int kWideBlock = 1024;   // lanes per workgroup
+constexpr int kWideRows = (1 << kWideBits) / kWideBlock;  // rows per lane
+constexpr int kWideLowBits = 4;    // bits 0..3 are always in B
+constexpr int kWideFat = 2;        // partner tiles read by at least two hops go through LDS
 
 // One off-diagonal term of H as the apply sees it: row idx couples to the
 // partner idx ^ f with coefficient c = (parity(idx & m) == 0) ? cs : cd.
@@ -76,7 +87,10 @@ struct alignas(16) GHop {
 };
 // Hops sharing one partner tile (same fhi), stored contiguously in three kinds:
 // n0 with m = 0, n1 whose tested bits are all >= 6 (the coefficient is uniform
-// over a wave of 64 consecutive rows), n2 with a per-row coefficient.
+// over a wave of 64 consecutive rows), n2 with a per-row coefficient.  In the
+// tables of bit-set tiles fhi = f & ~B, flo is the partner's tile index
+// offset (the bits of f & B compressed to B's positions), and the n1 hops
+// test no bit of B (the coefficient is uniform over the tile).
 struct HopGroup {
   uint32_t fhi;
   int32_t start;
@@ -124,6 +138,10 @@ struct Seg {
   int32_t x_base;      // transform apply: first workgroup of this segment
   int32_t xy;          // transform apply with a YY part (D_Y, the block Y)
   int32_t xdots;       // FP64 transform Lanczos: <u_j, r_j> from the XP_* planes
+  int32_t wide;        // 1: the apply takes bit-set tiles (hops / groups / thin and the
+                       // counts above are then the bit-set tables)
+  int32_t wp_base;     // first workgroup of this segment in a bit-set apply launch
+  uint32_t wbits;      // the row bits B that vary inside a bit-set tile
   const void* dx;      // transform apply: D_X / 2^N in T (tile order above 20 bits)
   const void* dy;      // transform apply: D_Y / 2^N in T, same order (xy segments)
   void* Y;             // xy segments: one block of dim x cpad for the YY part
@@ -215,6 +233,9 @@ template <typename T>
 hipError_t launch_norm(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
 template <typename T>
 hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStream_t st);
+// the apply over the wide segments: ntiles = sum of 2^(nbits - kWideBits) * P
+template <typename T>
+hipError_t launch_apply_wide(const Seg* segs, int nseg, int ntiles, hipStream_t st);
 // pass 0, 1 or 2 of the plain transform apply Y = H X (MODE_PLAIN segments
 // with xz = 1); passes 3 (once: X^ = W_lo X / 64 in place), 4 and 5 the same
 // product on blocks kept as X^, giving R = W_lo H X / 64; the strided pass

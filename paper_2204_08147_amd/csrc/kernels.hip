@@ -607,6 +607,241 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
 }
 
 // ---------------------------------------------------------------------------
+// apply on bit-set tiles (Seg::wide): the product and recurrence of k_apply
+// for the Lanczos steps of hop-table operators on kWideBits sites or more.
+//
+// A tile is the 2^kWideBits rows that differ only in the row bits B
+// (Seg::wbits) and agree with the tile's base in all other bits.  A workgroup
+// of kWideBlock lanes owns one tile of one panel; lane l holds the rows of
+// tile index t = l + kWideBlock q (q < kWideRows) at row base | deposit(t, B).
+// A hop with flip bits f maps tile index t to t ^ flo in the partner tile
+// base ^ fhi (fhi = f & ~B, flo = f & B packed to B's positions).  The hops
+// are grouped by fhi on the host, B chosen there to leave few distinct
+// partner tiles.  A group's partner tile is staged in LDS at slot t (16-byte
+// slots; the 8 lanes of a 128-byte phase read t ^ flo from one aligned group
+// of 8 slots, so there are no bank conflicts); the next group's tile is
+// loaded into registers while the current group's hops run.  The own tile
+// (the hops inside it) comes last, so the diagonal term and <u_j, r> read
+// the row's own value from LDS.  Hops whose partner tile no other hop reads
+// are gathered directly from memory.
+// ---------------------------------------------------------------------------
+// the low bits of x deposited at the set bits of mask, lowest first
+__device__ __forceinline__ uint32_t deposit_bits(uint32_t x, uint32_t mask) {
+  uint32_t r = 0;
+  for (uint32_t m = mask; m != 0u; m &= m - 1u, x >>= 1)
+    if (x & 1u) r |= m & (0u - m);
+  return r;
+}
+
+struct WTile {
+  int32_t seg;
+  uint32_t base;   // row bits outside B
+  int32_t panel;
+  int32_t tile;    // partial-sum row
+};
+
+// The tile of this workgroup: binary search of blockIdx.x in the segments'
+// wp_base offsets, then panel-major inside the segment (the workgroups in
+// flight share one panel, whose partner tiles the memory-side cache holds).
+// Workgroups go round-robin to the 8 XCDs; inside a panel the k-th workgroup
+// of each XCD takes consecutive tiles, so partner tiles whose bases differ in
+// low tile bits are read through that XCD's L2.  A bijection on the panel's
+// 2^(N - kWideBits) tiles (a multiple of 8 from N = kWideBits + 3 on).
+__device__ __forceinline__ WTile wide_tile_of(const Seg* segs, int nseg) {
+  const CONST_AS Seg* cs = (const CONST_AS Seg*)segs;
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cs[mid].wp_base <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int tb = cs[lo].nbits - kWideBits;
+  const int nt = 1 << tb;
+  const int lt = b - cs[lo].wp_base;
+  const int panel = lt >> tb;
+  int tile = lt & (nt - 1);
+  if (nt >= 8) tile = (tile & 7) * (nt >> 3) + (tile >> 3);
+  const uint32_t outside = ~cs[lo].wbits & ((1u << cs[lo].nbits) - 1u);
+  return WTile{lo, deposit_bits((uint32_t)tile, outside), panel, tile};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWideBlock) void k_apply_wide(const Seg* __restrict__ segs, int nseg) {
+  using V = typename PanelT<T>::V;
+  constexpr int W = PanelT<T>::W;
+  constexpr int R = kWideRows;
+  constexpr int NW = kWideBlock / 64;
+  __shared__ V tl[1 << kWideBits];
+  __shared__ double lds[NW * W];
+  const WTile t = wide_tile_of(segs, nseg);
+  const CONST_AS CSeg& sg = cseg(segs, t.seg);
+  const int j = sg.stepc[0];
+  if (j > sg.k) return;
+  const int cp = sg.cpad;
+  const uint64_t pstride = (uint64_t)1 << sg.nbits;
+  const V* ub = (const V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel * pstride;
+  const V* uprev = j > 1 ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel * pstride : nullptr;
+  V* out = (V*)sg.R + (uint64_t)t.panel * pstride;
+  const CONST_AS GHop<T>* hp = (const CONST_AS GHop<T>*)sg.hops;
+  const CONST_AS HopGroup* gr = (const CONST_AS HopGroup*)sg.groups;
+  const int ng = sg.ngroups;
+  const T* dg = (const T*)sg.diag;
+  const bool dots = sg.mode == MODE_LANCZOS;
+  const CONST_AS double* st = (const CONST_AS double*)sg.st;
+
+  const uint32_t B = sg.wbits;
+  const uint32_t lane = threadIdx.x;
+  const uint32_t lrow = t.base | deposit_bits(lane, B);
+  uint32_t row[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) row[q] = lrow | deposit_bits((uint32_t)(q * kWideBlock), B);
+
+  // next partner group (1 .. ng-1) that contributes to this tile: a
+  // tile-uniform group whose coefficients all vanish here is skipped (no
+  // load, no barrier); ng stands for the own tile (group 0), staged last so
+  // that its values are still in LDS for the diagonal and the dot products
+  auto next_active = [&](int g) -> int {
+    for (; g < ng; ++g) {
+      if (!gr[g].tile_uniform) return g;
+      const int h0 = gr[g].start, n1 = gr[g].n1;
+      for (int h = h0; h < h0 + n1; ++h) {
+        const T c = (__builtin_popcount(t.base & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
+        if (c != T(0)) return g;
+      }
+    }
+    return ng;
+  };
+
+  V acc[R], nx[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc[q][e] = T(0);
+  int g = next_active(1);
+  {
+    const uint32_t f = g < ng ? gr[g].fhi : 0u;
+#pragma unroll
+    for (int q = 0; q < R; ++q) nx[q] = ldg(ub, row[q] ^ f);
+  }
+  for (;;) {
+    const int cur = g < ng ? g : 0;
+    const int gn = g < ng ? next_active(g + 1) : -1;
+    __syncthreads();             // the previous group's reads of tl are done
+#pragma unroll
+    for (int q = 0; q < R; ++q) tl[lane + q * kWideBlock] = nx[q];
+    __syncthreads();
+    if (gn >= 0) {
+      const uint32_t f = gn < ng ? gr[gn].fhi : 0u;
+#pragma unroll
+      for (int q = 0; q < R; ++q) nx[q] = ldg(ub, row[q] ^ f);
+    }
+    const int h0 = gr[cur].start, e0 = h0 + gr[cur].n0, e1 = e0 + gr[cur].n1, e2 = e1 + gr[cur].n2;
+    int h = h0;
+    for (; h < e0; ++h) {        // m = 0
+      const uint32_t flo = hp[h].flo;
+      const T c = hp[h].cs;
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += c * tl[(lane + q * kWideBlock) ^ flo];
+    }
+    for (; h < e1; ++h) {        // coefficient uniform over the tile; zero ones skipped
+      const T c = (__builtin_popcount(t.base & hp[h].m) & 1u) ? hp[h].cd : hp[h].cs;
+      if (c == T(0)) continue;
+      const uint32_t flo = hp[h].flo;
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += c * tl[(lane + q * kWideBlock) ^ flo];
+    }
+    for (; h < e2; ++h) {        // per-row coefficient
+      const uint32_t flo = hp[h].flo, m = hp[h].m;
+      const T cs = hp[h].cs, cd = hp[h].cd;
+      V a[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) a[q] = tl[(lane + q * kWideBlock) ^ flo];
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += ((__builtin_popcount(row[q] & m) & 1u) ? cd : cs) * a[q];
+    }
+    if (gn < 0) break;
+    g = gn;
+  }
+
+  // hops whose partner tile no other hop reads: gathered directly
+  {
+    const CONST_AS GHop<T>* th = (const CONST_AS GHop<T>*)sg.thin;
+    const int e0 = sg.nt0, e1 = e0 + sg.nt1, e2 = e1 + sg.nt2;
+    int h = 0;
+    for (; h < e0; ++h) {
+      const uint32_t f = th[h].flo;
+      const T c = th[h].cs;
+      V x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += c * x[q];
+    }
+    for (; h < e1; ++h) {
+      const T c = (__builtin_popcount(t.base & th[h].m) & 1u) ? th[h].cd : th[h].cs;
+      if (c == T(0)) continue;
+      const uint32_t f = th[h].flo;
+      V x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += c * x[q];
+    }
+    for (; h < e2; ++h) {
+      const uint32_t f = th[h].flo, m = th[h].m;
+      const T cs = th[h].cs, cd = th[h].cd;
+      V x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += ((__builtin_popcount(row[q] & m) & 1u) ? cd : cs) * x[q];
+    }
+  }
+
+  double dq[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) dq[e] = 0.0;
+  V up[R];
+  if (uprev) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) up[q] = ldg_nt(uprev, row[q]);
+  }
+  const V sc = scur_of<T, 1>(st, cp, t.panel, 0, false);
+  const V bp = bps_of<T, 1>(st, cp, t.panel, 0);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const V x = tl[lane + q * kWideBlock];   // the own row, staged last
+    V r = sc * (acc[q] + ldg_s(dg, row[q]) * x);
+    if (uprev) {
+#pragma unroll
+      for (int e = 0; e < W; ++e) r[e] = fma_s(-bp[e], up[q][e], r[e]);
+    }
+    stg_stream<true>(out, row[q], r);
+    if (dots) {
+#pragma unroll
+      for (int e = 0; e < W; ++e) dq[e] += (double)x[e] * (double)r[e];
+    }
+  }
+  if (!dots) return;
+  // fixed-order sum over the workgroup's NW waves
+#pragma unroll
+  for (int e = 0; e < W; ++e) dq[e] = wave_sum(dq[e]);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int e = 0; e < W; ++e) lds[wave * W + e] = dq[e];
+  }
+  __syncthreads();
+  if (threadIdx.x < W) {
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tot += lds[w * W + threadIdx.x];
+    sg.part[(uint64_t)t.tile * cp + t.panel * W + threadIdx.x] = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Transform apply for operators whose off-diagonal part has only X-type terms
 // (XX couplings and x-fields, no YY): in the Hadamard basis such a term is
 // diagonal, so H = D_Z + W D_X W with W the unnormalised Walsh-Hadamard
@@ -1944,6 +2179,13 @@ hipError_t launch_apply(const Seg* segs, int nseg, int ntiles, int slab, hipStre
 }
 
 template <typename T>
+hipError_t launch_apply_wide(const Seg* segs, int nseg, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_apply_wide<T>), dim3(ntiles), dim3(kWideBlock), 0, st, segs, nseg);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_xz_split(int op, const Seg* segs, int nseg, int ntiles, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 g(ntiles), b(kBlock);
@@ -2116,6 +2358,8 @@ template hipError_t launch_norm<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_norm<double>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<float>(const Seg*, int, int, int, hipStream_t);
 template hipError_t launch_apply<double>(const Seg*, int, int, int, hipStream_t);
+template hipError_t launch_apply_wide<float>(const Seg*, int, int, hipStream_t);
+template hipError_t launch_apply_wide<double>(const Seg*, int, int, hipStream_t);
 template hipError_t launch_xz_pass<float>(int, const Seg*, int, int, hipStream_t, int);
 template hipError_t launch_xz_split<float>(int, const Seg*, int, int, hipStream_t);
 template hipError_t launch_xz_split<double>(int, const Seg*, int, int, hipStream_t);

@@ -223,7 +223,7 @@ Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int sta
   Seg s{};
   s.nbits = g.nbits;
   s.n_row_tiles = g.n_row_tiles;
-  bind_apply(s, op);
+  bind_apply(s, op, mode != MODE_PLAIN);
   // FP64 transform steps assemble <u_j, r_j> from XP_COUNT planes of x_tiles
   // rows each (n_row_tiles = dim / 256 rows leave room for them)
   static_assert(XP_COUNT * kBlock <= (1 << kXzTileBits), "partial-sum planes exceed the part buffer");
@@ -349,7 +349,7 @@ int common_slab(std::vector<Seg>& segs) {
   return slab;
 }
 
-void bind_apply(Seg& s, const OpDevice* op) {
+void bind_apply(Seg& s, const OpDevice* op, bool lanczos) {
   s.hops = op->hops;
   s.groups = op->groups;
   s.thin = op->thin;
@@ -365,19 +365,38 @@ void bind_apply(Seg& s, const OpDevice* op) {
   s.x_tiles = op->xz ? 1 << (s.nbits - kXzTileBits) : 0;
   s.ap_rows = op->xz ? s.x_tiles : s.n_row_tiles;
   s.nm_rows = s.ap_rows;
+  s.wide = 0;
+  s.wbits = 0;
+  if (lanczos && op->wide && !op->xz && s.nbits >= kWideBits) {
+    // the Lanczos apply on bit-set tiles: their tables, one partial-sum row
+    // per tile (the norm step keeps its 256-row tiles)
+    s.wide = 1;
+    s.wbits = op->wbits;
+    s.hops = op->whops;
+    s.groups = op->wgroups;
+    s.thin = op->wthin;
+    s.ngroups = op->wngroups;
+    s.nt0 = op->wnt[0];
+    s.nt1 = op->wnt[1];
+    s.nt2 = op->wnt[2];
+    s.ap_rows = 1 << (s.nbits - kWideBits);
+  }
 }
 
 Launch assign_tiles(std::vector<Seg>& segs) {
-  // the norm and apply launches cover the hop-table segments, the transform
-  // passes the others (pass 1 doing their norm step).  Segments of
-  // the other kind get no workgroups (their base is the running count, which
-  // the kernels' binary search never resolves to them).
+  // the norm launch covers the hop-table segments, the apply launch those of
+  // them on 256-row tiles and the bit-set apply launch the others, the
+  // transform passes the rest (pass 1 doing their norm step).  Segments
+  // outside a launch get no workgroups in it (their base is the running
+  // count, which the kernels' binary search never resolves to them).
   Launch L;
   for (auto& sg : segs) {
     sg.tile_base = L.norm;
     if (!sg.xz) L.norm += sg.n_row_tiles * (sg.P / sg.S);
     sg.ap_base = L.apply;
-    if (!sg.xz) L.apply += sg.n_row_tiles * (sg.P / sg.S);
+    if (!sg.xz && !sg.wide) L.apply += sg.n_row_tiles * (sg.P / sg.S);
+    sg.wp_base = L.wide;
+    if (sg.wide) L.wide += (1 << (sg.nbits - kWideBits)) * sg.P;
     sg.x_base = L.xz;
     if (sg.xz) {
       L.xz += sg.x_tiles * sg.P;
@@ -435,6 +454,7 @@ rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, in
   if (tm) RDM_HIP(tm->apply.mark(st));
   RDM_HIP(d ? launch_apply<double>(dsegs, nseg, L.apply, slab, st)
             : launch_apply<float>(dsegs, nseg, L.apply, slab, st));
+  RDM_HIP(d ? launch_apply_wide<double>(dsegs, nseg, L.wide, st) : launch_apply_wide<float>(dsegs, nseg, L.wide, st));
   RDM_HIP(d ? launch_xz_lanczos<double>(2, false, dsegs, nseg, L.xz, 0, st)
             : launch_xz_lanczos<float>(2, false, dsegs, nseg, L.xz, 0, st));
   if (tm) RDM_HIP(tm->apply.mark(st));
@@ -621,12 +641,12 @@ namespace {
 struct GraphKey {
   int device;
   const void* dsegs;
-  int nseg, norm, apply, xz, slab, cmax, prec, nsteps;
+  int nseg, norm, apply, wide, xz, slab, cmax, prec, nsteps;
   int variants;  // bit (3 * regen + geometry) set when that strided variant runs, bit
                  // (6 + geometry) when that YY strided variant runs
   bool operator<(const GraphKey& o) const {
-    return std::tie(device, dsegs, nseg, norm, apply, xz, slab, cmax, prec, nsteps, variants) <
-           std::tie(o.device, o.dsegs, o.nseg, o.norm, o.apply, o.xz, o.slab, o.cmax, o.prec, o.nsteps,
+    return std::tie(device, dsegs, nseg, norm, apply, wide, xz, slab, cmax, prec, nsteps, variants) <
+           std::tie(o.device, o.dsegs, o.nseg, o.norm, o.apply, o.wide, o.xz, o.slab, o.cmax, o.prec, o.nsteps,
                     o.variants);
   }
 };
@@ -693,7 +713,7 @@ rdm_status graph_steps_locked(int prec, Seg* dsegs, int nseg, const Launch& L, i
   } else {
     gs = its->second;
   }
-  const GraphKey key{dev, dsegs, nseg, L.norm, L.apply, L.xz, slab, cmax, prec, nsteps, launch_variants(L)};
+  const GraphKey key{dev, dsegs, nseg, L.norm, L.apply, L.wide, L.xz, slab, cmax, prec, nsteps, launch_variants(L)};
   hipGraphExec_t exec = nullptr;
   auto it = g_graphs.find(key);
   if (it != g_graphs.end()) {

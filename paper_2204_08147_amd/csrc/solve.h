@@ -118,10 +118,13 @@ Seg seg_of(const InstRun& r, int which, int mode, double tau);
 int common_slab(std::vector<Seg>& segs);
 // Operator tables of a segment's apply (hop tables or transform).  Needs
 // nbits and n_row_tiles set.
-void bind_apply(Seg& s, const OpDevice* op);
-// workgroups of the norm launch and of the two kinds of apply launch
+// lanczos: the segment runs Lanczos steps (not MODE_PLAIN), so a wide
+// operator's apply may take its bit-set tiles
+void bind_apply(Seg& s, const OpDevice* op, bool lanczos = false);
+// workgroups of the norm launch and of the three kinds of apply launch
 struct Launch {
   int norm = 0, apply = 0, xz = 0;
+  int wide = 0;  // workgroups of the apply on bit-set tiles
   // transform segments in each mode, by strided geometry (XG_SHALLOW,
   // XG_DEEP, XG_SPLIT); xy: those with a YY part
   bool xz_lanczos[3] = {false, false, false}, xz_regen[3] = {false, false, false};
@@ -129,7 +132,7 @@ struct Launch {
   bool any_xy() const { return xy[0] || xy[1] || xy[2]; }
   bool any_split() const { return xz_lanczos[XG_SPLIT] || xz_regen[XG_SPLIT]; }
 };
-// sets every segment's tile_base / ap_base / x_base
+// sets every segment's tile_base / ap_base / wp_base / x_base
 Launch assign_tiles(std::vector<Seg>& segs);
 rdm_status launch_step(int prec, const Seg* dsegs, int nseg, const Launch& L, int slab, int cmax, hipStream_t st,
                        StepTimers* tm);

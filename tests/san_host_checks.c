@@ -38,7 +38,7 @@ static int hamiltonians(void) {
     for (int kind = RDM_APPLY_AUTO; kind <= RDM_APPLY_TRANSFORM; ++kind) {
       rdm_hamiltonian* h = NULL;
       CHECK(rdm_hamiltonian_create_ex(n_s, n_b, cps, nc, hx, hz, kind, &h) == RDM_OK);
-      int64_t info[17];
+      int64_t info[21];
       CHECK(rdm_hamiltonian_info(h, info) == RDM_OK && info[0] == n);
       int ds = 1 << n_s;
       double* m = malloc(sizeof(double) * ds * ds);

@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from oracle import lanczos as olz
-from workloads import long_range_xxz, cfg_long_range, cfg_small_chain, nn_xxz_chain, random_dense_terms
+from workloads import (long_range_xxz, cfg_long_range, cfg_small_chain, nn_xxz_chain, random_dense_terms,
+                       random_sparse_xxz, tfim_request)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 rdm = pytest.importorskip("paper_2204_08147_amd")
@@ -95,6 +96,31 @@ def test_transform_apply_selection():
     assert xonly["transform_yy"] == 0
     out = rdm.C.c_void_p()
     assert rdm.LIB.rdm_hamiltonian_create_ex(1, 3, None, 0, None, None, 7, rdm.C.byref(out)) == -1
+    assert rdm.LIB.rdm_hamiltonian_create_ex(1, 3, None, 0, None, None, 4, rdm.C.byref(out)) == -1
+
+
+def test_bitset_tile_selection():
+    # hop-table operators on 12 sites and more: the Lanczos steps take tiles of
+    # 4096 rows over 12 chosen row bits when those read fewer partner tiles
+    # per tile than the 256-row tiles read partner rows per row
+    sparse = random_sparse_xxz(3001, n_range=(22, 22), n_v=1, k=30)    # degree 4, 22 sites
+    i = rdm.Hamiltonian.from_instance(sparse).info()
+    assert i["transform"] == 0 and i["bitset_tiles"] == 1 and i["bath_bitset_tiles"] == 1
+    assert 0 < i["bitset_partners"] < (i["tile_groups"] - 1 + i["direct_hops"]) / 2
+    rows = rdm.Hamiltonian.from_instance(sparse, apply="hops_rows").info()
+    assert rows["transform"] == 0 and rows["bitset_tiles"] == 0 and rows["bath_bitset_tiles"] == 0
+    assert rows["tile_groups"] == i["tile_groups"] and rows["direct_hops"] == i["direct_hops"]
+    # a transverse-field chain: one partner tile per site outside the tile bits
+    tfim = rdm.Hamiltonian.from_instance(tfim_request(3, n_range=(24, 24))).info()
+    assert tfim["bitset_tiles"] == 1 and tfim["bitset_partners"] == 24 - 12
+    # exactly 12 sites: one tile holds the whole vector
+    twelve = rdm.Hamiltonian.from_instance(random_sparse_xxz(3011, n_range=(12, 12))).info()
+    assert twelve["n"] == 12 and twelve["bitset_tiles"] == 1 and twelve["bitset_partners"] == 0
+    # under 12 sites, and for operators on the transform apply: no bit-set tiles
+    small = rdm.Hamiltonian.from_instance(cfg_small_chain()).info()
+    assert small["bitset_tiles"] == 0 and small["bitset_partners"] == 0
+    xz = rdm.Hamiltonian.from_instance(cfg_long_range(0)).info()
+    assert xz["transform"] == 1 and xz["bitset_tiles"] == 0 and xz["bath_bitset_tiles"] == 0
 
 
 @pytest.mark.parametrize("bad", [

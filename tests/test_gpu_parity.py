@@ -271,6 +271,13 @@ SOLVE_CASES = {
     # tables and on the transform apply
     "random_4+6": lambda: random_dense_terms(4, 6, 93, betas=(0.4, 2.0), n_v=2, k=30),
     "xz_4+12": lambda: long_range_xx_zz(4, 12, 1.0, 95, betas=(1.0,), n_v=1, k=30),
+    # hop tables on bit-set tiles (4096 rows over 12 chosen row bits, partner
+    # tiles outside them): sparse XXZ (per-row and tile-uniform coefficients,
+    # the latter skipped where they vanish), a transverse-field chain
+    # (constant coefficients), every term type at random
+    "sparse_16": lambda: random_sparse_xxz(3021, n_range=(16, 16), n_v=1, k=30),
+    "tfim_15": lambda: tfim_request(21, n_range=(15, 15), n_v=2, k=30),
+    "dense_2+13": lambda: random_dense_terms(2, 13, 97, density=0.3, n_v=2, k=30),
 }
 
 # cases that exercise an apply kind other than the default
@@ -631,7 +638,7 @@ def test_k_capped_at_dimension():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_equals_solo(prec):
     insts = [SOLVE_CASES[n]() for n in ("chain_1+9", "random_2+6", "xz_2+14", "random_3+5", "lr_2+9",
-                                        "sparse", "random_4+6")]
+                                        "sparse", "random_4+6", "sparse_16", "tfim_15")]
     hs = [H(i) for i in insts]
     items = [dict(h=h, betas=i.betas, n_v=i.n_v, k=i.k, seed=i.seed) for h, i in zip(hs, insts)]
     batch = rdm.solve_batch(items, precision=prec)
@@ -1006,6 +1013,39 @@ def test_transform_beyond_20_bits_matches_hop_tables(name):
     check_result(a, want, 1e-10, "transform vs hop tables " + name)
     m = rdm.solve(h, inst.betas, inst.n_v, inst.k, inst.seed, precision="mixed")
     check_result(m, want, 1e-5, "mixed transform vs FP64 hop tables " + name)
+
+
+BITSET_CASES = {
+    # a batch instance at the batch's largest size (22 sites, degree 4)
+    "sparse_22": lambda: random_sparse_xxz(3001, n_range=(22, 22), n_v=1, k=30),
+    # the transverse-field chain at 24 sites (single-bit flips)
+    "tfim_24": lambda: tfim_request(3, n_range=(24, 24), n_v=1, k=16),
+    # all-pairs couplings from hop tables: many hops per staged partner tile
+    "lr_1+20": lambda: long_range_xx_zz(1, 20, 1.0, 81, betas=(0.5, 2.0), n_v=2, k=30),
+}
+
+
+@pytest.mark.parametrize("name", list(BITSET_CASES))
+def test_bitset_tiles_match_row_tiles(name):
+    # the Lanczos steps on bit-set tiles against the 256-row tiles (row-checked
+    # against the oracle in the apply tests) at full size; the regeneration
+    # pass and the eager launches repeat the graph-replayed stored run bit for bit
+    inst = BITSET_CASES[name]()
+    hw, hr = HH(inst), rdm.Hamiltonian.from_instance(inst, apply="hops_rows")
+    assert hw.info()["bitset_tiles"] == 1 and hr.info()["bitset_tiles"] == 0
+    args = (inst.betas, inst.n_v, inst.k, inst.seed)
+    b = rdm.solve(hr, *args, precision="fp64")
+    want = [{key: b[key][t] for key in ("rho", "h_star", "log_z", "entropy")} for t in range(len(inst.betas))]
+    a = rdm.solve(hw, *args, precision="fp64")
+    check_result(a, want, 1e-10, "bit-set vs row tiles " + name)
+    m = rdm.solve(hw, *args, precision="mixed", mode="stored")
+    check_result(m, want, 1e-5, "mixed bit-set vs FP64 row tiles " + name)
+    m2 = rdm.solve(hw, *args, precision="mixed", mode="two_pass")
+    me = rdm.solve(hw, *args, precision="mixed", mode="stored", eager=True)
+    assert m2["two_pass"] and not m["two_pass"]
+    for key in ("rho", "h_star", "log_z", "entropy"):
+        assert np.array_equal(m[key], m2[key]), key
+        assert np.array_equal(m[key], me[key]), key
 
 
 SPLIT_CASES = {
