@@ -69,8 +69,8 @@ constexpr int kFatGroup = 3;       // partner tiles read by at least this many h
 // others.  A hop with flip bits f reads the partner tile base ^ (f & ~B); B is
 // chosen per operator so that few distinct partner tiles remain.
 constexpr int kWideBits = 12;
-constexpr int kWideBlock = 1024;   // lanes per workgroup
-constexpr int kWideRows = (1 << kWideBits) / kWideBlock;  // rows per lane
+constexpr int kWideRows = 4;       // rows per lane
+constexpr int kWideBlock = (1 << kWideBits) / kWideRows;  // lanes per workgroup
 constexpr int kWideLowBits = 4;    // bits 0..3 are always in B
 constexpr int kWideFat = 2;        // partner tiles read by at least two hops go through LDS
 

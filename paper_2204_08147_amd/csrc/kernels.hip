@@ -693,9 +693,21 @@ __global__ __launch_bounds__(kWideBlock) void k_apply_wide(const Seg* __restrict
   const uint32_t B = sg.wbits;
   const uint32_t lane = threadIdx.x;
   const uint32_t lrow = t.base | deposit_bits(lane, B);
-  uint32_t row[R];
+  // row q of the lane = lrow | dep[q]; dep[q] is uniform, so a per-row
+  // coefficient parity(row & m) is parity(lrow & m) (per lane, once per hop)
+  // flipped by the uniform parity(dep[q] & m)
+  uint32_t dep[R], row[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) row[q] = lrow | deposit_bits((uint32_t)(q * kWideBlock), B);
+  for (int q = 0; q < R; ++q) {
+    dep[q] = deposit_bits((uint32_t)(q * kWideBlock), B);
+    row[q] = lrow | dep[q];
+  }
+  auto row_coefs = [&](uint32_t m, T cs, T cd, T (&c)[R]) {
+    const bool p0 = __builtin_popcount(lrow & m) & 1u;
+    const T ca = p0 ? cd : cs, cb = p0 ? cs : cd;
+#pragma unroll
+    for (int q = 0; q < R; ++q) c[q] = (__builtin_popcount(dep[q] & m) & 1u) ? cb : ca;
+  };
 
   // next partner group (1 .. ng-1) that contributes to this tile: a
   // tile-uniform group whose coefficients all vanish here is skipped (no
@@ -724,6 +736,61 @@ __global__ __launch_bounds__(kWideBlock) void k_apply_wide(const Seg* __restrict
 #pragma unroll
     for (int q = 0; q < R; ++q) nx[q] = ldg(ub, row[q] ^ f);
   }
+
+  // hops whose partner tile no other hop reads: gathered directly, two hops
+  // (2R loads) in flight, while the first staged tile is on its way
+  {
+    const CONST_AS GHop<T>* th = (const CONST_AS GHop<T>*)sg.thin;
+    const int e0 = sg.nt0, e1 = e0 + sg.nt1, e2 = e1 + sg.nt2;
+    int h = 0;
+    for (; h < e0; ++h) {
+      const uint32_t f = th[h].flo;
+      const T c = th[h].cs;
+      V x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += c * x[q];
+    }
+    for (; h < e1; ++h) {
+      const T c = (__builtin_popcount(t.base & th[h].m) & 1u) ? th[h].cd : th[h].cs;
+      if (c == T(0)) continue;
+      const uint32_t f = th[h].flo;
+      V x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += c * x[q];
+    }
+    for (; h + 2 <= e2; h += 2) {
+      const uint32_t f0 = th[h].flo, f1 = th[h + 1].flo;
+      V x0[R], x1[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        x0[q] = ldg(ub, row[q] ^ f0);
+        x1[q] = ldg(ub, row[q] ^ f1);
+      }
+      T c0[R], c1[R];
+      row_coefs(th[h].m, th[h].cs, th[h].cd, c0);
+      row_coefs(th[h + 1].m, th[h + 1].cs, th[h + 1].cd, c1);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        acc[q] += c0[q] * x0[q];
+        acc[q] += c1[q] * x1[q];
+      }
+    }
+    if (h < e2) {
+      const uint32_t f = th[h].flo;
+      V x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
+      T c[R];
+      row_coefs(th[h].m, th[h].cs, th[h].cd, c);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += c[q] * x[q];
+    }
+  }
+
   for (;;) {
     const int cur = g < ng ? g : 0;
     const int gn = g < ng ? next_active(g + 1) : -1;
@@ -752,51 +819,17 @@ __global__ __launch_bounds__(kWideBlock) void k_apply_wide(const Seg* __restrict
       for (int q = 0; q < R; ++q) acc[q] += c * tl[(lane + q * kWideBlock) ^ flo];
     }
     for (; h < e2; ++h) {        // per-row coefficient
-      const uint32_t flo = hp[h].flo, m = hp[h].m;
-      const T cs = hp[h].cs, cd = hp[h].cd;
+      const uint32_t flo = hp[h].flo;
       V a[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) a[q] = tl[(lane + q * kWideBlock) ^ flo];
+      T c[R];
+      row_coefs(hp[h].m, hp[h].cs, hp[h].cd, c);
 #pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += ((__builtin_popcount(row[q] & m) & 1u) ? cd : cs) * a[q];
+      for (int q = 0; q < R; ++q) acc[q] += c[q] * a[q];
     }
     if (gn < 0) break;
     g = gn;
-  }
-
-  // hops whose partner tile no other hop reads: gathered directly
-  {
-    const CONST_AS GHop<T>* th = (const CONST_AS GHop<T>*)sg.thin;
-    const int e0 = sg.nt0, e1 = e0 + sg.nt1, e2 = e1 + sg.nt2;
-    int h = 0;
-    for (; h < e0; ++h) {
-      const uint32_t f = th[h].flo;
-      const T c = th[h].cs;
-      V x[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
-#pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += c * x[q];
-    }
-    for (; h < e1; ++h) {
-      const T c = (__builtin_popcount(t.base & th[h].m) & 1u) ? th[h].cd : th[h].cs;
-      if (c == T(0)) continue;
-      const uint32_t f = th[h].flo;
-      V x[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
-#pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += c * x[q];
-    }
-    for (; h < e2; ++h) {
-      const uint32_t f = th[h].flo, m = th[h].m;
-      const T cs = th[h].cs, cd = th[h].cd;
-      V x[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) x[q] = ldg(ub, row[q] ^ f);
-#pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += ((__builtin_popcount(row[q] & m) & 1u) ? cd : cs) * x[q];
-    }
   }
 
   double dq[W];
