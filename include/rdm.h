@@ -155,8 +155,8 @@ rdm_status rdm_hamiltonian_create(int32_t n_s, int32_t n_b, const rdm_coupling* 
 /* As rdm_hamiltonian_create, choosing how products with H_t and H_b are
  * computed (the results agree to rounding either way):
  *   RDM_APPLY_HOPS: gathers of the partner rows idx ^ f from hop tables.
- *     Tiles of 256 consecutive rows, or, for the Lanczos steps on 12 sites
- *     and more, tiles of the 4096 rows that differ only in 12 row bits chosen
+ *     Tiles of 256 consecutive rows, or, on 12 sites and more, tiles of
+ *     the 4096 rows that differ only in 12 row bits chosen
  *     per operator (the 4 lowest and those that leave the fewest distinct
  *     partner tiles), when that form reads fewer partner tiles per tile
  *     than the other reads partner rows per row;
@@ -203,7 +203,7 @@ rdm_status rdm_energy_deviation(const rdm_hamiltonian* h, int32_t n_beta, const 
  * hops), [11] / [12] hops it gathers directly from memory instead, [13] /
  * [14] 1 when H_t / H_b is applied by the transform (rdm_hamiltonian_create_ex)
  * instead, [15] / [16] 1 when that transform has a YY part, [17] / [18] 1
- * when the Lanczos steps with H_t / H_b take the 4096-row tiles of chosen
+ * when products with H_t / H_b take the 4096-row tiles of chosen
  * row bits, [19] / [20] partner tiles one such tile reads (staged tiles other
  * than its own plus hops gathered directly; 0 under 12 sites).
  * out: host array of 21 int64. */

@@ -81,8 +81,8 @@ class Hamiltonian:
 
     couplings: iterable of (i, j, jx, jy, jz); hx, hz: coefficients of the
     one-site Pauli terms (length n_s + n_b).  apply: how products with H are
-    computed -- "auto", "hops" (hop-table gathers; the Lanczos steps take
-    4096-row tiles of chosen row bits where those read fewer partner tiles),
+    computed -- "auto", "hops" (hop-table gathers; 4096-row tiles of chosen
+    row bits where those read fewer partner tiles),
     "hops_rows" (hop tables with 256-row tiles only) or "transform" (the
     Walsh-Hadamard form on 16..28 sites)."""
 

@@ -496,6 +496,8 @@ extern "C" rdm_status rdm_apply(const rdm_hamiltonian* h, int32_t which, int32_t
                                       : launch_xz_pass<float>(pass, (Seg*)d, 1, L.xz, st, deep));
     RDM_HIP(precision == RDM_FP64 ? launch_apply<double>((Seg*)d, 1, L.apply, g.S, st)
                                   : launch_apply<float>((Seg*)d, 1, L.apply, g.S, st));
+    RDM_HIP(precision == RDM_FP64 ? launch_apply_wide<double>((Seg*)d, 1, L.wide, st)
+                                  : launch_apply_wide<float>((Seg*)d, 1, L.wide, st));
     RDM_HIP(hipStreamSynchronize(st));
     return RDM_OK;
   };

@@ -150,6 +150,7 @@ rdm_status run_block(const BlockPlan& bp, const OpDevice* op_t, char* ws, char* 
     const Seg* sj = dsegs + (j - 1) % 3;
     if (tm) RDM_HIP(tm->apply.mark(st));
     RDM_HIP(launch_apply<T>(sj, 1, L.apply, 1, st));
+    RDM_HIP(launch_apply_wide<T>(sj, 1, L.wide, st));
     if (op_t->xz)
       for (int pass = 4; pass <= 5; ++pass) RDM_HIP(launch_xz_pass<T>(pass, sj, 1, L.xz, st, deep));
     if (op_t->xz && op_t->xy)

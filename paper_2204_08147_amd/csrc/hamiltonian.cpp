@@ -189,9 +189,9 @@ void compile(const rdm_hamiltonian& h, int first_site, OpTables& t) {
   t.xy = use && any_y;
   // Bit-set tile form of the same hops (kWideBits sites and more): grouped by
   // partner tile f & ~B; tiles read by at least kWideFat hops (and the own
-  // tile) are staged in LDS, the other hops gathered directly.  The Lanczos
-  // steps use it when it reads fewer partner tiles per tile than the 256-row
-  // form reads partner rows per row.
+  // tile) are staged in LDS, the other hops gathered directly.  Products use
+  // it when it reads fewer partner tiles per tile than the 256-row form reads
+  // partner rows per row.
   if (t.nbits >= kWideBits) {
     std::vector<uint32_t> flips;
     for (const H& x : all) flips.push_back(x.f);

@@ -607,8 +607,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Seg* __restrict__ segs, 
 }
 
 // ---------------------------------------------------------------------------
-// apply on bit-set tiles (Seg::wide): the product and recurrence of k_apply
-// for the Lanczos steps of hop-table operators on kWideBits sites or more.
+// apply on bit-set tiles (Seg::wide): the product (MODE_PLAIN) or product and
+// recurrence of k_apply for hop-table operators on kWideBits sites or more.
 //
 // A tile is the 2^kWideBits rows that differ only in the row bits B
 // (Seg::wbits) and agree with the tile's base in all other bits.  A workgroup
@@ -676,12 +676,17 @@ __global__ __launch_bounds__(kWideBlock) void k_apply_wide(const Seg* __restrict
   __shared__ double lds[NW * W];
   const WTile t = wide_tile_of(segs, nseg);
   const CONST_AS CSeg& sg = cseg(segs, t.seg);
-  const int j = sg.stepc[0];
-  if (j > sg.k) return;
+  const bool plain = sg.mode == MODE_PLAIN;
+  int j = 1;
+  if (!plain) {
+    j = sg.stepc[0];
+    if (j > sg.k) return;
+  }
   const int cp = sg.cpad;
   const uint64_t pstride = (uint64_t)1 << sg.nbits;
-  const V* ub = (const V*)slot_ptr<T>(sg, j) + (uint64_t)t.panel * pstride;
-  const V* uprev = j > 1 ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel * pstride : nullptr;
+  const V* ub = (plain ? (const V*)sg.Q : (const V*)slot_ptr<T>(sg, j)) + (uint64_t)t.panel * pstride;
+  const V* uprev = (!plain && j > 1) ? (const V*)slot_ptr<T>(sg, j - 1) + (uint64_t)t.panel * pstride
+                                     : nullptr;
   V* out = (V*)sg.R + (uint64_t)t.panel * pstride;
   const CONST_AS GHop<T>* hp = (const CONST_AS GHop<T>*)sg.hops;
   const CONST_AS HopGroup* gr = (const CONST_AS HopGroup*)sg.groups;
@@ -840,8 +845,9 @@ __global__ __launch_bounds__(kWideBlock) void k_apply_wide(const Seg* __restrict
 #pragma unroll
     for (int q = 0; q < R; ++q) up[q] = ldg_nt(uprev, row[q]);
   }
-  const V sc = scur_of<T, 1>(st, cp, t.panel, 0, false);
-  const V bp = bps_of<T, 1>(st, cp, t.panel, 0);
+  const V sc = scur_of<T, 1>(st, cp, t.panel, 0, plain);
+  V bp;
+  if (uprev) bp = bps_of<T, 1>(st, cp, t.panel, 0);
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const V x = tl[lane + q * kWideBlock];   // the own row, staged last

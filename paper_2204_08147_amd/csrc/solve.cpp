@@ -223,7 +223,7 @@ Seg make_seg(const SegPlan& g, const OpDevice* op, char* base, int mode, int sta
   Seg s{};
   s.nbits = g.nbits;
   s.n_row_tiles = g.n_row_tiles;
-  bind_apply(s, op, mode != MODE_PLAIN);
+  bind_apply(s, op);
   // FP64 transform steps assemble <u_j, r_j> from XP_COUNT planes of x_tiles
   // rows each (n_row_tiles = dim / 256 rows leave room for them)
   static_assert(XP_COUNT * kBlock <= (1 << kXzTileBits), "partial-sum planes exceed the part buffer");
@@ -349,7 +349,7 @@ int common_slab(std::vector<Seg>& segs) {
   return slab;
 }
 
-void bind_apply(Seg& s, const OpDevice* op, bool lanczos) {
+void bind_apply(Seg& s, const OpDevice* op) {
   s.hops = op->hops;
   s.groups = op->groups;
   s.thin = op->thin;
@@ -367,9 +367,9 @@ void bind_apply(Seg& s, const OpDevice* op, bool lanczos) {
   s.nm_rows = s.ap_rows;
   s.wide = 0;
   s.wbits = 0;
-  if (lanczos && op->wide && !op->xz && s.nbits >= kWideBits) {
-    // the Lanczos apply on bit-set tiles: their tables, one partial-sum row
-    // per tile (the norm step keeps its 256-row tiles)
+  if (op->wide && !op->xz && s.nbits >= kWideBits) {
+    // the apply on bit-set tiles: their tables, one partial-sum row per tile
+    // (the norm step keeps its 256-row tiles)
     s.wide = 1;
     s.wbits = op->wbits;
     s.hops = op->whops;

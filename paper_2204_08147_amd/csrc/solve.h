@@ -118,9 +118,8 @@ Seg seg_of(const InstRun& r, int which, int mode, double tau);
 int common_slab(std::vector<Seg>& segs);
 // Operator tables of a segment's apply (hop tables or transform).  Needs
 // nbits and n_row_tiles set.
-// lanczos: the segment runs Lanczos steps (not MODE_PLAIN), so a wide
-// operator's apply may take its bit-set tiles
-void bind_apply(Seg& s, const OpDevice* op, bool lanczos = false);
+// A wide operator's segment takes the bit-set tables (Seg::wide).
+void bind_apply(Seg& s, const OpDevice* op);
 // workgroups of the norm launch and of the three kinds of apply launch
 struct Launch {
   int norm = 0, apply = 0, xz = 0;

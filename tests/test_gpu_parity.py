@@ -182,9 +182,23 @@ def test_apply_full_size_sampled_rows(make, cols, prec):
     # the 2^23 and 2^26 all-pairs operators and the 2^24 X-type one split the
     # high bits over three strided passes (the 2^24 chain takes hop tables);
     # the 2^21, 2^22 sparse, 2^23 and 2^26 operators have a YY part; 2^28
-    # (the largest size, one column) runs hop tables
-    inst = make()
-    h = H(inst)
+    # (the largest size, one column) runs hop tables; the hop-table operators
+    # (2^22 sparse, 2^24 and 2^28 chains) on bit-set tiles
+    _sampled_rows_check(make(), cols, prec, "auto")
+
+
+@pytest.mark.parametrize("make,cols", [(lambda: tfim_request(3, n_range=(24, 24)), 32),
+                                       (lambda: random_sparse_xxz(3001, n_range=(22, 22)), 32)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_apply_row_tiles_full_size_sampled_rows(make, cols, prec):
+    # the same hop-table operators on 256-row tiles
+    _sampled_rows_check(make(), cols, prec, "hops_rows")
+
+
+def _sampled_rows_check(inst, cols, prec, apply):
+    h = rdm.Hamiltonian.from_instance(inst, apply=apply)
+    if apply == "hops_rows":
+        assert h.info()["bitset_tiles"] == 0 and h.info()["transform"] == 0
     op = spin.sparse_hamiltonian(inst.n, inst.couplings, inst.hx, inst.hz)
     dt = torch.float64 if prec == "fp64" else torch.float32
     g = torch.Generator(device="cuda").manual_seed(5)
