@@ -18,7 +18,7 @@
   } while (0)
 
 static int hamiltonians(void) {
-  /* every term type, duplicates summed, both apply kinds, several sizes */
+  /* every term type, duplicates summed, every apply kind, several sizes */
   for (int n = 4; n <= 20; n += 4) {
     int n_s = n < 8 ? 1 : 2, n_b = n - n_s, nc = 0;
     rdm_coupling cps[256];
@@ -35,11 +35,14 @@ static int hamiltonians(void) {
       hx[s] = 0.1 * s;
       hz[s] = -0.05 * s;
     }
-    for (int kind = RDM_APPLY_AUTO; kind <= RDM_APPLY_TRANSFORM; ++kind) {
+    for (int kind = RDM_APPLY_AUTO; kind <= RDM_APPLY_HOPS_ROWS; ++kind) {
       rdm_hamiltonian* h = NULL;
       CHECK(rdm_hamiltonian_create_ex(n_s, n_b, cps, nc, hx, hz, kind, &h) == RDM_OK);
       int64_t info[21];
       CHECK(rdm_hamiltonian_info(h, info) == RDM_OK && info[0] == n);
+      /* bit-set tiles only from 12 sites on, never with the transform or on request of row tiles */
+      CHECK(info[17] == 0 || (n >= 12 && info[13] == 0 && kind != RDM_APPLY_HOPS_ROWS));
+      CHECK(info[19] >= 0 && (n >= 12 || info[19] == 0));
       int ds = 1 << n_s;
       double* m = malloc(sizeof(double) * ds * ds);
       CHECK(rdm_system_hamiltonian(h, m) == RDM_OK);
