@@ -51,6 +51,7 @@ uint32_t choose_tile_bits(const std::vector<uint32_t>& flips, int nbits) {
         best_n = n;
       }
     }
+    if (best < 0) break;  // fewer than kWideBits bits: callers need nbits >= kWideBits
     B |= 1u << best;
   }
   return B;
