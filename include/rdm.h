@@ -198,7 +198,7 @@ rdm_status rdm_energy_deviation(const rdm_hamiltonian* h, int32_t n_beta, const 
 /* Table sizes of a built Hamiltonian: out[0]=N, [1]=n_s, [2]=n_b,
  * [3]=uniform-coefficient hops, [4]=parity-dependent hops, [5]=diagonal terms,
  * [6..8] the same three counts for H_b, [9] / [10] partner-tile groups the
- * apply kernel stages in LDS for H_t / H_b (hops grouped by their flip bits
+ * 256-row-tile apply stages in LDS for H_t / H_b (hops grouped by their flip bits
  * above a 256-row tile; the own tile plus every tile read by at least three
  * hops), [11] / [12] hops it gathers directly from memory instead, [13] /
  * [14] 1 when H_t / H_b is applied by the transform (rdm_hamiltonian_create_ex)
