@@ -292,6 +292,9 @@ SOLVE_CASES = {
     "sparse_16": lambda: random_sparse_xxz(3021, n_range=(16, 16), n_v=1, k=30),
     "tfim_15": lambda: tfim_request(21, n_range=(15, 15), n_v=2, k=30),
     "dense_2+13": lambda: random_dense_terms(2, 13, 97, density=0.3, n_v=2, k=30),
+    # exactly 12 sites (one bit-set tile holds the vector) with 2 x 3 = 6
+    # columns (a ragged last panel)
+    "sparse_1+11": lambda: random_sparse_xxz(3108, n_range=(12, 12), n_v=3, k=40),
 }
 
 # cases that exercise an apply kind other than the default
