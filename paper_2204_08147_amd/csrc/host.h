@@ -50,7 +50,7 @@ struct OpTables {
   std::vector<double> t_cs, t_cd;
   int nt[3] = {0, 0, 0};
   // the same two forms for bit-set tiles (kWideBits sites and more): tile bits
-  // wbits; wide when the per-column Lanczos steps use them
+  // wbits; wide when products with the operator use them
   bool wide = false;
   uint32_t wbits = 0;
   std::vector<uint32_t> w_flo, w_m;
