@@ -123,6 +123,42 @@ def test_bitset_tile_selection():
     assert xz["transform"] == 1 and xz["bitset_tiles"] == 0 and xz["bath_bitset_tiles"] == 0
 
 
+def _tile_bit_rule(flips, nbits, tile_bits=12, low_bits=4):
+    # the documented choice: the low bits, then greedily the bit leaving the
+    # fewest distinct partner offsets f & ~B (lowest bit on ties); returns the
+    # partner tiles one tile reads (offsets used by two or more hops are one
+    # staged tile each, the others one gathered hop each)
+    B = (1 << low_bits) - 1
+    while bin(B).count("1") < tile_bits:
+        best = None
+        for b in range(low_bits, nbits):
+            if B >> b & 1:
+                continue
+            n = len({f & ~(B | 1 << b) for f in flips} - {0})
+            if best is None or n < best[0]:
+                best = (n, b)
+        B |= 1 << best[1]
+    uses = {}
+    for f in flips:
+        if f & ~B:
+            uses[f & ~B] = uses.get(f & ~B, 0) + 1
+    return sum(1 if u >= 2 else u for u in uses.values())
+
+
+@pytest.mark.parametrize("make", [lambda: random_sparse_xxz(3001, n_range=(22, 22)),
+                                  lambda: random_sparse_xxz(3021, n_range=(16, 16)),
+                                  lambda: nn_xxz_chain(2, 13, 96),
+                                  lambda: random_dense_terms(2, 13, 97, density=0.3),
+                                  lambda: tfim_request(17, n_range=(23, 23))])
+def test_bitset_partner_count_follows_the_tile_bit_rule(make):
+    inst = make()
+    n = inst.n
+    flips = [(1 << (n - 1 - i)) | (1 << (n - 1 - j)) for (i, j, jx, jy, jz) in inst.couplings if jx or jy]
+    flips += [1 << (n - 1 - s) for s in range(n) if inst.hx[s] != 0.0]
+    i = rdm.Hamiltonian.from_instance(inst, apply="hops").info()
+    assert i["bitset_partners"] == _tile_bit_rule(flips, n)
+
+
 @pytest.mark.parametrize("bad", [
     dict(n_s=0, n_b=4, couplings=[]),
     dict(n_s=5, n_b=4, couplings=[]),
